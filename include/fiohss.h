@@ -1,0 +1,239 @@
+/*
+ * fiohss — approximate inversion of discrete Fourier integral operators on AMD
+ * Instinct MI355X (gfx950): butterfly-factorization (BF) apply, randomized HSS
+ * construction of G~ ~ K~^* K~, ULV factorization and solve, and the online
+ * solve f^ = F K~^* u (Li & Liu, "Approximate Inversion of Discrete Fourier
+ * Integral Operators via Hierarchically Semiseparable Matrices").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Complex data are complex128 stored as interleaved (re, im) doubles.
+ *  - Blocks of vectors are column-major: element (i, j) of an N x k block with
+ *    leading dimension ld >= N is at offset i + j * ld (in complex elements).
+ *  - Pointers documented as "device" must point to GPU memory allocated by
+ *    the caller; the caller owns them.  Pointers documented as "host" are
+ *    ordinary CPU memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Calls
+ *    are stream-ordered and asynchronous unless stated otherwise.  Argument
+ *    errors are returned synchronously, before anything is enqueued.
+ *  - Handles (fio_bf_t, hss_t, hss_ulv_t) are created by the library, are
+ *    immutable once built and are released by the matching *_destroy.  Applies
+ *    and solves on one handle may run concurrently on different streams when
+ *    each call gets its own workspace.
+ *  - Vector ordering of the discrete FIO (Section 1, eq. fio): spatial entry i
+ *    is x_i = i / N, frequency entry j is xi_j = j - N/2.
+ */
+#ifndef FIOHSS_H
+#define FIOHSS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FIO_OK = 0,
+    FIO_ERR_ARG = -1,            /* invalid argument (bad size, NULL pointer, workspace too small) */
+    FIO_ERR_OOM = -2,            /* a device allocation failed; no handle was created */
+    FIO_ERR_HIP = -3,            /* a HIP runtime call failed */
+    FIO_ERR_NOT_HPD = -4,        /* a Cholesky pivot of the ULV factorization was not positive */
+    FIO_ERR_NOT_CONVERGED = -5,  /* refinement did not reach the requested residual */
+    FIO_ERR_UNSUPPORTED = -6,    /* valid request outside what this build implements */
+    FIO_ERR_CALLBACK = -7,       /* a caller callback returned non-zero */
+    FIO_WARN_RANK_CAP = 1        /* HSS ranks hit the cap; the result is valid but less accurate */
+} fio_status;
+
+typedef enum {
+    FIO_PREC_FP64 = 0,           /* complex128 factors and coefficients */
+    FIO_PREC_FP32 = 1,           /* complex64 factors and coefficients, complex128 input/output */
+    FIO_PREC_SPLIT_FP16 = 2      /* factors split into two fp16 halves, MFMA with fp32 accumulation */
+} fio_prec;
+
+typedef struct fio_bf_s *fio_bf_t;
+typedef struct hss_s *hss_t;
+typedef struct hss_ulv_s *hss_ulv_t;
+
+/* ---------------------------------------------------------------------------
+ * Butterfly factorization (Section 2.2, eq. bf):
+ *   K~ = U^[L'] B^[L'] ... B^[h+1] M^[h] C^[h+1] ... C^[L'] V^[L'],
+ * with N = 2^L (L even), h = L/2, L' = max(L - level_offset, h) (the outer
+ * level of Section 5.2's implementation note), q first-kind Chebyshev points
+ * per box on the closed box, and the 1D phase
+ *   Phi(x, xi) = x xi + (c0 + c1 sin(2 pi x)) |xi|,  amplitude 1.
+ * (c0, c1) = (0, 0) is the shifted DFT; (1/8, 1/16) is c(x) = (2 + sin 2 pi x)/16.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int dim;                 /* 1 (the only dimension this build implements) */
+    long n;                  /* N = 2^L, L even, N >= 64 */
+    double c0, c1;           /* phase parameters, see above */
+    int q;                   /* Chebyshev points per box (rank r = q), 2 <= q <= 16 */
+    int level_offset;        /* L' = max(L - level_offset, L/2); 3 gives leaf boxes of 8 points */
+    unsigned prec_mask;      /* bit p set: keep a copy of the factors in fio_prec p resident */
+} fio_bf_desc;
+
+/* Number of complex entries of the explicit factors of `desc`, in the layout
+ * read by fio_bf_import and written by fio_bf_export (0 on an invalid desc). */
+size_t fio_bf_factor_count(const fio_bf_desc *desc);
+
+/* Builds the factors on the GPU from the definitions of Section 2.2: every
+ * entry of U, B, M, C, V is evaluated by a kernel from Phi, the Chebyshev
+ * points and the Lagrange basis (phase differences are evaluated as
+ * differences, see the design notes).  Synchronizes `stream` before returning. */
+fio_status fio_bf_build(const fio_bf_desc *desc, void *stream, fio_bf_t *out);
+
+/* Creates a handle from explicit factors held in HOST memory, `count`
+ * complex128 entries laid out as
+ *   V[sigma][tau][j][s]                 2^L' x 2^(L-L') x q x b
+ *   C^[L'], C^[L'-1], ..., C^[h+1]       each (N/2) x 2q x 2q
+ *   M[p][i][j]                          N x q x q
+ *   B^[h+1], ..., B^[L']                each (N/2) x 2q x 2q
+ *   U[tau][sigma][s][i]                 2^L' x 2^(L-L') x b x q
+ * with b = N / 2^L' and the pair/group numbering
+ *   U-side level l:  pair (tau at spatial level l, sigma at frequency level L-l) -> tau 2^(L-l) + sigma
+ *   V-side level l:  pair (tau at spatial level L-l, sigma at frequency level l) -> tau 2^l + sigma
+ *   B^[l+1] group (alpha at spatial level l, sigma at frequency level L-l-1) -> alpha 2^(L-l-1) + sigma
+ *   C^[l+1] group (alpha at spatial level L-l-1, sigma at frequency level l) -> alpha 2^l + sigma
+ *   block row c_out q + i (output pair tau = 2 alpha + c_out), column c_in q + t (input pair
+ *   beta = 2 sigma + c_in), entries as defined in Section 2.2 (eq. bf_left_func_low_rank and
+ *   its frequency-side mirror).
+ * Used to apply factors produced elsewhere (e.g. to test the apply kernels on
+ * factors of a reference implementation).  Synchronous. */
+fio_status fio_bf_import(const fio_bf_desc *desc, const void *host_factors, size_t count,
+                         void *stream, fio_bf_t *out);
+
+/* Copies the FP64 factors of `bf` to HOST memory in the import layout.  Synchronous. */
+fio_status fio_bf_export(fio_bf_t bf, void *host_out, size_t count, void *stream);
+
+/* Bytes of device workspace fio_bf_apply / fio_bf_apply_adj need for nrhs columns. */
+fio_status fio_bf_workspace_size(fio_bf_t bf, int nrhs, fio_prec prec, size_t *bytes);
+
+/* Y = K~ X (N x nrhs blocks, device).  `prec` selects the factor copy; the
+ * input and output are complex128 in every precision.  `ws` is device memory
+ * of at least fio_bf_workspace_size bytes, or NULL to use a workspace owned
+ * by the handle (then calls on the handle must not overlap).  X and Y must
+ * not overlap. */
+fio_status fio_bf_apply(fio_bf_t bf, const void *X, long ldx, void *Y, long ldy, int nrhs,
+                        fio_prec prec, void *ws, size_t ws_bytes, void *stream);
+
+/* Y = K~^* X: the factors of eq. bf in reverse order, conjugate-transposed
+ * (Section 2.2, last paragraph).  Arguments as fio_bf_apply. */
+fio_status fio_bf_apply_adj(fio_bf_t bf, const void *X, long ldx, void *Y, long ldy, int nrhs,
+                            fio_prec prec, void *ws, size_t ws_bytes, void *stream);
+
+void fio_bf_destroy(fio_bf_t bf);
+
+/* ---------------------------------------------------------------------------
+ * Randomized black-box HSS construction of a Hermitian matrix (Section 3).
+ * The tree is binary over rows 0..N-1, leaves of `leaf` rows (N = leaf 2^Lh);
+ * ranks are per node; the effective leaf size of a nonleaf node is the sum of
+ * its children's ranks, and level l uses s_l = m_max + rhat + p samples with
+ * m_max the largest effective leaf size of the level (rhat <= 0: rhat = m_max).
+ * A column of the QRCP of the sample block is kept while |R_jj| > tol * g,
+ * g = norm_est if > 0, else ||Y^[L]||_F / ||Omega^[L]||_F from the leaf level.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int leaf;           /* leaf size m_L (64) */
+    double tol;         /* relative truncation tolerance */
+    int p;              /* oversampling */
+    int rhat;           /* rank guess added to the sample count; <= 0: m_max */
+    double norm_est;    /* scale of the tolerance; <= 0: estimated from the leaf samples */
+    int rank_cap;       /* <= 0: no cap; else ranks are truncated at rank_cap (FIO_WARN_RANK_CAP) */
+} hss_opts;
+
+/* Y = H X for ncols columns (device, column-major).  Return 0 on success. */
+typedef int (*hss_matvec_fn)(void *ctx, const void *X, long ldx, void *Y, long ldy, int ncols,
+                             void *stream);
+/* Fills the rows x cols test matrix Omega^[level] (device, column-major, ld = rows)
+ * with i.i.d. standard complex Gaussians.  Return 0 on success. */
+typedef int (*hss_omega_fn)(void *ctx, int level, long rows, long cols, void *out, void *stream);
+
+/* Section 3.1-3.3 with a caller-supplied matvec and test-matrix source.  The
+ * level loop runs on the host (each level's sizes depend on the ranks found
+ * below it); all per-node algebra runs in batched kernels.  Synchronous. */
+fio_status hss_build_from_samples(long n, const hss_opts *opts, hss_matvec_fn matvec, void *matvec_ctx,
+                                  hss_omega_fn omega, void *omega_ctx, void *stream, hss_t *out);
+
+/* Algorithm alg:fio_inv step 2: hss_build_from_samples with the matvec
+ * X -> K~^* (K~ X) applied in FP64 by this library's BF kernels. */
+fio_status fio_hss_build(fio_bf_t bf, const hss_opts *opts, hss_omega_fn omega, void *omega_ctx,
+                         void *stream, hss_t *out);
+
+/* Tree shape of an HSS handle: *levels = Lh; ranks (host, may be NULL) receives
+ * the 2^(Lh+1) - 2 node ranks level by level from level 1 to Lh. */
+fio_status hss_shape(hss_t h, int *levels, int *leaf, long *n, int *ranks, size_t nranks);
+
+/* HSS generators to/from HOST memory, packed level by level:
+ *   for l = 1..Lh, node j: U_(l,j) column-major m x r;
+ *   for l = 0..Lh-1, node j: B_(l,j) = B_{a2,a1} column-major r_a2 x r_a1;
+ *   for leaves j: D_j column-major leaf x leaf.
+ * `ranks` lists the node ranks as hss_shape does.  hss_generator_count gives
+ * the number of complex entries.  Synchronous. */
+size_t hss_generator_count(long n, int leaf, const int *ranks);
+fio_status hss_export(hss_t h, void *host_out, size_t count, void *stream);
+fio_status hss_import(long n, int leaf, const int *ranks, const void *host_gen, size_t count,
+                      void *stream, hss_t *out);
+
+/* Y = H X with the telescoping form (eq. hss_telescoping_factorization). */
+fio_status hss_matvec(hss_t h, const void *X, long ldx, void *Y, long ldy, int nrhs, void *stream);
+
+void hss_destroy(hss_t h);
+
+/* ---------------------------------------------------------------------------
+ * ULV factorization (Section 2.4): per node, QL basis elimination, Cholesky
+ * of the eliminated block, Schur complement, merge; root Cholesky.  The
+ * factors are stored per node as the m x m matrix W = [L11^-1 Q1^*;
+ * Q2^* - Dhat21 L11^-1 Q1^*], so that the bottom-up solve step is
+ * [bhat1; yhat2] = W y and the top-down step is c = W^* [bhat1; chat2]
+ * (algebraically the same steps as Section 2.4).  Synchronous; returns
+ * FIO_ERR_NOT_HPD when a pivot is not positive.
+ * ------------------------------------------------------------------------- */
+fio_status hss_ulv_factor(hss_t h, void *stream, hss_ulv_t *out);
+
+/* Bytes of device workspace hss_ulv_solve needs for nrhs columns. */
+fio_status hss_ulv_workspace_size(hss_ulv_t f, int nrhs, size_t *bytes);
+
+/* C = G~^{-1} Y (N x nrhs, device).  In-place (C == Y, ldc == ldy) is allowed. */
+fio_status hss_ulv_solve(hss_ulv_t f, const void *Y, long ldy, void *C, long ldc, int nrhs,
+                         void *ws, size_t ws_bytes, void *stream);
+
+void hss_ulv_destroy(hss_ulv_t f);
+
+/* ---------------------------------------------------------------------------
+ * Online solve (Section 4.1, eq. fio_inv_approx): F ~ K^{-1} U.
+ *   mode DIRECT: F = G~^{-1} K~^* U (K~^* in `prec`, ULV in FP64).
+ *   mode IR:     F0 = G~^{-1} K~^*_prec U; then up to max_ir times
+ *                R = U - K~ F (FP64), F += G~^{-1} K~^*_prec R, stopping when the
+ *                largest column ratio ||R_j|| / ||U_j|| <= rel_res_tol
+ *                (rel_res_tol <= 0: exactly max_ir steps, no host sync).
+ * ------------------------------------------------------------------------- */
+typedef enum { FIO_SOLVE_DIRECT = 0, FIO_SOLVE_IR = 1 } fio_solve_mode;
+
+typedef struct {
+    int mode;             /* fio_solve_mode */
+    int prec;             /* fio_prec of the K~^* applies */
+    double rel_res_tol;   /* IR stopping rule, see above */
+    int max_ir;           /* IR step limit */
+} fio_solve_opts;
+
+typedef struct {
+    int ir_steps;         /* refinement steps taken */
+    double rel_res;       /* largest column relative residual after the last step (IR with
+                             rel_res_tol > 0 only; -1 otherwise) */
+} fio_solve_info;
+
+fio_status fio_solve_workspace_size(fio_bf_t bf, hss_ulv_t f, int nrhs, const fio_solve_opts *opts,
+                                    size_t *bytes);
+
+/* `info` is host memory (may be NULL).  With mode IR and rel_res_tol > 0 the
+ * call synchronizes `stream` once per step to read the residual norms. */
+fio_status fio_approx_solve(fio_bf_t bf, hss_ulv_t f, const void *U, long ldu, void *F, long ldf,
+                            int nrhs, const fio_solve_opts *opts, fio_solve_info *info,
+                            void *ws, size_t ws_bytes, void *stream);
+
+const char *fio_status_str(fio_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

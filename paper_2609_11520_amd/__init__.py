@@ -1,0 +1,317 @@
+"""fiohss: MI355X (gfx950) approximate inversion of discrete Fourier integral operators.
+
+Thin Python binding of the C ABI in include/fiohss.h.  Every numerical step runs
+in the HIP library (libfiohss.so); this module only marshals arguments.  Device
+data are torch complex128 CUDA tensors of shape (N, k) in column-major layout
+(``colmajor`` converts); streams are torch's current stream.  There is no CPU
+fallback: importing works without a GPU, but every call needs the built library
+and a GPU.
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import (FIO_PREC_FP64, FIO_PREC_FP32, FIO_PREC_SPLIT_FP16, FIO_SOLVE_DIRECT, FIO_SOLVE_IR,
+                   FioError)
+
+__all__ = ["BF", "HSS", "ULV", "approx_solve", "colmajor", "empty", "FIO_PREC_FP64", "FIO_PREC_FP32",
+           "FIO_PREC_SPLIT_FP16", "FIO_SOLVE_DIRECT", "FIO_SOLVE_IR", "FioError", "lib"]
+
+
+def lib():
+    return _lib.load()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def colmajor(x):
+    """(N,) or (N, k) complex128 CUDA tensor -> (tensor in column-major layout, ld)."""
+    torch = _torch()
+    if x.dtype != torch.complex128:
+        raise TypeError("complex128 tensors required")
+    if not x.is_cuda:
+        raise TypeError("device (CUDA) tensors required")
+    if x.dim() == 1:
+        x = x.reshape(-1, 1)
+    n, k = x.shape
+    if not (x.stride(0) == 1 and (k == 1 or x.stride(1) >= n)):
+        x = x.t().contiguous().t()
+    ld = x.stride(1) if k > 1 else n
+    return x, ld
+
+
+def empty(n, k, device="cuda"):
+    torch = _torch()
+    return torch.empty((k, n), dtype=torch.complex128, device=device).t()
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _workspace(nbytes):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device="cuda")
+
+
+class BF:
+    """Butterfly factorization K~ of the 1D FIO Phi = x xi + (c0 + c1 sin 2 pi x)|xi| (Section 2.2)."""
+
+    def __init__(self, n, q=9, c0=2.0 / 16, c1=1.0 / 16, level_offset=3, precs=(FIO_PREC_FP64,), factors=None):
+        L = lib()
+        mask = 0
+        for p in precs:
+            mask |= 1 << p
+        self.desc = _lib.BfDesc(1, n, c0, c1, q, level_offset, mask)
+        self.n, self.q = n, q
+        h = C.c_void_p()
+        if factors is None:
+            st = L.fio_bf_build(C.byref(self.desc), _stream(), C.byref(h))
+            _lib.check(st, "fio_bf_build")
+        else:
+            f = np.ascontiguousarray(factors, dtype=np.complex128)
+            st = L.fio_bf_import(C.byref(self.desc), f.ctypes.data_as(C.c_void_p), f.size, _stream(), C.byref(h))
+            _lib.check(st, "fio_bf_import")
+        self.h = h
+
+    def factor_count(self):
+        return lib().fio_bf_factor_count(C.byref(self.desc))
+
+    def export(self):
+        n = self.factor_count()
+        out = np.empty(n, dtype=np.complex128)
+        _lib.check(lib().fio_bf_export(self.h, out.ctypes.data_as(C.c_void_p), n, _stream()), "fio_bf_export")
+        return out
+
+    def workspace_size(self, nrhs, prec=FIO_PREC_FP64):
+        b = C.c_size_t()
+        _lib.check(lib().fio_bf_workspace_size(self.h, nrhs, prec, C.byref(b)), "fio_bf_workspace_size")
+        return b.value
+
+    def _apply(self, fn, X, prec, out, ws):
+        X, ldx = colmajor(X)
+        k = X.shape[1]
+        Y = empty(self.n, k) if out is None else out
+        Y, ldy = colmajor(Y)
+        if ws is None:
+            ws = _workspace(self.workspace_size(k, prec))
+        st = fn(self.h, _ptr(X), ldx, _ptr(Y), ldy, k, prec, _ptr(ws), ws.numel(), _stream())
+        _lib.check(st, fn.__name__)
+        return Y
+
+    def apply(self, X, prec=FIO_PREC_FP64, out=None, ws=None):
+        """K~ X."""
+        return self._apply(lib().fio_bf_apply, X, prec, out, ws)
+
+    def apply_adj(self, X, prec=FIO_PREC_FP64, out=None, ws=None):
+        """K~^* X."""
+        return self._apply(lib().fio_bf_apply_adj, X, prec, out, ws)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib._lib is not None:
+            _lib._lib.fio_bf_destroy(self.h)
+            self.h = None
+
+
+class _DeviceView:
+    """Exposes a raw device pointer to torch through __cuda_array_interface__."""
+
+    def __init__(self, ptr, rows, cols, ld):
+        self.__cuda_array_interface__ = {
+            "shape": (cols, rows), "typestr": "<c16", "data": (ptr, False), "version": 3,
+            "strides": (ld * 16, 16)}
+
+
+def _as_tensor(ptr, rows, cols, ld):
+    torch = _torch()
+    t = torch.as_tensor(_DeviceView(ptr, rows, cols, ld), device="cuda")
+    return t.t()           # (rows, cols) column-major view
+
+
+def omega_from(fn):
+    """Wraps fn(level, rows, cols) -> numpy (rows x cols) complex array as an omega callback."""
+    torch = _torch()
+
+    def cb(ctx, level, rows, cols, out, stream):
+        try:
+            a = np.asarray(fn(level, rows, cols), dtype=np.complex128)
+            dst = _as_tensor(out, rows, cols, rows)
+            dst.copy_(torch.from_numpy(np.ascontiguousarray(a)).to("cuda"))
+            return 0
+        except Exception as e:          # reported to the library as a callback failure
+            print("omega callback failed:", repr(e))
+            return 1
+    return _lib.OMEGA_FN(cb)
+
+
+def omega_torch(seed):
+    """Omega callback drawing standard complex Gaussians with torch's device generator."""
+    torch = _torch()
+    gen = torch.Generator(device="cuda")
+
+    def cb(ctx, level, rows, cols, out, stream):
+        try:
+            gen.manual_seed(int(seed) * 1000003 + level)
+            dst = _as_tensor(out, rows, cols, rows)
+            re = torch.randn((rows, cols), dtype=torch.float64, device="cuda", generator=gen)
+            im = torch.randn((rows, cols), dtype=torch.float64, device="cuda", generator=gen)
+            dst.copy_(torch.complex(re, im))
+            return 0
+        except Exception as e:
+            print("omega callback failed:", repr(e))
+            return 1
+    return _lib.OMEGA_FN(cb)
+
+
+class HSS:
+    """Hermitian HSS matrix (Section 2.3) built on the GPU (Section 3) or imported."""
+
+    def __init__(self, handle):
+        self.h = handle
+        lv, leaf, n = C.c_int(), C.c_int(), C.c_long()
+        _lib.check(lib().hss_shape(self.h, C.byref(lv), C.byref(leaf), C.byref(n), None, 0), "hss_shape")
+        self.levels, self.leaf, self.n = lv.value, leaf.value, n.value
+
+    @staticmethod
+    def _opts(tol, p, leaf, rhat, norm_est, rank_cap):
+        return _lib.HssOpts(leaf, tol, p, rhat, norm_est, rank_cap)
+
+    @classmethod
+    def from_bf(cls, bf, tol, p=10, leaf=64, omega=None, seed=1000, rhat=0, norm_est=0.0, rank_cap=0):
+        """Algorithm alg:fio_inv step 2 with K~^* K~ applied by the library's BF kernels."""
+        cb = omega if omega is not None else omega_torch(seed)
+        h = C.c_void_p()
+        o = cls._opts(tol, p, leaf, rhat, norm_est, rank_cap)
+        st = lib().fio_hss_build(bf.h, C.byref(o), cb, None, _stream(), C.byref(h))
+        _lib.check(st, "fio_hss_build", allow_warn=True)
+        obj = cls(h)
+        obj.status = st
+        obj._cb = cb
+        return obj
+
+    @classmethod
+    def from_samples(cls, n, matvec, tol, p=10, leaf=64, omega=None, seed=1000, rhat=0, norm_est=0.0, rank_cap=0):
+        """hss_build_from_samples with matvec(X: (n, k) device tensor) -> (n, k) device tensor."""
+        def mv(ctx, X, ldx, Y, ldy, ncols, stream):
+            try:
+                x = _as_tensor(X, n, ncols, ldx)
+                y = _as_tensor(Y, n, ncols, ldy)
+                y.copy_(matvec(x))
+                return 0
+            except Exception as e:
+                print("matvec callback failed:", repr(e))
+                return 1
+        mcb = _lib.MATVEC_FN(mv)
+        cb = omega if omega is not None else omega_torch(seed)
+        h = C.c_void_p()
+        o = cls._opts(tol, p, leaf, rhat, norm_est, rank_cap)
+        st = lib().hss_build_from_samples(n, C.byref(o), mcb, None, cb, None, _stream(), C.byref(h))
+        _lib.check(st, "hss_build_from_samples", allow_warn=True)
+        obj = cls(h)
+        obj.status = st
+        obj._cb = (mcb, cb)
+        return obj
+
+    @classmethod
+    def from_generators(cls, n, leaf, ranks, gen):
+        r = np.ascontiguousarray(ranks, dtype=np.int32)
+        g = np.ascontiguousarray(gen, dtype=np.complex128)
+        h = C.c_void_p()
+        st = lib().hss_import(n, leaf, r.ctypes.data_as(C.POINTER(C.c_int)), g.ctypes.data_as(C.c_void_p), g.size,
+                              _stream(), C.byref(h))
+        _lib.check(st, "hss_import")
+        return cls(h)
+
+    def ranks(self):
+        cnt = (2 << self.levels) - 2
+        r = np.zeros(cnt, dtype=np.int32)
+        _lib.check(lib().hss_shape(self.h, None, None, None, r.ctypes.data_as(C.POINTER(C.c_int)), cnt),
+                   "hss_shape")
+        out, k = {}, 0
+        for l in range(1, self.levels + 1):
+            out[l] = list(r[k:k + (1 << l)])
+            k += 1 << l
+        return out
+
+    def export(self):
+        r = np.concatenate([np.array(v, dtype=np.int32) for _, v in sorted(self.ranks().items())])
+        cnt = lib().hss_generator_count(self.n, self.leaf, r.ctypes.data_as(C.POINTER(C.c_int)))
+        g = np.empty(cnt, dtype=np.complex128)
+        _lib.check(lib().hss_export(self.h, g.ctypes.data_as(C.c_void_p), cnt, _stream()), "hss_export")
+        return r, g
+
+    def matvec(self, X):
+        X, ldx = colmajor(X)
+        Y = empty(self.n, X.shape[1])
+        _lib.check(lib().hss_matvec(self.h, _ptr(X), ldx, _ptr(Y), Y.stride(1) if X.shape[1] > 1 else self.n,
+                                    X.shape[1], _stream()), "hss_matvec")
+        return Y
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib._lib is not None:
+            _lib._lib.hss_destroy(self.h)
+            self.h = None
+
+
+class ULV:
+    """ULV factorization F ~ G~^{-1} of an HSS matrix (Section 2.4)."""
+
+    def __init__(self, hss):
+        h = C.c_void_p()
+        _lib.check(lib().hss_ulv_factor(hss.h, _stream(), C.byref(h)), "hss_ulv_factor")
+        self.h, self.n, self.hss = h, hss.n, hss
+
+    def workspace_size(self, nrhs):
+        b = C.c_size_t()
+        _lib.check(lib().hss_ulv_workspace_size(self.h, nrhs, C.byref(b)), "hss_ulv_workspace_size")
+        return b.value
+
+    def solve(self, Y, out=None, ws=None):
+        Y, ldy = colmajor(Y)
+        k = Y.shape[1]
+        Cm = empty(self.n, k) if out is None else out
+        Cm, ldc = colmajor(Cm)
+        if ws is None:
+            ws = _workspace(self.workspace_size(k))
+        _lib.check(lib().hss_ulv_solve(self.h, _ptr(Y), ldy, _ptr(Cm), ldc, k, _ptr(ws), ws.numel(), _stream()),
+                   "hss_ulv_solve")
+        return Cm
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib._lib is not None:
+            _lib._lib.hss_ulv_destroy(self.h)
+            self.h = None
+
+
+def solve_workspace_size(bf, ulv, nrhs, mode=FIO_SOLVE_DIRECT, prec=FIO_PREC_FP64, rel_res_tol=0.0, max_ir=0):
+    o = _lib.SolveOpts(mode, prec, rel_res_tol, max_ir)
+    b = C.c_size_t()
+    _lib.check(lib().fio_solve_workspace_size(bf.h, ulv.h, nrhs, C.byref(o), C.byref(b)), "fio_solve_workspace_size")
+    return b.value
+
+
+def approx_solve(bf, ulv, U, mode=FIO_SOLVE_DIRECT, prec=FIO_PREC_FP64, rel_res_tol=0.0, max_ir=0, out=None,
+                 ws=None, info=None, raise_on_nonconv=True):
+    """F ~ K^{-1} U = G~^{-1} K~^* U (Section 4.1), optionally refined (mode IR)."""
+    U, ldu = colmajor(U)
+    k = U.shape[1]
+    F = empty(bf.n, k) if out is None else out
+    F, ldf = colmajor(F)
+    o = _lib.SolveOpts(mode, prec, rel_res_tol, max_ir)
+    if ws is None:
+        ws = _workspace(solve_workspace_size(bf, ulv, k, mode, prec, rel_res_tol, max_ir))
+    inf = _lib.SolveInfo() if info is None else info
+    st = lib().fio_approx_solve(bf.h, ulv.h, _ptr(U), ldu, _ptr(F), ldf, k, C.byref(o), C.byref(inf), _ptr(ws),
+                                ws.numel(), _stream())
+    if st != _lib.FIO_OK and not (st == -5 and not raise_on_nonconv):
+        _lib.check(st, "fio_approx_solve")
+    return F, inf

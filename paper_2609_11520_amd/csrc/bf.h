@@ -1,0 +1,27 @@
+// Butterfly factorization handle (Section 2.2) shared by the BF, HSS and solve units.
+#pragma once
+#include "common.h"
+
+struct fio_bf_s {
+    fio_bf_desc desc;
+    long N = 0;
+    int L = 0, h = 0, Lp = 0, nl = 0, q = 0, b = 0, nsl = 0;
+    // element offsets (complex entries) of each factor inside the packed arrays
+    size_t offV = 0, offM = 0, offU = 0, total = 0;
+    std::vector<size_t> offC, offB;   // offC[lev] = C^[h+1+lev], offB[lev] = B^[h+1+lev]
+    fio::DevBuf f64;                   // complex128 factors, import/export layout
+    fio::DevBuf f32;                   // complex64 copy (FIO_PREC_FP32)
+    fio::DevBuf f16;                   // split-fp16 copy: hi and lo planes (FIO_PREC_SPLIT_FP16)
+    fio::DevBuf ws;                    // handle-owned workspace (ws == NULL in the applies)
+    std::mutex ws_mu;
+};
+
+namespace fio {
+// Computes the geometry of `d` into `bf` (no allocation).  Returns FIO_OK or FIO_ERR_ARG/UNSUPPORTED.
+fio_status bf_plan(const fio_bf_desc *d, fio_bf_s *bf);
+size_t bf_coef_elems(const fio_bf_s *bf, int nrhs);   // complex entries of one coefficient buffer
+// Internal apply used by the HSS construction and the solver (workspace given explicitly).
+void bf_apply_impl(fio_bf_s *bf, bool adjoint, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs,
+                   fio_prec prec, void *ws, hipStream_t s);
+size_t bf_ws_bytes(const fio_bf_s *bf, int nrhs, fio_prec prec);
+}  // namespace fio

@@ -1,0 +1,912 @@
+// Randomized black-box HSS construction (Section 3) on gfx950.
+//
+// The level loop runs on the host because every level's sizes depend on the
+// ranks found below it; everything else runs on the device:
+//   * basis lift / projection of the test and sample matrices: batched GEMMs;
+//   * the sampling matvec: the caller's callback (the FIO path passes K~^* K~);
+//   * the per-node algebra of Section 3.1: one workgroup per node — full
+//     Householder QR of Omega_tau^*, Y_tau Q, column-pivoted QR of Y_tau Gamma_tau
+//     (truncated at the tolerance), U_tau, Y_tau Omega_tau^+, the residual block;
+//   * the postprocessing of Section 3.3: one workgroup per child node.
+// Householder convention and pivot rule (shared reading with the oracle):
+//   beta = -(x0/|x0|) ||x||, v = (x - beta e0)/(x0 - beta), tau = 1 + |x0|/||x||;
+//   QRCP takes the remaining column of largest norm (recomputed every step),
+//   lowest index on ties.
+#include "hss.h"
+
+#include <cmath>
+
+namespace fio {
+
+constexpr int kMaxM = 1024;     // largest effective leaf size handled by the node kernel
+constexpr int kMaxNW = 2048;    // largest number of sample columns beyond m
+
+// ---------------------------------------------------------------------------
+// workgroup helpers (blockDim.x == 256, four waves)
+__device__ __forceinline__ double wg_sum(double v, double *sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+    return t;
+}
+
+// Householder vector of x[0..n) (stride 1) in place: x[0] <- beta, x[1..] <- v[1..].
+// Returns tau; every thread gets the same value.
+__device__ double wg_house(double2 *x, int n, double *sh, double *beta_abs) {
+    const double2 a0 = x[0];
+    double part = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) part += x[i].x * x[i].x + x[i].y * x[i].y;
+    const double sigma = sqrt(wg_sum(part, sh));
+    if (sigma == 0.0) {
+        if (beta_abs) *beta_abs = 0.0;
+        __syncthreads();
+        if (threadIdx.x == 0) x[0] = zc(0.0, 0.0);
+        __syncthreads();
+        return 0.0;
+    }
+    const double aa = sqrt(a0.x * a0.x + a0.y * a0.y);
+    double2 ph = aa > 0.0 ? zc(a0.x / aa, a0.y / aa) : zc(1.0, 0.0);
+    double2 beta = zc(-ph.x * sigma, -ph.y * sigma);
+    double2 den = csub(a0, beta);                         // = ph (|a0| + sigma)
+    double dn = den.x * den.x + den.y * den.y;
+    double2 inv = zc(den.x / dn, -den.y / dn);
+    for (int i = 1 + threadIdx.x; i < n; i += blockDim.x) x[i] = cmul(x[i], inv);
+    __syncthreads();
+    if (threadIdx.x == 0) x[0] = beta;
+    if (beta_abs) *beta_abs = sigma;
+    __syncthreads();
+    return 1.0 + aa / sigma;
+}
+
+// A[0..n, 0..nc) -= tau v (v^* A), v = [1; vt[0..n-1)] (vt = v[1..]); A column-major (lda).
+__device__ void wg_house_left(const double2 *vt, int n, double tau, double2 *A, int lda, int nc) {
+    if (tau == 0.0) return;
+    const int sub = threadIdx.x & 3;
+    for (int c0 = 0; c0 < nc; c0 += (int)(blockDim.x >> 2)) {
+        const int c = c0 + (threadIdx.x >> 2);
+        double2 w = zc(0.0, 0.0);
+        double2 *col = A + (size_t)(c < nc ? c : 0) * lda;
+        if (c < nc) {
+            for (int i = sub; i < n; i += 4) {
+                double2 vi = i == 0 ? zc(1.0, 0.0) : vt[i - 1];
+                cfmac(w, vi, col[i]);
+            }
+        }
+        w.x += __shfl_xor(w.x, 1);
+        w.y += __shfl_xor(w.y, 1);
+        w.x += __shfl_xor(w.x, 2);
+        w.y += __shfl_xor(w.y, 2);
+        if (c < nc) {
+            double2 tw = zc(tau * w.x, tau * w.y);
+            for (int i = sub; i < n; i += 4) {
+                double2 vi = i == 0 ? zc(1.0, 0.0) : vt[i - 1];
+                col[i] = csub(col[i], cmul(vi, tw));
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Z[0..mr, 0..n) <- Z (I - tau v v^*), v = [1; vt]; Z column-major (ldz).
+__device__ void wg_house_right(const double2 *vt, int n, double tau, double2 *Z, int ldz, int mr) {
+    if (tau == 0.0) return;
+    const int sub = threadIdx.x & 3;
+    for (int r0 = 0; r0 < mr; r0 += (int)(blockDim.x >> 2)) {
+        const int r = r0 + (threadIdx.x >> 2);
+        double2 w = zc(0.0, 0.0);
+        if (r < mr) {
+            for (int l = sub; l < n; l += 4) {
+                double2 vl = l == 0 ? zc(1.0, 0.0) : vt[l - 1];
+                cfma(w, Z[r + (size_t)l * ldz], vl);
+            }
+        }
+        w.x += __shfl_xor(w.x, 1);
+        w.y += __shfl_xor(w.y, 1);
+        w.x += __shfl_xor(w.x, 2);
+        w.y += __shfl_xor(w.y, 2);
+        if (r < mr) {
+            double2 tw = zc(tau * w.x, tau * w.y);
+            for (int l = sub; l < n; l += 4) {
+                double2 vl = l == 0 ? zc(1.0, 0.0) : vt[l - 1];
+                double2 &z = Z[r + (size_t)l * ldz];
+                // z -= tw conj(vl)
+                z.x -= tw.x * vl.x + tw.y * vl.y;
+                z.y -= tw.y * vl.x - tw.x * vl.y;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+struct NodeArgs {
+    const double2 *Om;     // test matrix, rows of the level x s, ld = ldR
+    const double2 *Y;      // sample matrix, same layout
+    long ldR;
+    const long *moff;      // first row of each node
+    const int *msz;        // effective leaf size of each node
+    int s;                 // samples
+    double tol_abs;
+    int cap;               // rank cap
+    double2 *scratch;
+    size_t stride;         // scratch entries per node
+    int *rank_out;
+    double2 *Uslot;        // U_tau slot (m x m) of every node
+    const size_t *uoff;
+    double2 *Dres;         // residual block slot (m x m) of every node
+    const size_t *doff;
+    int root;              // 1: only H0 = Y Omega^+ (made Hermitian) into Dres
+};
+
+// Section 3.1 for one node (blockIdx.x), or the root solve of Section 3.2.
+__global__ void __launch_bounds__(256) k_node_step(NodeArgs a) {
+    __shared__ double sh[8];
+    __shared__ double s_tau[kMaxM];
+    __shared__ double s_tauw[kMaxM];
+    __shared__ double s_nrm[kMaxNW];
+    __shared__ int s_piv;
+    __shared__ double s_max;
+    const int node = blockIdx.x;
+    const int m = a.msz[node], s = a.s;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    double2 *out = a.Dres + a.doff[node];
+    if (m == 0) {
+        if (tid == 0 && !a.root) a.rank_out[node] = 0;
+        return;
+    }
+    double2 *A = a.scratch + a.stride * node;       // s x m : Omega_tau^*, then reflectors / R
+    double2 *Z = A + (size_t)s * m;                  // m x s : Y_tau Q
+    double2 *U = Z + (size_t)m * s;                  // m x m
+    double2 *P = U + (size_t)m * m;                  // m x m
+    double2 *X = P + (size_t)m * m;                  // m x m
+    double2 *Dt = X + (size_t)m * m;                 // m x m
+    const double2 *Om = a.Om + a.moff[node];
+    const double2 *Yt = a.Y + a.moff[node];
+    for (int e = tid; e < s * m; e += nt) {
+        int i = e % s, j = e / s;                    // A(i, j) = conj(Om(j, i))
+        double2 v = Om[j + (size_t)i * a.ldR];
+        A[e] = zc(v.x, -v.y);
+    }
+    for (int e = tid; e < m * s; e += nt) {
+        int i = e % m, j = e / m;
+        Z[e] = Yt[i + (size_t)j * a.ldR];
+    }
+    __syncthreads();
+    // full Householder QR of Omega_tau^* (s x m)
+    for (int j = 0; j < m; ++j) {
+        double2 *col = A + j + (size_t)j * s;
+        double tau = wg_house(col, s - j, sh, nullptr);
+        if (tid == 0) s_tau[j] = tau;
+        wg_house_left(col + 1, s - j, tau, col + s, s, m - j - 1);
+    }
+    __syncthreads();
+    // Z = Y_tau Q, Q = H_0 ... H_{m-1}
+    for (int j = 0; j < m; ++j) {
+        wg_house_right(A + j + 1 + (size_t)j * s, s - j, s_tau[j], Z + (size_t)j * m, m, m);
+    }
+    int r = 0;
+    if (!a.root) {
+        // QRCP of W = Z[:, m:s]  (m x nw)
+        double2 *W = Z + (size_t)m * m;
+        const int nw = s - m;
+        int kmax = m < nw ? m : nw;
+        if (a.cap > 0 && a.cap < kmax) kmax = a.cap;
+        for (int j = 0; j < kmax; ++j) {
+            const int sub = tid & 3;
+            for (int c0 = j; c0 < nw; c0 += nt >> 2) {
+                int c = c0 + (tid >> 2);
+                double p = 0.0;
+                if (c < nw)
+                    for (int i = j + sub; i < m; i += 4) {
+                        double2 v = W[i + (size_t)c * m];
+                        p += v.x * v.x + v.y * v.y;
+                    }
+                p += __shfl_xor(p, 1);
+                p += __shfl_xor(p, 2);
+                if (c < nw && sub == 0) s_nrm[c] = sqrt(p);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                int best = j;
+                double bv = s_nrm[j];
+                for (int c = j + 1; c < nw; ++c)
+                    if (s_nrm[c] > bv) {
+                        bv = s_nrm[c];
+                        best = c;
+                    }
+                s_piv = best;
+                s_max = bv;
+            }
+            __syncthreads();
+            if (!(s_max > a.tol_abs)) break;
+            const int pc = s_piv;
+            if (pc != j) {
+                for (int i = tid; i < m; i += nt) {
+                    double2 t = W[i + (size_t)j * m];
+                    W[i + (size_t)j * m] = W[i + (size_t)pc * m];
+                    W[i + (size_t)pc * m] = t;
+                }
+                __syncthreads();
+            }
+            double2 *col = W + j + (size_t)j * m;
+            double tau = wg_house(col, m - j, sh, nullptr);
+            if (tid == 0) s_tauw[j] = tau;
+            wg_house_left(col + 1, m - j, tau, col + m, m, nw - j - 1);
+            r = j + 1;
+        }
+        __syncthreads();
+        // U = H_0 ... H_{r-1} [I_r; 0]
+        for (int e = tid; e < m * r; e += nt) {
+            int i = e % m, j = e / m;
+            U[e] = zc(i == j ? 1.0 : 0.0, 0.0);
+        }
+        __syncthreads();
+        for (int j = r - 1; j >= 0; --j)
+            wg_house_left(W + j + 1 + (size_t)j * m, m - j, s_tauw[j], U + j, m, r);
+        if (tid == 0) a.rank_out[node] = r;
+    }
+    // T = Z1 R^{-*} (R = upper m x m of A): solve T R^* = Z1 row by row, in place in Z[:, 0:m]
+    for (int i = tid; i < m; i += nt) {
+        for (int j = m - 1; j >= 0; --j) {
+            double2 acc = Z[i + (size_t)j * m];
+            for (int k = j + 1; k < m; ++k) {
+                double2 rjk = A[j + (size_t)k * s];
+                double2 t = Z[i + (size_t)k * m];
+                // acc -= t conj(rjk)
+                acc.x -= t.x * rjk.x + t.y * rjk.y;
+                acc.y -= t.y * rjk.x - t.x * rjk.y;
+            }
+            double2 rjj = A[j + (size_t)j * s];
+            double d = rjj.x * rjj.x + rjj.y * rjj.y;
+            // acc / conj(rjj) = acc rjj / |rjj|^2
+            Z[i + (size_t)j * m] = zc((acc.x * rjj.x - acc.y * rjj.y) / d, (acc.x * rjj.y + acc.y * rjj.x) / d);
+        }
+    }
+    __syncthreads();
+    const double2 *T = Z;
+    if (a.root) {
+        for (int e = tid; e < m * m; e += nt) {
+            int i = e % m, j = e / m;
+            double2 x = T[i + (size_t)j * m], y = T[j + (size_t)i * m];
+            out[e] = zc(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+        }
+        return;
+    }
+    // P = U^* T (r x m)
+    for (int e = tid; e < r * m; e += nt) {
+        int aa = e % r, c = e / r;
+        double2 acc = zc(0.0, 0.0);
+        for (int i = 0; i < m; ++i) cfmac(acc, U[i + (size_t)aa * m], T[i + (size_t)c * m]);
+        P[aa + (size_t)c * m] = acc;
+    }
+    __syncthreads();
+    // X = T - U P
+    for (int e = tid; e < m * m; e += nt) {
+        int i = e % m, c = e / m;
+        double2 acc = T[i + (size_t)c * m];
+        for (int aa = 0; aa < r; ++aa) {
+            double2 t = cmul(U[i + (size_t)aa * m], P[aa + (size_t)c * m]);
+            acc = csub(acc, t);
+        }
+        X[e] = acc;
+    }
+    __syncthreads();
+    // P = U^* X^*  (r x m): P(a, c) = sum_i conj(U(i, a)) conj(X(c, i))
+    for (int e = tid; e < r * m; e += nt) {
+        int aa = e % r, c = e / r;
+        double2 acc = zc(0.0, 0.0);
+        for (int i = 0; i < m; ++i) {
+            double2 u = U[i + (size_t)aa * m], x = X[c + (size_t)i * m];
+            // conj(u) conj(x) = conj(u x)
+            double2 t = cmul(u, x);
+            acc.x += t.x;
+            acc.y -= t.y;
+        }
+        P[aa + (size_t)c * m] = acc;
+    }
+    __syncthreads();
+    // Dt = X + U P
+    for (int e = tid; e < m * m; e += nt) {
+        int i = e % m, c = e / m;
+        double2 acc = X[e];
+        for (int aa = 0; aa < r; ++aa) cfma(acc, U[i + (size_t)aa * m], P[aa + (size_t)c * m]);
+        Dt[e] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < m * m; e += nt) {
+        int i = e % m, j = e / m;
+        double2 x = Dt[i + (size_t)j * m], y = Dt[j + (size_t)i * m];
+        out[e] = zc(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+    }
+    double2 *Uo = a.Uslot + a.uoff[node];
+    for (int e = tid; e < m * r; e += nt) Uo[e] = U[e];
+}
+
+// Section 3.3 for the two children of every node of level l (one workgroup per child c):
+//   A = the child's diagonal block of D^[l]_parent; B_{a2,a1} = A_21 (written by the first child);
+//   D_c = D_res_c + U_c A U_c^*.
+struct PostArgs {
+    const double2 *Dpar;   // parent diagonal blocks (m_par x m_par slots)
+    const size_t *dpoff;
+    const int *mpar;       // parent sizes
+    const int *rch;        // child ranks (level l+1)
+    const double2 *Dres;   // child residual slots
+    const size_t *droff;
+    const int *mch;        // child sizes
+    const double2 *Uslot;  // child U slots
+    const size_t *uoff;
+    double2 *Dout;         // child D slots
+    const size_t *dooff;
+    double2 *Bout;         // B of the parents
+    const size_t *boff;
+    double2 *tmp;          // scratch, m_ch x r_ch per child
+    size_t tstride;
+};
+
+__global__ void __launch_bounds__(256) k_post(PostArgs a) {
+    const int c = blockIdx.x, par = c >> 1, tid = threadIdx.x, nt = blockDim.x;
+    const int mp = a.mpar[par], mc = a.mch[c], r = a.rch[c];
+    const int r1 = a.rch[par * 2];
+    const double2 *Dp = a.Dpar + a.dpoff[par];
+    const int o = (c & 1) ? r1 : 0;                  // the child's block of the parent's D
+    if ((c & 1) == 0) {
+        const int r2 = a.rch[par * 2 + 1];
+        double2 *Bo = a.Bout + a.boff[par];
+        for (int e = tid; e < r2 * r1; e += nt) {
+            int i = e % r2, j = e / r2;
+            Bo[e] = Dp[(r1 + i) + (size_t)j * mp];
+        }
+    }
+    const double2 *Uc = a.Uslot + a.uoff[c];
+    double2 *T = a.tmp + a.tstride * c;
+    // T = U_c A   (mc x r)
+    for (int e = tid; e < mc * r; e += nt) {
+        int i = e % mc, j = e / mc;
+        double2 acc = zc(0.0, 0.0);
+        for (int k = 0; k < r; ++k) cfma(acc, Uc[i + (size_t)k * mc], Dp[(o + k) + (size_t)(o + j) * mp]);
+        T[e] = acc;
+    }
+    __syncthreads();
+    const double2 *Dr = a.Dres + a.droff[c];
+    double2 *Do = a.Dout + a.dooff[c];
+    for (int e = tid; e < mc * mc; e += nt) {
+        int i = e % mc, j = e / mc;
+        double2 acc = Dr[e];
+        for (int k = 0; k < r; ++k) cfmac(acc, Uc[j + (size_t)k * mc], T[i + (size_t)k * mc]);
+        Do[e] = acc;
+    }
+}
+
+__global__ void k_sumsq_partial(const double2 *x, size_t n, double *part) {
+    __shared__ double sh[8];
+    double p = 0.0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p += x[i].x * x[i].x + x[i].y * x[i].y;
+    double t = wg_sum(p, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// deterministic sum of squares of n complex entries
+static double sumsq(const double2 *x, size_t n, hipStream_t s) {
+    const int nb = 512;
+    DevBuf part(nb * sizeof(double));
+    k_sumsq_partial<<<nb, 256, 0, s>>>(x, n, part.as<double>());
+    FIO_HIP(hipGetLastError());
+    std::vector<double> hp(nb);
+    FIO_HIP(hipMemcpyAsync(hp.data(), part.p, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+    FIO_HIP(hipStreamSynchronize(s));
+    double t = 0.0;
+    for (double v : hp) t += v;
+    return t;
+}
+
+template <typename T> static DevBuf *upload(const std::vector<T> &v, hipStream_t s) {
+    DevBuf *b = new DevBuf(v.size() * sizeof(T) + 8);
+    FIO_HIP(hipMemcpyAsync(b->p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return b;
+}
+
+void hss_layout_level(hss_s *h, int l) {
+    const int nn = h->nodes(l);
+    h->m[l].assign(nn, 0);
+    h->uoff[l].assign(nn, 0);
+    size_t off = 0;
+    for (int j = 0; j < nn; ++j) {
+        h->m[l][j] = (l == h->Lh) ? h->leaf : h->rank[l + 1][2 * j] + h->rank[l + 1][2 * j + 1];
+        h->uoff[l][j] = off;
+        off += (size_t)h->m[l][j] * h->m[l][j];
+    }
+    if (h->Ubuf[l]) delete h->Ubuf[l];
+    h->Ubuf[l] = new DevBuf(off * sizeof(double2) + 16);
+}
+
+void hss_layout_B(hss_s *h) {
+    size_t off = 0;
+    h->boff.assign(h->Lh, {});
+    for (int l = 0; l < h->Lh; ++l) {
+        h->boff[l].assign(h->nodes(l), 0);
+        for (int j = 0; j < h->nodes(l); ++j) {
+            h->boff[l][j] = off;
+            off += (size_t)h->rank[l + 1][2 * j] * h->rank[l + 1][2 * j + 1];
+        }
+    }
+    h->Bbuf.alloc(off * sizeof(double2) + 16);
+    h->Dbuf.alloc((size_t)h->nodes(h->Lh) * h->leaf * h->leaf * sizeof(double2));
+}
+
+// X_out (rows sum m_lv) = diag(U_(lv,j)) X_in (rows sum r_lv), or the projection with U^*.
+static void lift_level(hss_s *h, int lv, const double2 *in, long ldin, double2 *out, long ldout, int ncols,
+                       bool project, hipStream_t s) {
+    ZgemmBatch zb;
+    long ro = 0, mo = 0;
+    for (int j = 0; j < h->nodes(lv); ++j) {
+        int m = h->m[lv][j], r = h->rank[lv][j];
+        if (!project)
+            zb.add(h->U(lv, j), m, in + ro, ldin, out + mo, ldout, m, ncols, r);
+        else
+            zb.add(h->U(lv, j), m, in + mo, ldin, out + ro, ldout, r, ncols, m);
+        ro += r;
+        mo += m;
+    }
+    zb.upload(s);
+    zb.run(project, zc(1.0), zc(0.0), s);
+    FIO_HIP(hipStreamSynchronize(s));   // the descriptor list is freed on return
+}
+
+static long level_rows_m(const hss_s *h, int lv) {
+    long t = 0;
+    for (int v : h->m[lv]) t += v;
+    return t;
+}
+static long level_rows_r(const hss_s *h, int lv) {
+    long t = 0;
+    for (int v : h->rank[lv]) t += v;
+    return t;
+}
+
+// Omega_big = U^[Lh] ... U^[l+1] Omega (N x ncols); Y = U^[l+1]* ... U^[Lh]* Y_big.
+static void lift_all(hss_s *h, int l, const double2 *Om, long R, double2 *t0, double2 *t1, double2 *out, int ncols,
+                     hipStream_t s) {
+    if (l == h->Lh) {
+        FIO_HIP(hipMemcpyAsync(out, Om, (size_t)R * ncols * sizeof(double2), hipMemcpyDeviceToDevice, s));
+        return;
+    }
+    const double2 *cur = Om;
+    long ldc = R;
+    for (int lv = l + 1; lv <= h->Lh; ++lv) {
+        long rows = level_rows_m(h, lv);
+        double2 *dst = (lv == h->Lh) ? out : ((lv - l) % 2 ? t0 : t1);
+        lift_level(h, lv, cur, ldc, dst, rows, ncols, false, s);
+        cur = dst;
+        ldc = rows;
+    }
+}
+
+static void project_all(hss_s *h, int l, const double2 *Yb, double2 *t0, double2 *t1, double2 *out, long R,
+                        int ncols, hipStream_t s) {
+    if (l == h->Lh) {
+        FIO_HIP(hipMemcpyAsync(out, Yb, (size_t)R * ncols * sizeof(double2), hipMemcpyDeviceToDevice, s));
+        return;
+    }
+    const double2 *cur = Yb;
+    long ldc = h->N;
+    for (int lv = h->Lh; lv >= l + 1; --lv) {
+        long rows = level_rows_r(h, lv);
+        double2 *dst = (lv == l + 1) ? out : ((h->Lh - lv) % 2 ? t1 : t0);
+        lift_level(h, lv, cur, ldc, dst, rows, ncols, true, s);
+        cur = dst;
+        ldc = rows;
+    }
+}
+
+struct Sampler {
+    hss_matvec_fn matvec;
+    void *mctx;
+    hss_omega_fn omega;
+    void *octx;
+};
+
+static fio_status build_impl(long n, const hss_opts *o, const Sampler &sm, hipStream_t s, hss_t *out) {
+    FIO_CHECK_ARG(o && out && sm.matvec && sm.omega);
+    FIO_CHECK_ARG(o->leaf >= 1 && o->p >= 0 && o->tol >= 0.0);
+    int Lh = 0;
+    while (((long)o->leaf << Lh) < n) ++Lh;
+    FIO_CHECK_ARG(((long)o->leaf << Lh) == n && Lh >= 1);
+    FIO_CHECK_ARG(o->leaf <= kMaxM);
+    hss_s *h = new hss_s();
+    h->N = n;
+    h->leaf = o->leaf;
+    h->Lh = Lh;
+    h->rank.assign(Lh + 1, {});
+    h->m.assign(Lh + 1, {});
+    h->uoff.assign(Lh + 1, {});
+    h->Ubuf.assign(Lh + 1, nullptr);
+    h->samples.assign(Lh + 1, 0);
+    std::vector<DevBuf *> Dres(Lh + 1, nullptr);
+    std::vector<std::vector<size_t>> doff(Lh + 1);
+    fio_status st = guarded([&] {
+        double g = o->norm_est;
+        DevBuf Om, Ob, Yb, Y, t0, t1, scratch;
+        for (int l = Lh; l >= 0; --l) {
+            const bool root = (l == 0);
+            if (!root) hss_layout_level(h, l);
+            const int nn = root ? 1 : h->nodes(l);
+            std::vector<int> ms(nn);
+            std::vector<long> mo(nn);
+            long R = 0;
+            int mmax = 0;
+            for (int j = 0; j < nn; ++j) {
+                ms[j] = root ? h->rank[1][0] + h->rank[1][1] : h->m[l][j];
+                mo[j] = R;
+                R += ms[j];
+                mmax = ms[j] > mmax ? ms[j] : mmax;
+            }
+            if (root) h->m[0] = {ms[0]};
+            doff[l].assign(nn, 0);
+            size_t dtot = 0;
+            for (int j = 0; j < nn; ++j) {
+                doff[l][j] = dtot;
+                dtot += (size_t)ms[j] * ms[j];
+            }
+            Dres[l] = new DevBuf(dtot * sizeof(double2) + 16);
+            if (mmax == 0) {
+                h->rank[l].assign(nn, 0);
+                continue;
+            }
+            if (mmax > kMaxM) throw Err{FIO_ERR_UNSUPPORTED};
+            const int rh = root ? 0 : (o->rhat > 0 ? o->rhat : mmax);
+            const int sl = mmax + rh + o->p;
+            if (!root && sl - mmax > kMaxNW) throw Err{FIO_ERR_UNSUPPORTED};
+            h->samples[l] = sl;
+            Om.ensure((size_t)R * sl * sizeof(double2));
+            if (sm.omega(sm.octx, l, R, sl, Om.p, s) != 0) throw Err{FIO_ERR_CALLBACK};
+            const size_t big = (size_t)n * sl * sizeof(double2);
+            Ob.ensure(big);
+            Yb.ensure(big);
+            t0.ensure(big);
+            t1.ensure(big);
+            Y.ensure((size_t)R * sl * sizeof(double2));
+            lift_all(h, l, Om.as<double2>(), R, t0.as<double2>(), t1.as<double2>(), Ob.as<double2>(), sl, s);
+            if (sm.matvec(sm.mctx, Ob.p, n, Yb.p, n, sl, s) != 0) throw Err{FIO_ERR_CALLBACK};
+            project_all(h, l, Yb.as<double2>(), t0.as<double2>(), t1.as<double2>(), Y.as<double2>(), R, sl, s);
+            if (l == Lh && !(g > 0.0)) {
+                double ny = sumsq(Y.as<double2>(), (size_t)R * sl, s);
+                double no = sumsq(Om.as<double2>(), (size_t)R * sl, s);
+                g = sqrt(ny) / sqrt(no);
+            }
+            // per-node algebra
+            size_t stride = (size_t)2 * sl * mmax + (size_t)5 * mmax * mmax;
+            scratch.ensure(stride * nn * sizeof(double2));
+            std::vector<size_t> uo(nn, 0);
+            if (!root) uo = h->uoff[l];
+            DevBuf *dmo = upload(mo, s), *dms = upload(ms, s), *duo = upload(uo, s), *ddo = upload(doff[l], s);
+            DevBuf rk(nn * sizeof(int));
+            NodeArgs na;
+            na.Om = Om.as<double2>();
+            na.Y = Y.as<double2>();
+            na.ldR = R;
+            na.moff = dmo->as<long>();
+            na.msz = dms->as<int>();
+            na.s = sl;
+            na.tol_abs = o->tol * g;
+            na.cap = o->rank_cap;
+            na.scratch = scratch.as<double2>();
+            na.stride = stride;
+            na.rank_out = rk.as<int>();
+            na.Uslot = root ? nullptr : h->Ubuf[l]->as<double2>();
+            na.uoff = duo->as<size_t>();
+            na.Dres = Dres[l]->as<double2>();
+            na.doff = ddo->as<size_t>();
+            na.root = root ? 1 : 0;
+            k_node_step<<<nn, 256, 0, s>>>(na);
+            FIO_HIP(hipGetLastError());
+            if (!root) {
+                h->rank[l].assign(nn, 0);
+                FIO_HIP(hipMemcpyAsync(h->rank[l].data(), rk.p, nn * sizeof(int), hipMemcpyDeviceToHost, s));
+            }
+            FIO_HIP(hipStreamSynchronize(s));
+            delete dmo;
+            delete dms;
+            delete duo;
+            delete ddo;
+            if (!root && o->rank_cap > 0)
+                for (int v : h->rank[l])
+                    if (v >= o->rank_cap) h->rank_capped = true;
+        }
+        h->gain = g;
+        // postprocessing (Section 3.3), top down
+        hss_layout_B(h);
+        DevBuf Dcur, Dnext, tmp;
+        // level-0 "D" is H0, stored in Dres[0]
+        const double2 *dpar = Dres[0]->as<double2>();
+        std::vector<size_t> dpoff = {0};
+        std::vector<int> mpar = {h->m[0][0]};
+        for (int l = 0; l < Lh; ++l) {
+            const int nc = h->nodes(l + 1);
+            std::vector<size_t> dooff(nc);
+            size_t tot = 0, tmax = 0;
+            for (int c = 0; c < nc; ++c) {
+                dooff[c] = tot;
+                tot += (size_t)h->m[l + 1][c] * h->m[l + 1][c];
+                size_t tt = (size_t)h->m[l + 1][c] * h->rank[l + 1][c];
+                tmax = tt > tmax ? tt : tmax;
+            }
+            double2 *dout;
+            if (l + 1 == Lh) {
+                dout = h->Dbuf.as<double2>();
+            } else {
+                Dnext.alloc(tot * sizeof(double2) + 16);
+                dout = Dnext.as<double2>();
+            }
+            tmp.ensure(tmax * nc * sizeof(double2) + 16);
+            std::vector<size_t> bo = h->boff[l];
+            DevBuf *d1 = upload(dpoff, s), *d2 = upload(mpar, s), *d3 = upload(h->rank[l + 1], s),
+                   *d4 = upload(doff[l + 1], s), *d5 = upload(h->m[l + 1], s), *d6 = upload(h->uoff[l + 1], s),
+                   *d7 = upload(dooff, s), *d8 = upload(bo, s);
+            PostArgs pa;
+            pa.Dpar = dpar;
+            pa.dpoff = d1->as<size_t>();
+            pa.mpar = d2->as<int>();
+            pa.rch = d3->as<int>();
+            pa.Dres = Dres[l + 1]->as<double2>();
+            pa.droff = d4->as<size_t>();
+            pa.mch = d5->as<int>();
+            pa.Uslot = h->Ubuf[l + 1]->as<double2>();
+            pa.uoff = d6->as<size_t>();
+            pa.Dout = dout;
+            pa.dooff = d7->as<size_t>();
+            pa.Bout = h->Bbuf.as<double2>();
+            pa.boff = d8->as<size_t>();
+            pa.tmp = tmp.as<double2>();
+            pa.tstride = tmax;
+            k_post<<<nc, 256, 0, s>>>(pa);
+            FIO_HIP(hipGetLastError());
+            FIO_HIP(hipStreamSynchronize(s));
+            for (DevBuf *d : {d1, d2, d3, d4, d5, d6, d7, d8}) delete d;
+            Dcur.swap(Dnext);
+            dpar = Dcur.as<double2>();
+            dpoff = dooff;
+            mpar = h->m[l + 1];
+        }
+        return h->rank_capped ? FIO_WARN_RANK_CAP : FIO_OK;
+    });
+    for (auto *d : Dres) delete d;
+    if (st < 0) {
+        delete h;
+        return st;
+    }
+    *out = h;
+    return st;
+}
+
+}  // namespace fio
+
+using namespace fio;
+
+extern "C" fio_status hss_build_from_samples(long n, const hss_opts *opts, hss_matvec_fn matvec, void *matvec_ctx,
+                                             hss_omega_fn omega, void *omega_ctx, void *stream, hss_t *out) {
+    Sampler sm{matvec, matvec_ctx, omega, omega_ctx};
+    return build_impl(n, opts, sm, as_stream(stream), out);
+}
+
+// ---------------------------------------------------------------------------
+#include "bf.h"
+
+namespace {
+struct BfGram {
+    fio_bf_s *bf;
+    DevBuf ws, tmp;
+};
+int bf_gram_matvec(void *ctx, const void *X, long ldx, void *Y, long ldy, int ncols, void *stream) {
+    BfGram *g = static_cast<BfGram *>(ctx);
+    fio_status st = guarded([&] {
+        hipStream_t s = as_stream(stream);
+        size_t need = bf_ws_bytes(g->bf, ncols, FIO_PREC_FP64);
+        g->ws.ensure(need);
+        g->tmp.ensure((size_t)g->bf->N * ncols * sizeof(double2));
+        bf_apply_impl(g->bf, false, (const double2 *)X, ldx, g->tmp.as<double2>(), g->bf->N, ncols, FIO_PREC_FP64,
+                      g->ws.p, s);
+        bf_apply_impl(g->bf, true, g->tmp.as<double2>(), g->bf->N, (double2 *)Y, ldy, ncols, FIO_PREC_FP64, g->ws.p,
+                      s);
+        return FIO_OK;
+    });
+    return st == FIO_OK ? 0 : 1;
+}
+}  // namespace
+
+extern "C" fio_status fio_hss_build(fio_bf_t bf, const hss_opts *opts, hss_omega_fn omega, void *omega_ctx,
+                                    void *stream, hss_t *out) {
+    FIO_CHECK_ARG(bf);
+    BfGram g;
+    g.bf = bf;
+    Sampler sm{bf_gram_matvec, &g, omega, omega_ctx};
+    return build_impl(bf->N, opts, sm, as_stream(stream), out);
+}
+
+extern "C" fio_status hss_shape(hss_t h, int *levels, int *leaf, long *n, int *ranks, size_t nranks) {
+    FIO_CHECK_ARG(h);
+    if (levels) *levels = h->Lh;
+    if (leaf) *leaf = h->leaf;
+    if (n) *n = h->N;
+    if (ranks) {
+        size_t need = ((size_t)2 << h->Lh) - 2;
+        FIO_CHECK_ARG(nranks >= need);
+        size_t k = 0;
+        for (int l = 1; l <= h->Lh; ++l)
+            for (int v : h->rank[l]) ranks[k++] = v;
+    }
+    return FIO_OK;
+}
+
+extern "C" size_t hss_generator_count(long n, int leaf, const int *ranks) {
+    if (!ranks || leaf <= 0) return 0;
+    int Lh = 0;
+    while (((long)leaf << Lh) < n) ++Lh;
+    std::vector<std::vector<int>> r(Lh + 1);
+    size_t k = 0;
+    for (int l = 1; l <= Lh; ++l)
+        for (int j = 0; j < (1 << l); ++j) r[l].push_back(ranks[k++]);
+    size_t tot = 0;
+    for (int l = 1; l <= Lh; ++l)
+        for (int j = 0; j < (1 << l); ++j) {
+            int m = (l == Lh) ? leaf : r[l + 1][2 * j] + r[l + 1][2 * j + 1];
+            tot += (size_t)m * r[l][j];
+        }
+    for (int l = 0; l < Lh; ++l)
+        for (int j = 0; j < (1 << l); ++j) tot += (size_t)r[l + 1][2 * j] * r[l + 1][2 * j + 1];
+    tot += (size_t)(1 << Lh) * leaf * leaf;
+    return tot;
+}
+
+extern "C" fio_status hss_export(hss_t h, void *host_out, size_t count, void *stream) {
+    FIO_CHECK_ARG(h && host_out);
+    std::vector<int> ranks;
+    for (int l = 1; l <= h->Lh; ++l)
+        for (int v : h->rank[l]) ranks.push_back(v);
+    FIO_CHECK_ARG(count == hss_generator_count(h->N, h->leaf, ranks.data()));
+    return guarded([&] {
+        hipStream_t s = as_stream(stream);
+        double2 *o = (double2 *)host_out;
+        for (int l = 1; l <= h->Lh; ++l)
+            for (int j = 0; j < h->nodes(l); ++j) {
+                size_t e = (size_t)h->m[l][j] * h->rank[l][j];
+                if (e) FIO_HIP(hipMemcpyAsync(o, h->U(l, j), e * sizeof(double2), hipMemcpyDeviceToHost, s));
+                o += e;
+            }
+        size_t nb = 0;
+        for (int l = 0; l < h->Lh; ++l)
+            for (int j = 0; j < h->nodes(l); ++j) nb += (size_t)h->rank[l + 1][2 * j] * h->rank[l + 1][2 * j + 1];
+        if (nb) FIO_HIP(hipMemcpyAsync(o, h->Bbuf.p, nb * sizeof(double2), hipMemcpyDeviceToHost, s));
+        o += nb;
+        size_t nd = (size_t)h->nodes(h->Lh) * h->leaf * h->leaf;
+        FIO_HIP(hipMemcpyAsync(o, h->Dbuf.p, nd * sizeof(double2), hipMemcpyDeviceToHost, s));
+        FIO_HIP(hipStreamSynchronize(s));
+        return FIO_OK;
+    });
+}
+
+extern "C" fio_status hss_import(long n, int leaf, const int *ranks, const void *host_gen, size_t count, void *stream,
+                                 hss_t *out) {
+    FIO_CHECK_ARG(ranks && host_gen && out && leaf >= 1 && leaf <= kMaxM);
+    int Lh = 0;
+    while (((long)leaf << Lh) < n) ++Lh;
+    FIO_CHECK_ARG(((long)leaf << Lh) == n && Lh >= 1);
+    FIO_CHECK_ARG(count == hss_generator_count(n, leaf, ranks));
+    hss_s *h = new hss_s();
+    h->N = n;
+    h->leaf = leaf;
+    h->Lh = Lh;
+    h->rank.assign(Lh + 1, {});
+    h->m.assign(Lh + 1, {});
+    h->uoff.assign(Lh + 1, {});
+    h->Ubuf.assign(Lh + 1, nullptr);
+    size_t k = 0;
+    for (int l = 1; l <= Lh; ++l)
+        for (int j = 0; j < (1 << l); ++j) h->rank[l].push_back(ranks[k++]);
+    fio_status st = guarded([&] {
+        hipStream_t s = as_stream(stream);
+        for (int l = Lh; l >= 1; --l) hss_layout_level(h, l);
+        h->m[0] = {h->rank[1][0] + h->rank[1][1]};
+        for (int l = 1; l <= Lh; ++l)
+            for (int j = 0; j < h->nodes(l); ++j)
+                if (h->m[l][j] > kMaxM || h->rank[l][j] > h->m[l][j] || h->rank[l][j] < 0) return FIO_ERR_ARG;
+        hss_layout_B(h);
+        const double2 *in = (const double2 *)host_gen;
+        for (int l = 1; l <= Lh; ++l)
+            for (int j = 0; j < h->nodes(l); ++j) {
+                size_t e = (size_t)h->m[l][j] * h->rank[l][j];
+                if (e) FIO_HIP(hipMemcpyAsync(h->U(l, j), in, e * sizeof(double2), hipMemcpyHostToDevice, s));
+                in += e;
+            }
+        size_t nb = 0;
+        for (int l = 0; l < Lh; ++l)
+            for (int j = 0; j < h->nodes(l); ++j) nb += (size_t)h->rank[l + 1][2 * j] * h->rank[l + 1][2 * j + 1];
+        if (nb) FIO_HIP(hipMemcpyAsync(h->Bbuf.p, in, nb * sizeof(double2), hipMemcpyHostToDevice, s));
+        in += nb;
+        size_t nd = (size_t)h->nodes(Lh) * leaf * leaf;
+        FIO_HIP(hipMemcpyAsync(h->Dbuf.p, in, nd * sizeof(double2), hipMemcpyHostToDevice, s));
+        FIO_HIP(hipStreamSynchronize(s));
+        return FIO_OK;
+    });
+    if (st != FIO_OK) {
+        delete h;
+        return st;
+    }
+    *out = h;
+    return FIO_OK;
+}
+
+// Y = H X by the telescoping form: upward xhat = U^* x, downward yhat from B and the
+// parent's yhat, leaves y = D x + U yhat.  All steps are batched GEMMs.
+extern "C" fio_status hss_matvec(hss_t h, const void *X, long ldx, void *Y, long ldy, int nrhs, void *stream) {
+    FIO_CHECK_ARG(h && X && Y && ldx >= h->N && ldy >= h->N && nrhs >= 0);
+    if (nrhs == 0) return FIO_OK;
+    return guarded([&] {
+        hipStream_t s = as_stream(stream);
+        const int Lh = h->Lh;
+        std::vector<long> rtot(Lh + 1, 0);
+        for (int l = 1; l <= Lh; ++l) rtot[l] = level_rows_r(h, l);
+        std::vector<DevBuf *> xh(Lh + 1, nullptr), yh(Lh + 1, nullptr);
+        for (int l = 1; l <= Lh; ++l) {
+            xh[l] = new DevBuf((size_t)(rtot[l] + 1) * nrhs * sizeof(double2));
+            yh[l] = new DevBuf((size_t)(rtot[l] + 1) * nrhs * sizeof(double2));
+        }
+        const double2 *x = (const double2 *)X;
+        double2 *y = (double2 *)Y;
+        // upward
+        lift_level(h, Lh, x, ldx, xh[Lh]->as<double2>(), rtot[Lh], nrhs, true, s);
+        for (int l = Lh - 1; l >= 1; --l)
+            lift_level(h, l, xh[l + 1]->as<double2>(), rtot[l + 1], xh[l]->as<double2>(), rtot[l], nrhs, true, s);
+        // downward: children of level l
+        for (int l = 0; l < Lh; ++l) {
+            double2 *yc = yh[l + 1]->as<double2>();
+            const double2 *xc = xh[l + 1]->as<double2>();
+            long ldc = rtot[l + 1];
+            if (l > 0) lift_level(h, l, yh[l]->as<double2>(), rtot[l], yc, ldc, nrhs, false, s);
+            ZgemmBatch b1, b2;
+            long ro = 0;
+            for (int j = 0; j < h->nodes(l); ++j) {
+                int r1 = h->rank[l + 1][2 * j], r2 = h->rank[l + 1][2 * j + 1];
+                // y_a2 += B x_a1 ; y_a1 += B^* x_a2
+                b1.add(h->B(l, j), r2, xc + ro, ldc, yc + ro + r1, ldc, r2, nrhs, r1);
+                b2.add(h->B(l, j), r2, xc + ro + r1, ldc, yc + ro, ldc, r1, nrhs, r2);
+                ro += r1 + r2;
+            }
+            double2 beta = l > 0 ? zc(1.0) : zc(0.0);
+            if (l == 0) {
+                FIO_HIP(hipMemsetAsync(yc, 0, (size_t)ldc * nrhs * sizeof(double2), s));
+                beta = zc(1.0);
+            }
+            b1.upload(s);
+            b1.run(false, zc(1.0), beta, s);
+            b2.upload(s);
+            b2.run(true, zc(1.0), beta, s);
+            FIO_HIP(hipStreamSynchronize(s));
+        }
+        // leaves: y = D x + U yhat
+        ZgemmBatch bd, bu;
+        long ro = 0;
+        for (int j = 0; j < h->nodes(Lh); ++j) {
+            int r = h->rank[Lh][j];
+            bd.add(h->D(j), h->leaf, x + (size_t)j * h->leaf, ldx, y + (size_t)j * h->leaf, ldy, h->leaf, nrhs, h->leaf);
+            bu.add(h->U(Lh, j), h->leaf, yh[Lh]->as<double2>() + ro, rtot[Lh], y + (size_t)j * h->leaf, ldy, h->leaf,
+                   nrhs, r);
+            ro += r;
+        }
+        bd.upload(s);
+        bd.run(false, zc(1.0), zc(0.0), s);
+        bu.upload(s);
+        bu.run(false, zc(1.0), zc(1.0), s);
+        FIO_HIP(hipStreamSynchronize(s));
+        for (int l = 1; l <= Lh; ++l) {
+            delete xh[l];
+            delete yh[l];
+        }
+        return FIO_OK;
+    });
+}
+
+extern "C" void hss_destroy(hss_t h) { delete h; }

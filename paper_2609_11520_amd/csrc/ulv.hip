@@ -1,0 +1,740 @@
+// ULV factorization of an HPD HSS matrix and its solve (Section 2.4) on gfx950.
+//
+// Factor (offline, one workgroup per node, level by level from the leaves):
+//   QL basis elimination U = Q [0; Uhat2] with Householder reflectors taken from
+//   the bottom of each column; Dchk = Q^* D Q; Cholesky Dchk11 = L11 L11^*;
+//   Dhat21 = Dchk21 L11^{-*}; Dhat22 = Dchk22 - Dhat21 Dhat21^*; then the merge
+//   of eq. ulv_merge for every parent and a Cholesky of the root block.
+// The two solve sweeps of Section 2.4 are stored per node as one m x m matrix
+//   W = [L11^{-1} Q1^*; Q2^* - Dhat21 L11^{-1} Q1^*]
+// so that the bottom-up step is [bhat1; yhat2] = W y_tau and the top-down step is
+// c_tau = W^* [bhat1; chat2]; the root keeps Linv = L_rho^{-1}.  The online solve
+// is therefore 2 Lh + 2 batched small GEMM launches (see k_ulv_level).
+#include "hss.h"
+
+#include <cmath>
+#include <cstring>
+
+struct hss_ulv_s {
+    long N = 0;
+    int leaf = 0, Lh = 0, m0 = 0;
+    std::vector<std::vector<int>> m, k, r;      // per level (1..Lh)
+    std::vector<std::vector<size_t>> woff;
+    std::vector<std::vector<long>> yoff, roff;  // rows of a node in its level vector / parent vector
+    std::vector<long> rows;                     // rows of the level-l vector (l = 0..Lh)
+    fio::DevBuf W;                              // all W slots
+    fio::DevBuf Linv;                           // m0 x m0
+    fio::DevBuf meta;                           // device copies of the per-level tables
+    std::vector<size_t> meta_woff, meta_m, meta_k, meta_yoff, meta_roff;   // byte offsets into meta
+    fio::DevBuf rootdesc;                       // ZgemmDesc[2] for the root (pointers into ws set per call)
+    fio::DevBuf ws;
+    std::mutex ws_mu;
+};
+
+namespace fio {
+
+__device__ __forceinline__ double wsum(double v, double *sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+    return t;
+}
+
+// In-place Cholesky (lower) of the leading n x n block of A (column-major, lda).
+// Returns false (on every thread) when a pivot is not positive.
+__device__ bool wg_potrf(double2 *A, int lda, int n, double *sh, int *s_flag) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (tid == 0) *s_flag = 0;
+    __syncthreads();
+    for (int c = 0; c < n; ++c) {
+        double d = A[c + (size_t)c * lda].x;
+        if (!(d > 0.0) || !isfinite(d)) {
+            if (tid == 0) *s_flag = 1;
+            __syncthreads();
+            return false;
+        }
+        d = sqrt(d);
+        __syncthreads();
+        for (int i = c + tid; i < n; i += nt) {
+            double2 v = A[i + (size_t)c * lda];
+            A[i + (size_t)c * lda] = i == c ? zc(d, 0.0) : zc(v.x / d, v.y / d);
+        }
+        __syncthreads();
+        // trailing update of the lower triangle: A(i, j) -= L(i, c) conj(L(j, c)), c < j <= i
+        const int rem = n - c - 1;
+        for (int e = tid; e < rem * rem; e += nt) {
+            int i = c + 1 + e % rem, j = c + 1 + e / rem;
+            if (j > i) continue;
+            double2 li = A[i + (size_t)c * lda], lj = A[j + (size_t)c * lda];
+            double2 &a = A[i + (size_t)j * lda];
+            a.x -= li.x * lj.x + li.y * lj.y;
+            a.y -= li.y * lj.x - li.x * lj.y;
+        }
+        __syncthreads();
+    }
+    // clear the strict upper triangle (not part of L)
+    for (int e = tid; e < n * n; e += nt) {
+        int i = e % n, j = e / n;
+        if (j > i) A[i + (size_t)j * lda] = zc(0.0, 0.0);
+    }
+    __syncthreads();
+    (void)sh;
+    return true;
+}
+
+struct FactArgs {
+    // inputs per node of the level
+    const double2 *D;       // node diagonal blocks
+    const size_t *doff;
+    const double2 *U;       // node bases
+    const size_t *uoff;
+    const int *msz, *rsz;
+    // outputs
+    double2 *W;             // m x m per node
+    const size_t *woff;
+    double2 *D22;           // r x r per node (slot m x m)
+    double2 *U2;            // r x r per node (slot m x m)
+    const size_t *soff;
+    double2 *scratch;       // 3 m^2 per node
+    const size_t *scoff;
+    int *fail;
+};
+
+// Basis elimination, partial Cholesky and the node's W (one workgroup per node).
+__global__ void __launch_bounds__(256) k_ulv_node(FactArgs a) {
+    __shared__ double sh[8];
+    __shared__ double s_tau[1024];
+    __shared__ int s_flag;
+    const int node = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const int m = a.msz[node], r = a.rsz[node], k = m - r;
+    if (m == 0) return;
+    double2 *Uw = a.scratch + a.scoff[node];        // m x r working copy, then reflectors
+    double2 *Q = Uw + (size_t)m * m;                 // m x m explicit Q
+    double2 *T = Q + (size_t)m * m;                  // m x m: Q^* D, then Dchk
+    const double2 *Uin = a.U + a.uoff[node];
+    const double2 *Din = a.D + a.doff[node];
+    for (int e = tid; e < m * r; e += nt) Uw[e] = Uin[e];
+    __syncthreads();
+    // QL: for column jj = r-1..0 eliminate rows 0..p-1 (p = k + jj) into row p
+    for (int jj = r - 1; jj >= 0; --jj) {
+        const int p = k + jj, n = p + 1;
+        double2 *x = Uw + (size_t)jj * m;            // rows 0..p
+        const double2 al = x[p];
+        double part = 0.0;
+        for (int i = tid; i < n; i += nt) part += x[i].x * x[i].x + x[i].y * x[i].y;
+        const double sigma = sqrt(wsum(part, sh));
+        double tau = 0.0;
+        if (sigma > 0.0) {
+            const double aa = sqrt(al.x * al.x + al.y * al.y);
+            double2 ph = aa > 0.0 ? zc(al.x / aa, al.y / aa) : zc(1.0, 0.0);
+            double2 beta = zc(-ph.x * sigma, -ph.y * sigma);
+            double2 den = csub(al, beta);
+            double dn = den.x * den.x + den.y * den.y;
+            double2 inv = zc(den.x / dn, -den.y / dn);
+            for (int i = tid; i < p; i += nt) x[i] = cmul(x[i], inv);
+            __syncthreads();
+            if (tid == 0) x[p] = beta;
+            tau = 1.0 + aa / sigma;
+        }
+        if (tid == 0) s_tau[jj] = tau;
+        __syncthreads();
+        // apply H = I - tau v v^*, v = [x[0..p); 1], to columns 0..jj-1 (rows 0..p)
+        if (tau != 0.0) {
+            for (int c = tid; c < jj; c += nt) {
+                double2 *col = Uw + (size_t)c * m;
+                double2 w = col[p];
+                for (int i = 0; i < p; ++i) cfmac(w, x[i], col[i]);
+                double2 tw = zc(tau * w.x, tau * w.y);
+                col[p] = csub(col[p], tw);
+                for (int i = 0; i < p; ++i) col[i] = csub(col[i], cmul(x[i], tw));
+            }
+        }
+        __syncthreads();
+    }
+    // Q = H_{r-1} ... H_0 I: apply H_0 first
+    for (int e = tid; e < m * m; e += nt) Q[e] = zc((e % m) == (e / m) ? 1.0 : 0.0, 0.0);
+    __syncthreads();
+    for (int jj = 0; jj < r; ++jj) {
+        const double tau = s_tau[jj];
+        if (tau == 0.0) continue;
+        const int p = k + jj;
+        const double2 *x = Uw + (size_t)jj * m;
+        for (int c = tid; c < m; c += nt) {
+            double2 *col = Q + (size_t)c * m;
+            double2 w = col[p];
+            for (int i = 0; i < p; ++i) cfmac(w, x[i], col[i]);
+            double2 tw = zc(tau * w.x, tau * w.y);
+            col[p] = csub(col[p], tw);
+            for (int i = 0; i < p; ++i) col[i] = csub(col[i], cmul(x[i], tw));
+        }
+        __syncthreads();
+    }
+    // Uhat2: rows k..m-1 of the transformed U (lower triangular r x r: entries j >= i of the
+    // reflector-free part); the transformed U is [0; L] with L(i, c) at row k + i, column c
+    double2 *U2 = a.U2 + a.soff[node];
+    for (int e = tid; e < r * r; e += nt) {
+        int i = e % r, c = e / r;
+        U2[e] = (c <= i) ? Uw[(k + i) + (size_t)c * m] : zc(0.0, 0.0);
+    }
+    // T = Q^* D
+    double2 *Wm = a.W + a.woff[node];
+    for (int e = tid; e < m * m; e += nt) {
+        int i = e % m, j = e / m;
+        double2 acc = zc(0.0, 0.0);
+        for (int l = 0; l < m; ++l) cfmac(acc, Q[l + (size_t)i * m], Din[l + (size_t)j * m]);
+        Wm[e] = acc;                                 // temporary use of the W slot
+    }
+    __syncthreads();
+    // Dchk = (Q^* D) Q
+    for (int e = tid; e < m * m; e += nt) {
+        int i = e % m, j = e / m;
+        double2 acc = zc(0.0, 0.0);
+        for (int l = 0; l < m; ++l) cfma(acc, Wm[i + (size_t)l * m], Q[l + (size_t)j * m]);
+        T[e] = acc;
+    }
+    __syncthreads();
+    // Cholesky of Dchk11 (k x k) in place
+    if (!wg_potrf(T, m, k, sh, &s_flag)) {
+        if (tid == 0) atomicAdd(a.fail, 1);
+        return;
+    }
+    // Dhat21 = Dchk21 L11^{-*} in place in T(k.., 0..k): X L^* = B, forward over columns
+    for (int i = tid; i < r; i += nt) {
+        double2 *row = T + k + i;
+        for (int j = 0; j < k; ++j) {
+            double2 acc = row[(size_t)j * m];
+            for (int l = 0; l < j; ++l) {
+                double2 x = row[(size_t)l * m], Ljl = T[j + (size_t)l * m];
+                // acc -= x conj(Ljl)
+                acc.x -= x.x * Ljl.x + x.y * Ljl.y;
+                acc.y -= x.y * Ljl.x - x.x * Ljl.y;
+            }
+            double d = T[j + (size_t)j * m].x;
+            row[(size_t)j * m] = zc(acc.x / d, acc.y / d);
+        }
+    }
+    __syncthreads();
+    // Dhat22 = Dchk22 - Dhat21 Dhat21^*
+    double2 *D22 = a.D22 + a.soff[node];
+    for (int e = tid; e < r * r; e += nt) {
+        int i = e % r, j = e / r;
+        double2 acc = T[(k + i) + (size_t)(k + j) * m];
+        for (int l = 0; l < k; ++l) {
+            double2 x = T[(k + i) + (size_t)l * m], y = T[(k + j) + (size_t)l * m];
+            acc.x -= x.x * y.x + x.y * y.y;
+            acc.y -= x.y * y.x - x.x * y.y;
+        }
+        D22[e] = acc;
+    }
+    __syncthreads();
+    // W1 = L11^{-1} Q1^* (k x m), forward substitution per column c of Q1^*
+    for (int c = tid; c < m; c += nt) {
+        for (int i = 0; i < k; ++i) {
+            double2 q = Q[c + (size_t)i * m];            // Q1^*(i, c) = conj(Q(c, i))
+            double2 acc = zc(q.x, -q.y);
+            for (int l = 0; l < i; ++l) {
+                double2 t = cmul(T[i + (size_t)l * m], Wm[l + (size_t)c * m]);
+                acc = csub(acc, t);
+            }
+            double d = T[i + (size_t)i * m].x;
+            Wm[i + (size_t)c * m] = zc(acc.x / d, acc.y / d);
+        }
+    }
+    __syncthreads();
+    // W2 = Q2^* - Dhat21 W1 (r x m)
+    for (int e = tid; e < r * m; e += nt) {
+        int i = e % r, c = e / r;
+        double2 q = Q[c + (size_t)(k + i) * m];
+        double2 acc = zc(q.x, -q.y);
+        for (int l = 0; l < k; ++l) {
+            double2 t = cmul(T[(k + i) + (size_t)l * m], Wm[l + (size_t)c * m]);
+            acc = csub(acc, t);
+        }
+        Wm[(k + i) + (size_t)c * m] = acc;
+    }
+}
+
+// Merge of eq. ulv_merge for every parent (one workgroup per parent):
+//   D+ = [[D22(a1), (U2(a2) B U2(a1)^*)^*], [U2(a2) B U2(a1)^*, D22(a2)]],
+//   U+ = diag(U2(a1), U2(a2)) U_parent  (skipped at the root).
+struct MergeArgs {
+    const double2 *D22, *U2;
+    const size_t *soff;      // child slots
+    const int *rch;          // child ranks
+    const double2 *B;        // B_{a2,a1} of each parent
+    const size_t *boff;
+    const double2 *Upar;     // parent bases (m x r_par slots), or null at the root
+    const size_t *upoff;
+    const int *rpar;
+    double2 *Dout;           // merged D (m x m per parent)
+    const size_t *dooff;
+    double2 *Uout;           // merged U (m x r_par per parent)
+    const size_t *uooff;
+    double2 *tmp;            // r2 x r1 per parent
+    const size_t *toff;
+};
+
+__global__ void __launch_bounds__(256) k_ulv_merge(MergeArgs a) {
+    const int par = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const int c1 = 2 * par, c2 = 2 * par + 1;
+    const int r1 = a.rch[c1], r2 = a.rch[c2], m = r1 + r2;
+    if (m == 0) return;
+    const double2 *Da = a.D22 + a.soff[c1], *Db = a.D22 + a.soff[c2];
+    const double2 *Ua = a.U2 + a.soff[c1], *Ub = a.U2 + a.soff[c2];
+    const double2 *B = a.B + a.boff[par];
+    double2 *T = a.tmp + a.toff[par];
+    // T = U2(a2) B  (r2 x r1); B is r2 x r1
+    for (int e = tid; e < r2 * r1; e += nt) {
+        int i = e % r2, j = e / r2;
+        double2 acc = zc(0.0, 0.0);
+        for (int l = 0; l < r2; ++l) cfma(acc, Ub[i + (size_t)l * r2], B[l + (size_t)j * r2]);
+        T[e] = acc;
+    }
+    __syncthreads();
+    double2 *D = a.Dout + a.dooff[par];
+    for (int e = tid; e < m * m; e += nt) {
+        int i = e % m, j = e / m;
+        double2 v;
+        if (i < r1 && j < r1) {
+            v = Da[i + (size_t)j * r1];
+        } else if (i >= r1 && j >= r1) {
+            v = Db[(i - r1) + (size_t)(j - r1) * r2];
+        } else if (i >= r1) {        // lower-left: (T U2(a1)^*)(i - r1, j)
+            double2 acc = zc(0.0, 0.0);
+            for (int l = 0; l < r1; ++l) cfmac(acc, Ua[j + (size_t)l * r1], T[(i - r1) + (size_t)l * r2]);
+            v = acc;
+        } else {                     // upper-right: conj of lower-left (j - r1, i)
+            double2 acc = zc(0.0, 0.0);
+            for (int l = 0; l < r1; ++l) cfmac(acc, Ua[i + (size_t)l * r1], T[(j - r1) + (size_t)l * r2]);
+            v = zc(acc.x, -acc.y);
+        }
+        D[e] = v;
+    }
+    if (a.Upar) {
+        const int rp = a.rpar[par];
+        const double2 *Up = a.Upar + a.upoff[par];
+        double2 *Uo = a.Uout + a.uooff[par];
+        for (int e = tid; e < m * rp; e += nt) {
+            int i = e % m, j = e / m;
+            double2 acc = zc(0.0, 0.0);
+            if (i < r1) {
+                for (int l = 0; l <= i; ++l) cfma(acc, Ua[i + (size_t)l * r1], Up[l + (size_t)j * m]);
+            } else {
+                int ii = i - r1;
+                for (int l = 0; l <= ii; ++l) cfma(acc, Ub[ii + (size_t)l * r2], Up[(r1 + l) + (size_t)j * m]);
+            }
+            Uo[e] = acc;
+        }
+    }
+}
+
+// Root: Cholesky of D+ and the explicit inverse Linv of the lower factor.
+__global__ void __launch_bounds__(256) k_ulv_root(double2 *D, int m, double2 *Linv, int *fail) {
+    __shared__ double sh[8];
+    __shared__ int s_flag;
+    if (!wg_potrf(D, m, m, sh, &s_flag)) {
+        if (threadIdx.x == 0) atomicAdd(fail, 1);
+        return;
+    }
+    // Linv column c: solve L x = e_c by forward substitution
+    for (int c = threadIdx.x; c < m; c += blockDim.x) {
+        for (int i = 0; i < m; ++i) {
+            double2 acc = zc(i == c ? 1.0 : 0.0, 0.0);
+            for (int l = c; l < i; ++l) {
+                double2 t = cmul(D[i + (size_t)l * m], Linv[l + (size_t)c * m]);
+                acc = csub(acc, t);
+            }
+            double d = D[i + (size_t)i * m].x;
+            Linv[i + (size_t)c * m] = i < c ? zc(0.0, 0.0) : zc(acc.x / d, acc.y / d);
+        }
+    }
+}
+
+// One level of the ULV solve.  UP: z = W y_tau, rows < k to Bh, rows >= k to the parent's
+// vector (Ylo).  DOWN: c_tau = W^* [Bh rows; Ylo rows].  32 x 32 output tiles, K through LDS.
+struct LevelArgs {
+    const double2 *W;
+    const size_t *woff;
+    const int *m, *k;
+    const long *yoff, *roff;
+};
+
+template <bool DOWN>
+__global__ void __launch_bounds__(256) k_ulv_level(LevelArgs a, const double2 *__restrict__ Yin, long ldin,
+                                                   double2 *__restrict__ Bh, long ldb, double2 *__restrict__ Ylo,
+                                                   long ldlo, double2 *__restrict__ Yout, long ldout, int nrhs,
+                                                   int tilesN) {
+    const int node = blockIdx.y;
+    const int m = a.m[node], k = a.k[node];
+    const int tm = blockIdx.x / tilesN, tn = blockIdx.x % tilesN;
+    const int m0 = tm * 32, n0 = tn * 32;
+    if (m0 >= m || n0 >= nrhs) return;
+    const double2 *W = a.W + a.woff[node];
+    const long yo = a.yoff[node], ro = a.roff[node];
+    __shared__ double2 As[16][33];
+    __shared__ double2 Bs[16][33];
+    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+    double2 acc[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = zc(0.0, 0.0);
+    for (int k0 = 0; k0 < m; k0 += 16) {
+        for (int e = tid; e < 512; e += 256) {
+            int mm, kk;
+            double2 v = zc(0.0, 0.0);
+            if (DOWN) {      // op(A) = W^*: element (row, kk) = conj(W(kk, row))
+                kk = e % 16;
+                mm = e / 16;
+                int gm = m0 + mm, gk = k0 + kk;
+                if (gm < m && gk < m) {
+                    double2 t = W[gk + (size_t)gm * m];
+                    v = zc(t.x, -t.y);
+                }
+            } else {
+                mm = e % 32;
+                kk = e / 32;
+                int gm = m0 + mm, gk = k0 + kk;
+                if (gm < m && gk < m) v = W[gm + (size_t)gk * m];
+            }
+            As[kk][mm] = v;
+        }
+        for (int e = tid; e < 512; e += 256) {
+            int kk = e % 16, nn = e / 16;
+            int gk = k0 + kk, gn = n0 + nn;
+            double2 v = zc(0.0, 0.0);
+            if (gk < m && gn < nrhs) {
+                if (DOWN)
+                    v = gk < k ? Bh[(yo + gk) + (size_t)gn * ldb] : Ylo[(ro + gk - k) + (size_t)gn * ldlo];
+                else
+                    v = Yin[(yo + gk) + (size_t)gn * ldin];
+            }
+            Bs[kk][nn] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            double2 a0 = As[kk][tx], a1 = As[kk][tx + 16];
+            double2 b0 = Bs[kk][ty], b1 = Bs[kk][ty + 16];
+            cfma(acc[0][0], a0, b0);
+            cfma(acc[0][1], a0, b1);
+            cfma(acc[1][0], a1, b0);
+            cfma(acc[1][1], a1, b1);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+        int gm = m0 + tx + 16 * x;
+        if (gm >= m) continue;
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+            int gn = n0 + ty + 16 * y;
+            if (gn >= nrhs) continue;
+            if (DOWN)
+                Yout[(yo + gm) + (size_t)gn * ldout] = acc[x][y];
+            else if (gm < k)
+                Bh[(yo + gm) + (size_t)gn * ldb] = acc[x][y];
+            else
+                Ylo[(ro + gm - k) + (size_t)gn * ldlo] = acc[x][y];
+        }
+    }
+}
+
+template <typename T> static size_t put(std::vector<char> &blob, const std::vector<T> &v) {
+    size_t off = (blob.size() + 255) & ~(size_t)255;
+    blob.resize(off + v.size() * sizeof(T) + 8);
+    if (!v.empty()) std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+}
+
+static fio_status factor_impl(hss_s *h, hipStream_t s, hss_ulv_t *out) {
+    hss_ulv_s *f = new hss_ulv_s();
+    const int Lh = h->Lh;
+    f->N = h->N;
+    f->leaf = h->leaf;
+    f->Lh = Lh;
+    f->m.assign(Lh + 1, {});
+    f->k.assign(Lh + 1, {});
+    f->r.assign(Lh + 1, {});
+    f->woff.assign(Lh + 1, {});
+    f->yoff.assign(Lh + 1, {});
+    f->roff.assign(Lh + 1, {});
+    f->rows.assign(Lh + 1, 0);
+    fio_status st = guarded([&] {
+        size_t wtot = 0;
+        for (int l = Lh; l >= 1; --l) {
+            const int nn = h->nodes(l);
+            long yo = 0, ro = 0;
+            for (int j = 0; j < nn; ++j) {
+                int m = h->m[l][j], r = h->rank[l][j];
+                f->m[l].push_back(m);
+                f->r[l].push_back(r);
+                f->k[l].push_back(m - r);
+                f->woff[l].push_back(wtot);
+                wtot += (size_t)m * m;
+                f->yoff[l].push_back(yo);
+                f->roff[l].push_back(ro);
+                yo += m;
+                ro += r;
+            }
+            f->rows[l] = yo;
+            f->rows[l - 1] = ro;
+        }
+        f->m0 = h->m[0][0];
+        f->W.alloc(wtot * sizeof(double2) + 16);
+        f->Linv.alloc((size_t)f->m0 * f->m0 * sizeof(double2) + 16);
+        DevBuf failb(sizeof(int));
+        FIO_HIP(hipMemsetAsync(failb.p, 0, sizeof(int), s));
+        // level-by-level factorization
+        DevBuf Dcur, Ucur, D22, U2, scr, tmp;
+        const double2 *Din = h->Dbuf.as<double2>();
+        std::vector<size_t> din_off(h->nodes(Lh)), uin_off = h->uoff[Lh];
+        for (int j = 0; j < h->nodes(Lh); ++j) din_off[j] = (size_t)j * h->leaf * h->leaf;
+        const double2 *Uin = h->Ubuf[Lh]->as<double2>();
+        for (int l = Lh; l >= 1; --l) {
+            const int nn = h->nodes(l);
+            std::vector<size_t> soff(nn), scoff(nn);
+            size_t stot = 0, sctot = 0;
+            for (int j = 0; j < nn; ++j) {
+                int m = f->m[l][j];
+                soff[j] = stot;
+                stot += (size_t)m * m;
+                scoff[j] = sctot;
+                sctot += (size_t)3 * m * m;
+                if (m > 1024) throw Err{FIO_ERR_UNSUPPORTED};
+            }
+            D22.alloc(stot * sizeof(double2) + 16);
+            U2.alloc(stot * sizeof(double2) + 16);
+            scr.alloc(sctot * sizeof(double2) + 16);
+            std::vector<char> blob;
+            size_t o_doff = put(blob, din_off), o_uoff = put(blob, uin_off), o_m = put(blob, f->m[l]),
+                   o_r = put(blob, f->r[l]), o_w = put(blob, f->woff[l]), o_s = put(blob, soff),
+                   o_sc = put(blob, scoff);
+            DevBuf meta(blob.size());
+            FIO_HIP(hipMemcpyAsync(meta.p, blob.data(), blob.size(), hipMemcpyHostToDevice, s));
+            char *mb = meta.as<char>();
+            FactArgs fa;
+            fa.D = Din;
+            fa.doff = (const size_t *)(mb + o_doff);
+            fa.U = Uin;
+            fa.uoff = (const size_t *)(mb + o_uoff);
+            fa.msz = (const int *)(mb + o_m);
+            fa.rsz = (const int *)(mb + o_r);
+            fa.W = f->W.as<double2>();
+            fa.woff = (const size_t *)(mb + o_w);
+            fa.D22 = D22.as<double2>();
+            fa.U2 = U2.as<double2>();
+            fa.soff = (const size_t *)(mb + o_s);
+            fa.scratch = scr.as<double2>();
+            fa.scoff = (const size_t *)(mb + o_sc);
+            fa.fail = failb.as<int>();
+            k_ulv_node<<<nn, 256, 0, s>>>(fa);
+            FIO_HIP(hipGetLastError());
+            // merge into level l-1
+            const int np = h->nodes(l - 1);
+            std::vector<size_t> dooff(np), uooff(np), toff(np), upoff(np, 0);
+            std::vector<int> rpar(np, 0);
+            size_t dt = 0, ut = 0, tt = 0;
+            for (int j = 0; j < np; ++j) {
+                int r1 = f->r[l][2 * j], r2 = f->r[l][2 * j + 1], m = r1 + r2;
+                dooff[j] = dt;
+                dt += (size_t)m * m;
+                toff[j] = tt;
+                tt += (size_t)r1 * r2;
+                if (l - 1 >= 1) {
+                    rpar[j] = h->rank[l - 1][j];
+                    upoff[j] = h->uoff[l - 1][j];
+                }
+                uooff[j] = ut;
+                ut += (size_t)m * rpar[j];
+            }
+            DevBuf Dn(dt * sizeof(double2) + 16), Un(ut * sizeof(double2) + 16);
+            tmp.alloc(tt * sizeof(double2) + 16);
+            std::vector<char> blob2;
+            std::vector<size_t> boff = h->boff[l - 1];
+            size_t q_s = put(blob2, soff), q_r = put(blob2, f->r[l]), q_b = put(blob2, boff), q_up = put(blob2, upoff),
+                   q_rp = put(blob2, rpar), q_do = put(blob2, dooff), q_uo = put(blob2, uooff), q_t = put(blob2, toff);
+            DevBuf meta2(blob2.size());
+            FIO_HIP(hipMemcpyAsync(meta2.p, blob2.data(), blob2.size(), hipMemcpyHostToDevice, s));
+            char *m2 = meta2.as<char>();
+            MergeArgs ma;
+            ma.D22 = D22.as<double2>();
+            ma.U2 = U2.as<double2>();
+            ma.soff = (const size_t *)(m2 + q_s);
+            ma.rch = (const int *)(m2 + q_r);
+            ma.B = h->Bbuf.as<double2>();
+            ma.boff = (const size_t *)(m2 + q_b);
+            ma.Upar = (l - 1 >= 1) ? h->Ubuf[l - 1]->as<double2>() : nullptr;
+            ma.upoff = (const size_t *)(m2 + q_up);
+            ma.rpar = (const int *)(m2 + q_rp);
+            ma.Dout = Dn.as<double2>();
+            ma.dooff = (const size_t *)(m2 + q_do);
+            ma.Uout = Un.as<double2>();
+            ma.uooff = (const size_t *)(m2 + q_uo);
+            ma.tmp = tmp.as<double2>();
+            ma.toff = (const size_t *)(m2 + q_t);
+            k_ulv_merge<<<np, 256, 0, s>>>(ma);
+            FIO_HIP(hipGetLastError());
+            FIO_HIP(hipStreamSynchronize(s));
+            int fail = 0;
+            FIO_HIP(hipMemcpy(&fail, failb.p, sizeof(int), hipMemcpyDeviceToHost));
+            if (fail) throw Err{FIO_ERR_NOT_HPD};
+            Dcur.swap(Dn);
+            Ucur.swap(Un);
+            Din = Dcur.as<double2>();
+            Uin = Ucur.as<double2>();
+            din_off = dooff;
+            uin_off = uooff;
+        }
+        if (f->m0 > 0) {
+            k_ulv_root<<<1, 256, 0, s>>>(Dcur.as<double2>(), f->m0, f->Linv.as<double2>(), failb.as<int>());
+            FIO_HIP(hipGetLastError());
+            FIO_HIP(hipStreamSynchronize(s));
+            int fail = 0;
+            FIO_HIP(hipMemcpy(&fail, failb.p, sizeof(int), hipMemcpyDeviceToHost));
+            if (fail) throw Err{FIO_ERR_NOT_HPD};
+        }
+        // device tables for the solve
+        std::vector<char> blob;
+        f->meta_woff.assign(Lh + 1, 0);
+        f->meta_m.assign(Lh + 1, 0);
+        f->meta_k.assign(Lh + 1, 0);
+        f->meta_yoff.assign(Lh + 1, 0);
+        f->meta_roff.assign(Lh + 1, 0);
+        for (int l = 1; l <= Lh; ++l) {
+            f->meta_woff[l] = put(blob, f->woff[l]);
+            f->meta_m[l] = put(blob, f->m[l]);
+            f->meta_k[l] = put(blob, f->k[l]);
+            f->meta_yoff[l] = put(blob, f->yoff[l]);
+            f->meta_roff[l] = put(blob, f->roff[l]);
+        }
+        f->meta.alloc(blob.size() + 16);
+        FIO_HIP(hipMemcpy(f->meta.p, blob.data(), blob.size(), hipMemcpyHostToDevice));
+        return FIO_OK;
+    });
+    if (st != FIO_OK) {
+        delete f;
+        return st;
+    }
+    *out = f;
+    return FIO_OK;
+}
+
+static size_t ulv_ws_bytes(const hss_ulv_s *f, int nrhs) {
+    // level vectors l = 0..Lh-1, Bh for l = 1..Lh, root temporary
+    size_t rows = 0;
+    for (int l = 0; l < f->Lh; ++l) rows += f->rows[l];
+    for (int l = 1; l <= f->Lh; ++l) rows += f->rows[l];
+    rows += f->m0;
+    return (rows + 8 * (size_t)(f->Lh + 2)) * (size_t)nrhs * sizeof(double2) + 4096;
+}
+
+void ulv_solve_impl(hss_ulv_s *f, const double2 *Y, long ldy, double2 *C, long ldc, int nrhs, void *ws,
+                    hipStream_t s) {
+    if (nrhs <= 0) return;
+    const int Lh = f->Lh;
+    double2 *base = reinterpret_cast<double2 *>(ws);
+    std::vector<double2 *> Yl(Lh + 1, nullptr), Bl(Lh + 1, nullptr);
+    size_t off = 0;
+    auto take = [&](long rows) {
+        double2 *p = base + off;
+        off += ((size_t)rows * nrhs + 7) & ~(size_t)7;
+        return p;
+    };
+    for (int l = 0; l < Lh; ++l) Yl[l] = take(f->rows[l]);
+    for (int l = 1; l <= Lh; ++l) Bl[l] = take(f->rows[l]);
+    double2 *rt = take(f->m0);
+    const char *mb = f->meta.as<char>();
+    auto args = [&](int l) {
+        LevelArgs a;
+        a.W = f->W.as<double2>();
+        a.woff = (const size_t *)(mb + f->meta_woff[l]);
+        a.m = (const int *)(mb + f->meta_m[l]);
+        a.k = (const int *)(mb + f->meta_k[l]);
+        a.yoff = (const long *)(mb + f->meta_yoff[l]);
+        a.roff = (const long *)(mb + f->meta_roff[l]);
+        return a;
+    };
+    const int tilesN = (nrhs + 31) / 32;
+    auto mmax = [&](int l) {
+        int v = 0;
+        for (int x : f->m[l]) v = x > v ? x : v;
+        return v;
+    };
+    // bottom-up
+    for (int l = Lh; l >= 1; --l) {
+        const int tilesM = (mmax(l) + 31) / 32;
+        if (tilesM == 0) continue;
+        const double2 *yin = (l == Lh) ? Y : Yl[l];
+        long ldin = (l == Lh) ? ldy : f->rows[l];
+        dim3 grid(tilesM * tilesN, f->m[l].size());
+        k_ulv_level<false><<<grid, 256, 0, s>>>(args(l), yin, ldin, Bl[l], f->rows[l], Yl[l - 1], f->rows[l - 1],
+                                                nullptr, 0, nrhs, tilesN);
+    }
+    // root: Y0 <- Linv^* Linv Y0
+    if (f->m0 > 0) {
+        ZgemmDesc d0{f->Linv.as<double2>(), Yl[0], rt, f->m0, nrhs, f->m0, f->m0, f->m0, f->m0};
+        ZgemmDesc d1{f->Linv.as<double2>(), rt, Yl[0], f->m0, nrhs, f->m0, f->m0, f->m0, f->m0};
+        zgemm_one(d0, false, zc(1.0), zc(0.0), s);
+        zgemm_one(d1, true, zc(1.0), zc(0.0), s);
+    }
+    // top-down
+    for (int l = 1; l <= Lh; ++l) {
+        const int tilesM = (mmax(l) + 31) / 32;
+        if (tilesM == 0) continue;
+        double2 *yout = (l == Lh) ? C : Yl[l];
+        long ldout = (l == Lh) ? ldc : f->rows[l];
+        dim3 grid(tilesM * tilesN, f->m[l].size());
+        k_ulv_level<true><<<grid, 256, 0, s>>>(args(l), nullptr, 0, Bl[l], f->rows[l], Yl[l - 1], f->rows[l - 1],
+                                               yout, ldout, nrhs, tilesN);
+    }
+    FIO_HIP(hipGetLastError());
+}
+
+size_t ulv_ws_bytes_pub(const hss_ulv_s *f, int nrhs) { return ulv_ws_bytes(f, nrhs); }
+
+}  // namespace fio
+
+using namespace fio;
+
+extern "C" fio_status hss_ulv_factor(hss_t h, void *stream, hss_ulv_t *out) {
+    FIO_CHECK_ARG(h && out);
+    return factor_impl(h, as_stream(stream), out);
+}
+
+extern "C" fio_status hss_ulv_workspace_size(hss_ulv_t f, int nrhs, size_t *bytes) {
+    FIO_CHECK_ARG(f && bytes && nrhs >= 0);
+    *bytes = ulv_ws_bytes(f, nrhs);
+    return FIO_OK;
+}
+
+extern "C" fio_status hss_ulv_solve(hss_ulv_t f, const void *Y, long ldy, void *C, long ldc, int nrhs, void *ws,
+                                    size_t ws_bytes, void *stream) {
+    FIO_CHECK_ARG(f && nrhs >= 0);
+    if (nrhs == 0) return FIO_OK;
+    FIO_CHECK_ARG(Y && C && ldy >= f->N && ldc >= f->N);
+    if (Y == C) FIO_CHECK_ARG(ldy == ldc);
+    size_t need = ulv_ws_bytes(f, nrhs);
+    return guarded([&] {
+        hipStream_t s = as_stream(stream);
+        if (ws) {
+            if (ws_bytes < need) return FIO_ERR_ARG;
+            ulv_solve_impl(f, (const double2 *)Y, ldy, (double2 *)C, ldc, nrhs, ws, s);
+        } else {
+            std::lock_guard<std::mutex> lk(f->ws_mu);
+            if (f->ws.bytes < need) {
+                FIO_HIP(hipStreamSynchronize(s));
+                f->ws.alloc(need);
+            }
+            ulv_solve_impl(f, (const double2 *)Y, ldy, (double2 *)C, ldc, nrhs, f->ws.p, s);
+        }
+        return FIO_OK;
+    });
+}
+
+extern "C" void hss_ulv_destroy(hss_ulv_t f) { delete f; }

@@ -1,0 +1,104 @@
+"""GPU parity of the butterfly factorization: factor generation and the batched applies."""
+import numpy as np
+import pytest
+
+import fio_inputs as fi
+from oracle import fio as ofio
+from gpu_common import fiohss, dev, host, rel, step, oracle_bf, gpu_bf, PHASES
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(float).eps
+
+
+def entry_tol(n):
+    # the oracle evaluates every phase naively: |Phi| <= (1 + 3/16) N / 2, so an entry carries
+    # up to ~2 pi eps |Phi| of rounding; the GPU evaluates phase differences, which are O(1)
+    return 8 * np.pi * EPS * 0.6 * n + 1e-13
+
+
+@pytest.mark.parametrize("n,phase", [(1024, "sin16"), (4096, "sin16"), (1024, "dft"), (64, "sin8")])
+def test_factor_generation_matches_oracle(n, phase):
+    F = fiohss()
+    step("factors n=%d %s" % (n, phase))
+    g = gpu_bf(F, n, 9, phase, imported=False).export()
+    o = oracle_bf(n, 9, phase).export_factors()
+    assert g.shape == o.shape
+    assert np.max(np.abs(g - o)) < entry_tol(n)
+
+
+@pytest.mark.parametrize("n,k", [(1024, 1), (1024, 3), (1024, 64), (4096, 70), (256, 128)])
+def test_apply_on_imported_factors_is_exact(n, k):
+    F = fiohss()
+    step("apply imported n=%d k=%d" % (n, k))
+    B = gpu_bf(F, n, 9, "sin16", imported=True)
+    ob = oracle_bf(n, 9, "sin16")
+    x = fi.complex_gaussian(11, fi.PURPOSE_PROBE, n, k)
+    assert rel(host(B.apply(dev(x))), ob.apply(x)) < 1e-12
+    assert rel(host(B.apply_adj(dev(x))), ob.apply_adj(x)) < 1e-12
+
+
+@pytest.mark.parametrize("n,phase", [(1024, "sin16"), (4096, "dft")])
+def test_apply_on_own_factors_vs_oracle(n, phase):
+    F = fiohss()
+    step("apply own n=%d" % n)
+    B = gpu_bf(F, n, 9, phase, imported=False)
+    ob = oracle_bf(n, 9, phase)
+    x = fi.complex_gaussian(12, fi.PURPOSE_PROBE, n, 5)
+    tol = 20 * entry_tol(n)
+    assert rel(host(B.apply(dev(x))), ob.apply(x)) < tol
+    assert rel(host(B.apply_adj(dev(x))), ob.apply_adj(x)) < tol
+
+
+def test_bf_vs_dense_K_at_q13_and_dft_closed_form():
+    F = fiohss()
+    n = 1024
+    step("dense K q=13")
+    c0, c1 = PHASES["sin16"]
+    B = F.BF(n, 13, c0, c1)
+    f = fi.rhs(0, n, 2)
+    K = ofio.dense_K(n, PHASES["sin16"])
+    assert rel(host(B.apply(dev(f))), K @ f) < 1e-7
+    D = F.BF(n, 13, 0.0, 0.0)
+    assert rel(host(D.apply(dev(f))), ofio.dft_apply(f)) < 1e-10
+    assert rel(host(D.apply_adj(dev(f))), ofio.dft_apply_adj(f)) < 1e-10
+
+
+@pytest.mark.parametrize("k", [1, 64])
+def test_adjoint_identity_on_gpu(k):
+    F = fiohss()
+    n = 4096
+    B = gpu_bf(F, n, 9, "sin16", imported=False)
+    x = fi.complex_gaussian(1, fi.PURPOSE_PROBE, n, k)
+    y = fi.complex_gaussian(2, fi.PURPOSE_PROBE, n, k)
+    a = np.vdot(y, host(B.apply(dev(x))))
+    b = np.vdot(host(B.apply_adj(dev(y))), x)
+    assert abs(a - b) / abs(a) < 1e-13
+
+
+def test_fp32_apply_error():
+    F = fiohss()
+    n = 4096
+    B = gpu_bf(F, n, 9, "sin16", imported=True, precs=(F.FIO_PREC_FP64, F.FIO_PREC_FP32))
+    ob = oracle_bf(n, 9, "sin16")
+    x = fi.complex_gaussian(13, fi.PURPOSE_PROBE, n, 64)
+    e = rel(host(B.apply(dev(x), prec=F.FIO_PREC_FP32)), ob.apply(x))
+    ea = rel(host(B.apply_adj(dev(x), prec=F.FIO_PREC_FP32)), ob.apply_adj(x))
+    assert 1e-9 < e < 1e-5 and 1e-9 < ea < 1e-5
+
+
+def test_edge_cases_and_errors():
+    F = fiohss()
+    import torch
+    B = gpu_bf(F, 64, 5, "sin16", imported=False)        # smallest tree: no transfer level
+    ob = __import__("oracle.bf", fromlist=["BF1D"]).BF1D(64, 5, PHASES["sin16"])
+    x = fi.complex_gaussian(3, fi.PURPOSE_PROBE, 64, 2)
+    assert rel(host(B.apply(dev(x))), ob.apply(x)) < 1e-12
+    # leading dimension larger than N
+    big = torch.zeros((3, 100), dtype=torch.complex128, device="cuda")
+    xv = big[:, :64].t()
+    xv.copy_(dev(x[:, :1]).expand(64, 3))
+    y = host(B.apply(xv))
+    assert rel(y[:, 2], ob.apply(x[:, 0])) < 1e-12
+    # FP32 factors were not requested
+    with pytest.raises(F.FioError):
+        B.apply(dev(x), prec=F.FIO_PREC_FP32)
