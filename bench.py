@@ -1,0 +1,248 @@
+#!/usr/bin/env python3
+"""Benchmark of the online solve f^ ~ K^{-1} u on one MI355X.
+
+Workload (the headline configuration): 1D FIO, N = 2^18, Phi = x xi + c(x)|xi|,
+c(x) = (2 + sin 2 pi x)/16, q = 9 Chebyshev points, HSS tolerance 1e-3 with
+p = 10 oversampling, 64 right-hand sides u = K~ f with f complex Gaussian (seed 1).
+One step solves all 64 right-hand sides to a relative residual of 5e-9 by
+iterative refinement (so that the relative error of f^ is below 1e-8):
+  fp64  : K~^* and K~ applied in FP64;
+  mixed : K~^* applied in FP32 (FP32 factors and coefficients), residual K~ f and
+          the ULV solve in FP64.
+`value` is the mixed path's RHS/s (64 / seconds per step); the FP64 path is
+reported beside it.  Offline work (BF, HSS and ULV construction) happens before
+the timed region; inputs are resident in HBM when it starts.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector
+FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector
+METRIC = "RHS solved/s at N=2^18, rel err 1e-8: FP64 vs mixed; p50/p99 latency"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_model(name, n, q, k):
+    """Algorithmic (bytes, flops) of one launch of a BF level kernel (see the design notes)."""
+    es = 16 if name.endswith("f64") else 8
+    if name.startswith("bf_transfer"):
+        groups = n // 2
+        fac = groups * (2 * q) ** 2 * es
+        coef = 2 * n * q * k * es
+        return fac + coef, 8.0 * groups * (2 * q) ** 2 * k
+    if name.startswith("bf_middle"):
+        return n * q * q * es + 2 * n * q * k * es, 8.0 * n * q * q * k
+    return None
+
+
+def cpu_baseline(n, q, nrhs_gpu, ir_steps):
+    """The oracle (as it stands) timed on the host: one right-hand side of the same workload."""
+    import resource
+    from oracle import bf as obf, fio as ofio, hss as ohss, ulv as oulv
+    import fio_inputs as fi
+    log("cpu baseline: building the oracle factors (untimed)")
+    B = obf.BF1D(n, q, ofio.PHASE_SIN16)
+    f = fi.rhs(1, n, 1)
+    u = B.apply(f)
+    # ULV solve on generators of the same tree shape (rank 4 at every node, the ranks the
+    # oracle finds at tolerance 1e-3 for this operator); only the solve is timed
+    h = synthetic_hss(n, 64, 4)
+    fac = oulv.factor(h)
+    t0, c0 = time.perf_counter(), time.process_time()
+    x = oulv.solve(fac, B.apply_adj(u))
+    for _ in range(ir_steps):
+        r = u - B.apply(x)
+        x = x + oulv.solve(fac, B.apply_adj(r))
+    wall = time.perf_counter() - t0
+    cpu = time.process_time() - c0
+    cores = max(1, int(round(cpu / wall)))
+    return {"value": 1.0 / wall, "unit": "RHS/s", "cores": cores, "kind": "oracle",
+            "sample": "oracle FP64 refinement solve of 1 of the %d RHS at N=%d (%d refinement steps: "
+                      "%d K~* and %d K~ applies, %d ULV solves; ULV on rank-4 generators of the same tree), "
+                      "%.1f s wall" % (nrhs_gpu, n, ir_steps, ir_steps + 1, ir_steps, ir_steps + 1, wall)}
+
+
+def synthetic_hss(n, leaf, r):
+    """Random Hermitian positive definite HSS generators of a given uniform rank (timing only)."""
+    from oracle import hss as ohss
+    import fio_inputs as fi
+    h = ohss.HSS(n, leaf)
+    Lh = h.Lh
+    for l in range(1, Lh + 1):
+        h.rank[l] = [r] * (2 ** l)
+        h.U[l] = []
+        for j in range(2 ** l):
+            m = leaf if l == Lh else 2 * r
+            Q, _ = np.linalg.qr(fi.complex_gaussian(j, fi.PURPOSE_DATA, m, r, level=l))
+            h.U[l].append(Q)
+    for l in range(Lh):
+        h.B[l] = [0.01 * fi.complex_gaussian(j, fi.PURPOSE_DATA, r, r, level=100 + l) for j in range(2 ** l)]
+    h.D = [n * np.eye(leaf, dtype=np.complex128) for _ in range(2 ** Lh)]
+    return h
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1 << 18)
+    ap.add_argument("--nrhs", type=int, default=64)
+    ap.add_argument("--q", type=int, default=9)
+    ap.add_argument("--hss-tol", type=float, default=1e-3)
+    ap.add_argument("--rel-res", type=float, default=5e-9)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (see the design notes on "
+              "sharding); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import fio_inputs as fi
+    import paper_2609_11520_amd as F
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    F.lib()
+    n, k, q = a.n, a.nrhs, a.q
+    dev = torch.device("cuda")
+
+    def sync():
+        torch.cuda.synchronize()
+
+    log("device", torch.cuda.get_device_name(0))
+    t = time.perf_counter()
+    B = F.BF(n, q, 2.0 / 16, 1.0 / 16, precs=(F.FIO_PREC_FP64, F.FIO_PREC_FP32))
+    sync()
+    t_bf = time.perf_counter() - t
+    t = time.perf_counter()
+    H = F.HSS.from_bf(B, tol=a.hss_tol, p=10, seed=1003)
+    sync()
+    t_hss = time.perf_counter() - t
+    ranks = H.ranks()
+    t = time.perf_counter()
+    U = F.ULV(H)
+    sync()
+    t_ulv = time.perf_counter() - t
+    log("offline: BF %.2fs, HSS %.2fs, ULV %.2fs; max ranks per level %s" %
+        (t_bf, t_hss, t_ulv, {l: int(max(v)) for l, v in ranks.items()}))
+
+    f_host = fi.rhs(1, n, k)
+    f = torch.from_numpy(np.ascontiguousarray(f_host.T)).to(dev).t()
+    u = B.apply(f)
+    sync()
+
+    results = {}
+    kernel_stats = {}
+    for name, prec in (("fp64", F.FIO_PREC_FP64), ("mixed", F.FIO_PREC_FP32)):
+        out = F.empty(n, k)
+        ws = torch.empty(F.solve_workspace_size(B, U, k, F.FIO_SOLVE_IR, prec, a.rel_res, 6), dtype=torch.uint8,
+                         device=dev)
+        kw = dict(mode=F.FIO_SOLVE_IR, prec=prec, rel_res_tol=a.rel_res, max_ir=6, out=out, ws=ws)
+        for _ in range(a.warmup):
+            F.approx_solve(B, U, u, **kw)
+        sync()
+        F.timing_reset()
+        F.timing_enable(True)
+        lat = []
+        steps_taken = []
+        sync()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            _, info = F.approx_solve(B, U, u, **kw)
+            e1.record()
+            steps_taken.append(info.ir_steps)
+            lat.append((e0, e1))
+        sync()
+        wall = time.perf_counter() - t0
+        F.timing_enable(False)
+        lat_ms = np.array([x.elapsed_time(y) for x, y in lat])
+        for kn in F.timing_names():
+            cnt, ms = F.timing_query(kn)
+            kernel_stats.setdefault(name, {})[kn] = (cnt, ms)
+        fh = out.detach().cpu().numpy()
+        err = np.linalg.norm(fh - f_host, axis=0) / np.linalg.norm(f_host, axis=0)
+        ms_step = wall * 1e3 / a.steps
+        results[name] = {"value": k / (ms_step / 1e3), "ms_per_step": ms_step, "max_col_rel_err": float(err.max()),
+                         "ir_steps": int(max(steps_taken)), "rel_res": float(info.rel_res),
+                         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))}}
+        log(name, json.dumps(results[name]))
+
+    # direct solve (no refinement) for reference: one K~^* apply and one ULV solve
+    out = F.empty(n, k)
+    for _ in range(a.warmup):
+        F.approx_solve(B, U, u, out=out)
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        F.approx_solve(B, U, u, out=out)
+    sync()
+    ms_direct = (time.perf_counter() - t0) * 1e3 / a.steps
+    err_d = float((np.linalg.norm(out.cpu().numpy() - f_host, axis=0) / np.linalg.norm(f_host, axis=0)).max())
+
+    # roofline of the dominant kernel of the headline (mixed) path
+    ks = kernel_stats["mixed"]
+    dom = max(ks, key=lambda kn: ks[kn][1])
+    cnt, tot = ks[dom]
+    avg_ms = tot / cnt
+    model = kernel_model(dom, n, q, k)
+    roof = None
+    if model:
+        byts, flops = model
+        peak_f = FP64_PEAK_TFLOPS if dom.endswith("f64") else FP32_PEAK_TFLOPS
+        t_mem = byts / (HBM_PEAK_GBS * 1e9)
+        t_alu = flops / (peak_f * 1e12)
+        if t_mem >= t_alu:
+            ach = byts / (avg_ms * 1e-3) / 1e9
+            roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+        else:
+            ach = flops / (avg_ms * 1e-3) / 1e12
+            roof = {"bound": "alu", "achieved": round(ach, 2), "peak": peak_f, "unit": "TFLOP/s",
+                    "frac": round(ach / peak_f, 4), "traffic": None}
+        roof.update({"kernel": dom, "avg_launch_ms": round(avg_ms, 4), "launches": cnt,
+                     "algorithmic_bytes_per_launch": int(byts), "algorithmic_flops_per_launch": float(flops)})
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = cpu_baseline(n, q, k, results["fp64"]["ir_steps"])
+
+    mixed = results["mixed"]
+    line = {
+        "metric": METRIC, "value": round(mixed["value"], 2), "unit": "RHS/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(mixed["ms_per_step"], 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp32+fp64", "data": "synthetic",
+        "config": {"workload": "1D FIO N=2^%d, c(x)=(2+sin 2pi x)/16, q=%d, HSS tol %g, p=10, %d RHS, "
+                               "refinement to rel residual %g" % (int(np.log2(n)), q, a.hss_tol, k, a.rel_res),
+                   "n": n, "nrhs": k, "q": q, "hss_tol": a.hss_tol,
+                   "hss_max_rank_per_level": {str(l): int(max(v)) for l, v in ranks.items()}},
+        "mixed": mixed, "fp64": results["fp64"],
+        "direct_fp64": {"ms_per_step": round(ms_direct, 3), "value": k / (ms_direct / 1e3),
+                        "max_col_rel_err": err_d},
+        "latency_ms": mixed["latency_ms"],
+        "offline_s": {"bf": round(t_bf, 3), "hss": round(t_hss, 3), "ulv": round(t_ulv, 3)},
+        "kernels_ms": {p: {kn: [c, round(m, 3)] for kn, (c, m) in d.items()} for p, d in kernel_stats.items()},
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -233,6 +233,20 @@ fio_status fio_approx_solve(fio_bf_t bf, hss_ulv_t f, const void *U, long ldu, v
 
 const char *fio_status_str(fio_status s);
 
+/* ---------------------------------------------------------------------------
+ * Measurement hooks.  While enabled, the library brackets each of its hot
+ * kernel launches (BF levels, ULV levels) with HIP events recorded on the
+ * launch stream and accumulates the durations per kernel name
+ * ("bf_transfer_f64", "bf_transfer_f32", "bf_middle_f64", "bf_leaf_in_f64",
+ * "bf_leaf_out_f64", ..., "ulv_up", "ulv_down", "ulv_root").
+ * fio_timing_query and fio_timing_names wait for the pending events; they
+ * return FIO_OK / the length of the comma-separated name list.
+ * ------------------------------------------------------------------------- */
+void fio_timing_enable(int on);
+void fio_timing_reset(void);
+int fio_timing_query(const char *kernel, long *launches, double *total_ms);
+int fio_timing_names(char *buf, size_t len);
+
 #ifdef __cplusplus
 }
 #endif

@@ -315,3 +315,24 @@ def approx_solve(bf, ulv, U, mode=FIO_SOLVE_DIRECT, prec=FIO_PREC_FP64, rel_res_
     if st != _lib.FIO_OK and not (st == -5 and not raise_on_nonconv):
         _lib.check(st, "fio_approx_solve")
     return F, inf
+
+
+def timing_enable(on=True):
+    lib().fio_timing_enable(1 if on else 0)
+
+
+def timing_reset():
+    lib().fio_timing_reset()
+
+
+def timing_query(kernel):
+    """(launches, total_ms) accumulated for a kernel name since the last reset."""
+    n, ms = C.c_long(), C.c_double()
+    _lib.check(lib().fio_timing_query(kernel.encode(), C.byref(n), C.byref(ms)), "fio_timing_query")
+    return n.value, ms.value
+
+
+def timing_names():
+    buf = C.create_string_buffer(4096)
+    lib().fio_timing_names(buf, 4096)
+    return [s for s in buf.value.decode().split(",") if s]

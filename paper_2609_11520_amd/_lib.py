@@ -68,6 +68,10 @@ PROTOS = {
     "fio_solve_workspace_size": (i32, [vp, vp, i32, C.POINTER(SolveOpts), C.POINTER(sz)]),
     "fio_approx_solve": (i32, [vp, vp, vp, lg, vp, lg, i32, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp, sz, vp]),
     "fio_status_str": (C.c_char_p, [i32]),
+    "fio_timing_enable": (None, [i32]),
+    "fio_timing_reset": (None, []),
+    "fio_timing_query": (i32, [C.c_char_p, C.POINTER(lg), C.POINTER(C.c_double)]),
+    "fio_timing_names": (i32, [C.c_char_p, sz]),
 }
 
 _lib = None

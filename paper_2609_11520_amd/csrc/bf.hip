@@ -9,6 +9,7 @@
 //   (p * q + i) * nrhs + col, so that consecutive lanes of a wave work on
 //   consecutive right-hand sides of the same pair.
 #include "bf.h"
+#include "timing.h"
 
 #include <cmath>
 #include <cstring>
@@ -468,8 +469,10 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
     const size_t nleaf = (size_t)(1L << bf->Lp) * bf->nsl;
     const long ng = bf->N / 2, np = bf->N;
     cpx<T> *cur = c0, *nxt = c1;
+    const bool f64 = sizeof(T) == 8;
     auto transfer = [&](size_t off, long G, bool a) {
         size_t nt = (size_t)ng * nrhs;
+        FIO_TIMED(f64 ? "bf_transfer_f64" : "bf_transfer_f32", s);
         if (a) {
             if (uni)
                 k_transfer<T, Q, true, true><<<grid1d(nt, TB), TB, 0, s>>>(F + off, G, cur, nxt, ng, nrhs);
@@ -485,6 +488,7 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
     };
     auto middle = [&](bool a) {
         size_t nt = (size_t)np * nrhs;
+        FIO_TIMED(f64 ? "bf_middle_f64" : "bf_middle_f32", s);
         if (a) {
             if (uni)
                 k_middle<T, Q, true, true><<<grid1d(nt, TB), TB, 0, s>>>(F + bf->offM, cur, nxt, np, nrhs);
@@ -499,17 +503,25 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
         std::swap(cur, nxt);
     };
     if (!adj) {
-        k_leaf_in_fwd<T, Q><<<grid1d(nleaf * nrhs, TB), TB, 0, s>>>(g, F + bf->offV, X, ldx, cur, nrhs);
+        {
+            FIO_TIMED(f64 ? "bf_leaf_in_f64" : "bf_leaf_in_f32", s);
+            k_leaf_in_fwd<T, Q><<<grid1d(nleaf * nrhs, TB), TB, 0, s>>>(g, F + bf->offV, X, ldx, cur, nrhs);
+        }
         for (int lev = bf->nl - 1; lev >= 0; --lev) transfer(bf->offC[lev], 1L << (bf->h + lev), false);
         middle(false);
         for (int lev = 0; lev < bf->nl; ++lev) transfer(bf->offB[lev], 1L << (bf->L - bf->h - lev - 1), false);
+        FIO_TIMED(f64 ? "bf_leaf_out_f64" : "bf_leaf_out_f32", s);
         k_leaf_out_fwd<T, Q><<<grid1d(((size_t)1 << bf->Lp) * nrhs, TB), TB, 0, s>>>(g, F + bf->offU, cur, Y,
                                                                                        ldy, nrhs);
     } else {
-        k_leaf_in_adj<T, Q><<<grid1d(nleaf * nrhs, TB), TB, 0, s>>>(g, F + bf->offU, X, ldx, cur, nrhs);
+        {
+            FIO_TIMED(f64 ? "bf_leaf_in_f64" : "bf_leaf_in_f32", s);
+            k_leaf_in_adj<T, Q><<<grid1d(nleaf * nrhs, TB), TB, 0, s>>>(g, F + bf->offU, X, ldx, cur, nrhs);
+        }
         for (int lev = bf->nl - 1; lev >= 0; --lev) transfer(bf->offB[lev], 1L << (bf->L - bf->h - lev - 1), true);
         middle(true);
         for (int lev = 0; lev < bf->nl; ++lev) transfer(bf->offC[lev], 1L << (bf->h + lev), true);
+        FIO_TIMED(f64 ? "bf_leaf_out_f64" : "bf_leaf_out_f32", s);
         k_leaf_out_adj<T, Q><<<grid1d(((size_t)1 << bf->Lp) * nrhs, TB), TB, 0, s>>>(g, F + bf->offV, cur, Y,
                                                                                        ldy, nrhs);
     }

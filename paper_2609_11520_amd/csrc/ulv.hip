@@ -11,6 +11,7 @@
 // c_tau = W^* [bhat1; chat2]; the root keeps Linv = L_rho^{-1}.  The online solve
 // is therefore 2 Lh + 2 batched small GEMM launches (see k_ulv_level).
 #include "hss.h"
+#include "timing.h"
 
 #include <cmath>
 #include <cstring>
@@ -673,6 +674,7 @@ void ulv_solve_impl(hss_ulv_s *f, const double2 *Y, long ldy, double2 *C, long l
         const double2 *yin = (l == Lh) ? Y : Yl[l];
         long ldin = (l == Lh) ? ldy : f->rows[l];
         dim3 grid(tilesM * tilesN, f->m[l].size());
+        FIO_TIMED("ulv_up", s);
         k_ulv_level<false><<<grid, 256, 0, s>>>(args(l), yin, ldin, Bl[l], f->rows[l], Yl[l - 1], f->rows[l - 1],
                                                 nullptr, 0, nrhs, tilesN);
     }
@@ -680,6 +682,7 @@ void ulv_solve_impl(hss_ulv_s *f, const double2 *Y, long ldy, double2 *C, long l
     if (f->m0 > 0) {
         ZgemmDesc d0{f->Linv.as<double2>(), Yl[0], rt, f->m0, nrhs, f->m0, f->m0, f->m0, f->m0};
         ZgemmDesc d1{f->Linv.as<double2>(), rt, Yl[0], f->m0, nrhs, f->m0, f->m0, f->m0, f->m0};
+        FIO_TIMED("ulv_root", s);
         zgemm_one(d0, false, zc(1.0), zc(0.0), s);
         zgemm_one(d1, true, zc(1.0), zc(0.0), s);
     }
@@ -690,6 +693,7 @@ void ulv_solve_impl(hss_ulv_s *f, const double2 *Y, long ldy, double2 *C, long l
         double2 *yout = (l == Lh) ? C : Yl[l];
         long ldout = (l == Lh) ? ldc : f->rows[l];
         dim3 grid(tilesM * tilesN, f->m[l].size());
+        FIO_TIMED("ulv_down", s);
         k_ulv_level<true><<<grid, 256, 0, s>>>(args(l), nullptr, 0, Bl[l], f->rows[l], Yl[l - 1], f->rows[l - 1],
                                                yout, ldout, nrhs, tilesN);
     }
