@@ -123,6 +123,13 @@ fio_status fio_bf_apply_adj(fio_bf_t bf, const void *X, long ldx, void *Y, long 
 
 void fio_bf_destroy(fio_bf_t bf);
 
+/* Selects the apply kernels: on != 0 (default) runs consecutive transfer factors
+ * as fused multi-level passes on closed sub-butterflies held in LDS, with the
+ * middle factor folded into the pass that ends at level h; on == 0 runs one
+ * kernel per factor.  Both give the same result up to rounding order.  Not
+ * thread-safe with respect to concurrent applies. */
+void fio_set_fused(int on);
+
 /* ---------------------------------------------------------------------------
  * Randomized black-box HSS construction of a Hermitian matrix (Section 3).
  * The tree is binary over rows 0..N-1, leaves of `leaf` rows (N = leaf 2^Lh);

@@ -336,3 +336,8 @@ def timing_names():
     buf = C.create_string_buffer(4096)
     lib().fio_timing_names(buf, 4096)
     return [s for s in buf.value.decode().split(",") if s]
+
+
+def set_fused(on=True):
+    """Fused multi-level butterfly passes (default) or one kernel per factor."""
+    lib().fio_set_fused(1 if on else 0)

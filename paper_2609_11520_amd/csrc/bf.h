@@ -12,6 +12,11 @@ struct fio_bf_s {
     fio::DevBuf f64;                   // complex128 factors, import/export layout
     fio::DevBuf f32;                   // complex64 copy (FIO_PREC_FP32)
     fio::DevBuf f16;                   // split-fp16 copy: hi and lo planes (FIO_PREC_SPLIT_FP16)
+    // structured transfer factors (built on the GPU only): twiddles of every B and C level and
+    // the two shared Lagrange matrices P_c(i, t) (host copy, passed as kernel arguments)
+    bool structured = false;
+    fio::DevBuf tw64, tw32;
+    double Pchild[2 * 16 * 16] = {};
     fio::DevBuf ws;                    // handle-owned workspace (ws == NULL in the applies)
     std::mutex ws_mu;
 };
@@ -24,4 +29,5 @@ size_t bf_coef_elems(const fio_bf_s *bf, int nrhs);   // complex entries of one 
 void bf_apply_impl(fio_bf_s *bf, bool adjoint, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs,
                    fio_prec prec, void *ws, hipStream_t s);
 size_t bf_ws_bytes(const fio_bf_s *bf, int nrhs, fio_prec prec);
+size_t bf_tw_off(const fio_bf_s *bf, bool cside, int lev);   // element offset of a level's twiddles
 }  // namespace fio

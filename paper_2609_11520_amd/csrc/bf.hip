@@ -8,16 +8,12 @@
 // Coefficient buffers: entry (pair p, coefficient i, column col) at
 //   (p * q + i) * nrhs + col, so that consecutive lanes of a wave work on
 //   consecutive right-hand sides of the same pair.
-#include "bf.h"
-#include "timing.h"
+#include "bf_apply.h"
 
 #include <cmath>
 #include <cstring>
 
 namespace fio {
-
-// Points per leaf box: N / 2^L' = 8 for every N >= 64 when L' = L - 3.
-constexpr int kLeafPts = 8;
 
 // ---------------------------------------------------------------------------
 // geometry
@@ -60,19 +56,21 @@ fio_status bf_plan(const fio_bf_desc *d, fio_bf_s *bf) {
     return FIO_OK;
 }
 
+static bool g_fused_off = false;
+bool fused_disabled() { return g_fused_off; }
+void set_fused_disabled(bool v) { g_fused_off = v; }
+
+size_t bf_tw_off(const fio_bf_s *bf, bool cside, int lev) {
+    const size_t ntw = (size_t)(bf->N / 2) * 8 * bf->q;
+    return ((cside ? bf->nl : 0) + (size_t)lev) * ntw;
+}
+
 size_t bf_coef_elems(const fio_bf_s *bf, int nrhs) { return (size_t)bf->N * bf->q * (size_t)nrhs; }
 
-// ---------------------------------------------------------------------------
 // factor evaluation (Section 2.2).  Phase differences are formed as
 // differences (centers are exact binary fractions / integers), so an entry's
 // phase carries only the rounding of O(1)-sized terms; M's full phase keeps
 // its large exact parts exact (integer products and two-product splits).
-struct Geo {
-    long N;
-    int L, h, Lp, q, b, nsl;
-    double c0, c1;
-};
-
 __device__ __forceinline__ double cheb_t(int i, int q) { return cospi((2.0 * i + 1.0) / (2.0 * q)); }
 
 // Lagrange basis of node t on the reference first-kind grid, at u in [-1, 1].
@@ -229,16 +227,82 @@ __global__ void gen_U(Geo g, double2 *out) {
     out[id] = zc(e.x * pv, e.y * pv);
 }
 
+// Structured transfer factors: every 2q x 2q transfer block is, per (c_out, c_in) quadrant,
+// diag(a) P diag(b) with P a Lagrange matrix shared by all groups of a side, and
+//   B side: a = exp(2 pi i (Phi(z_tau,i, eta_beta) - Phi(y_alpha, eta_beta))),
+//           b = exp(-2 pi i (Phi(z_alpha,t, eta_beta) - Phi(y_alpha, eta_beta))), P = P_cout(i, t);
+//   C side: a = exp(-2 pi i (Phi(y_tau, gamma_sigma,j) - Phi(y_tau, eta_sigma))),
+//           b = exp(2 pi i (Phi(y_tau, gamma_beta,t) - Phi(y_tau, eta_sigma))),   P = P_cin(t, j),
+// with P_c(i, t) = p_t((c - 1/2) + t_i / 2) on the reference grid.  The products a P b are the
+// entries of Section 2.2 (the common phase at the parent's center cancels); a and b are phase
+// differences between nearby points, so they are accurate at any N.
+// Layout per group: [c_out][4][q] = a(c_out, 0), a(c_out, 1), b(c_out, 0), b(c_out, 1).
+__global__ void gen_TW_B(Geo g, int l, double2 *out) {
+    const int q = g.q;
+    size_t n = (size_t)(g.N / 2) * 8 * q;
+    size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    const int i = id % q, kind = (id / q) % 4, cout = (id / (4 * q)) % 2;
+    const long grp = id / (8 * q);
+    const long G = 1L << (g.L - l - 1);
+    const long alpha = grp / G, sigma = grp % G;
+    const int cin = kind & 1;
+    const double wa = 1.0 / (double)(1L << l), wt = 0.5 * wa;
+    const double ya = (alpha + 0.5) * wa;
+    const long beta = 2 * sigma + cin;
+    const double wf = (double)g.N / (double)(1L << (g.L - l));
+    const double eta = -0.5 * g.N + (beta + 0.5) * wf;
+    double dz, sz, sgn;
+    if (kind < 2) {        // a: z_tau,i - y_alpha
+        dz = (cout - 0.5) * wt + 0.5 * wt * cheb_t(i, q);
+        sgn = 1.0;
+    } else {               // b: z_alpha,i - y_alpha, conjugated
+        dz = 0.5 * wa * cheb_t(i, q);
+        sgn = -1.0;
+    }
+    sz = 2.0 * ya + dz;
+    const double ph = dz * eta + 2.0 * g.c1 * cospi(sz) * sinpi(dz) * fabs(eta);
+    out[id] = e2pi(sgn * ph);
+}
+
+__global__ void gen_TW_C(Geo g, int l, double2 *out) {
+    const int q = g.q;
+    size_t n = (size_t)(g.N / 2) * 8 * q;
+    size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    const int i = id % q, kind = (id / q) % 4, cout = (id / (4 * q)) % 2;
+    const long grp = id / (8 * q);
+    const long G = 1L << l;
+    const long alpha = grp / G, sigma = grp % G;
+    const int cin = kind & 1;
+    const long tau = 2 * alpha + cout;
+    const double y = (tau + 0.5) / (double)(1L << (g.L - l));
+    const double ws = (double)g.N / (double)(1L << l), wb = 0.5 * ws;
+    const double eta_s = -0.5 * g.N + (sigma + 0.5) * ws;
+    const double sgn = eta_s > 0 ? 1.0 : -1.0;
+    const double kap = y + sgn * c_of(g, y);
+    double ph;
+    if (kind < 2)          // a: -(gamma_sigma,j - eta_sigma)
+        ph = -kap * (0.5 * ws * cheb_t(i, q));
+    else                   // b: gamma_beta,t - eta_sigma
+        ph = kap * ((cin - 0.5) * wb + 0.5 * wb * cheb_t(i, q));
+    out[id] = e2pi(ph);
+}
+
+__global__ void gen_Pchild(int q, double *out) {
+    // out[c][i][t] = P_c(i, t) = p_t((c - 1/2) + t_i / 2)
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= 2 * q * q) return;
+    const int t = id % q, i = (id / q) % q, c = id / (q * q);
+    out[id] = lagr((c - 0.5) + 0.5 * cheb_t(i, q), t, q);
+}
+
 __global__ void cvt_f64_f32(const double2 *in, float2 *out, size_t n) {
     size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     if (id < n) {
         double2 v = in[id];
         out[id] = make_float2((float)v.x, (float)v.y);
     }
-}
-
-static Geo geo_of(const fio_bf_s *bf) {
-    return Geo{bf->N, bf->L, bf->h, bf->Lp, bf->q, bf->b, bf->nsl, bf->desc.c0, bf->desc.c1};
 }
 
 static void bf_generate(fio_bf_s *bf, hipStream_t s) {
@@ -256,6 +320,21 @@ static void bf_generate(fio_bf_s *bf, hipStream_t s) {
     gen_M<<<grid1d(nM, T), T, 0, s>>>(g, base + bf->offM);
     gen_U<<<grid1d(nV, T), T, 0, s>>>(g, base + bf->offU);
     FIO_HIP(hipGetLastError());
+    // structured transfer twiddles and the shared Lagrange matrices
+    if (bf->nl > 0) {
+        const size_t ntw = (size_t)(bf->N / 2) * 8 * bf->q;
+        bf->tw64.alloc(2 * bf->nl * ntw * sizeof(double2));
+        for (int lev = 0; lev < bf->nl; ++lev) {
+            gen_TW_B<<<grid1d(ntw, T), T, 0, s>>>(g, bf->h + lev, bf->tw64.as<double2>() + bf_tw_off(bf, false, lev));
+            gen_TW_C<<<grid1d(ntw, T), T, 0, s>>>(g, bf->h + lev, bf->tw64.as<double2>() + bf_tw_off(bf, true, lev));
+        }
+        DevBuf pd(2 * bf->q * bf->q * sizeof(double));
+        gen_Pchild<<<1, 2 * bf->q * bf->q, 0, s>>>(bf->q, pd.as<double>());
+        FIO_HIP(hipGetLastError());
+        FIO_HIP(hipMemcpyAsync(bf->Pchild, pd.p, 2 * bf->q * bf->q * sizeof(double), hipMemcpyDeviceToHost, s));
+        FIO_HIP(hipStreamSynchronize(s));
+        bf->structured = true;
+    }
 }
 
 void bf_make_lowprec(fio_bf_s *bf, hipStream_t s);   // bf_lowprec.hip
@@ -265,283 +344,20 @@ static void bf_make_copies(fio_bf_s *bf, hipStream_t s) {
         bf->f32.alloc(bf->total * sizeof(float2));
         cvt_f64_f32<<<grid1d(bf->total, 256), 256, 0, s>>>(bf->f64.as<double2>(), bf->f32.as<float2>(),
                                                          bf->total);
+        if (bf->structured) {
+            const size_t ntw = 2 * bf->nl * (size_t)(bf->N / 2) * 8 * bf->q;
+            bf->tw32.alloc(ntw * sizeof(float2));
+            cvt_f64_f32<<<grid1d(ntw, 256), 256, 0, s>>>(bf->tw64.as<double2>(), bf->tw32.as<float2>(), ntw);
+        }
         FIO_HIP(hipGetLastError());
     }
     if (bf->desc.prec_mask & (1u << FIO_PREC_SPLIT_FP16)) bf_make_lowprec(bf, s);
 }
 
-// ---------------------------------------------------------------------------
-// apply kernels.  One thread per (unit, column); a unit is a leaf box, a
-// transfer group or a middle-level pair.  Template Q = q keeps the 2q input
-// and output coefficients of a unit in registers.
-template <typename T> __device__ __forceinline__ cpx<T> ld_in(const double2 *p) {
-    double2 v = *p;
-    return cmake<cpx<T>>((T)v.x, (T)v.y);
-}
-
-// V (forward): coef[(tau 2^L' + sigma) q + j] = sum_s V[sigma][tau][j][s] x[sigma b + s]
-template <typename T, int Q>
-__global__ void k_leaf_in_fwd(Geo g, const cpx<T> *__restrict__ V, const double2 *__restrict__ X, long ldx,
-                              cpx<T> *__restrict__ out, int nrhs) {
-    using C = cpx<T>;
-    size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    size_t nunit = (size_t)(1L << g.Lp) * g.nsl;
-    if (id >= nunit * nrhs) return;
-    int col = id % nrhs;
-    size_t unit = id / nrhs;
-    int tau = unit % g.nsl;
-    long sigma = unit / g.nsl;
-    C x[kLeafPts];
-    const double2 *xp = X + (size_t)col * ldx + sigma * kLeafPts;
-#pragma unroll
-    for (int s = 0; s < kLeafPts; ++s) x[s] = ld_in<T>(xp + s);
-    const C *blk = V + (sigma * g.nsl + tau) * (size_t)Q * kLeafPts;
-    size_t p = (size_t)tau * (1L << g.Lp) + sigma;
-    C *op = out + p * Q * nrhs + col;
-#pragma unroll
-    for (int j = 0; j < Q; ++j) {
-        C acc = czero<C>();
-#pragma unroll
-        for (int s = 0; s < kLeafPts; ++s) cfma(acc, blk[j * kLeafPts + s], x[s]);
-        op[(size_t)j * nrhs] = acc;
-    }
-}
-
-// U^* (adjoint): coef[(tau nsl + sigma) q + i] = sum_s conj(U[tau][sigma][s][i]) u[tau b + s]
-template <typename T, int Q>
-__global__ void k_leaf_in_adj(Geo g, const cpx<T> *__restrict__ U, const double2 *__restrict__ X, long ldx,
-                              cpx<T> *__restrict__ out, int nrhs) {
-    using C = cpx<T>;
-    size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    size_t nunit = (size_t)(1L << g.Lp) * g.nsl;
-    if (id >= nunit * nrhs) return;
-    int col = id % nrhs;
-    size_t unit = id / nrhs;              // = tau * nsl + sigma = pair index at U-level L'
-    long tau = unit / g.nsl;
-    C x[kLeafPts];
-    const double2 *xp = X + (size_t)col * ldx + tau * kLeafPts;
-#pragma unroll
-    for (int s = 0; s < kLeafPts; ++s) x[s] = ld_in<T>(xp + s);
-    const C *blk = U + unit * (size_t)kLeafPts * Q;
-    C *op = out + unit * Q * nrhs + col;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        C acc = czero<C>();
-#pragma unroll
-        for (int s = 0; s < kLeafPts; ++s) cfmac(acc, blk[s * Q + i], x[s]);
-        op[(size_t)i * nrhs] = acc;
-    }
-}
-
-// One transfer factor (B or C, forward or conjugate-transposed).
-// Group grp = alpha G + sigma; forward inputs at pairs alpha 2G + 2 sigma + c,
-// outputs at pairs (2 alpha + c) G + sigma.
-template <typename T, int Q, bool ADJ, bool UNI>
-__global__ void __launch_bounds__(256) k_transfer(const cpx<T> *__restrict__ A, long G,
-                                                  const cpx<T> *__restrict__ in, cpx<T> *__restrict__ out,
-                                                  long ngroups, int nrhs) {
-    using C = cpx<T>;
-    constexpr int Q2 = 2 * Q;
-    size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (id >= (size_t)ngroups * nrhs) return;
-    int col = id % nrhs;
-    long grp = id / nrhs;
-    if (UNI) grp = __builtin_amdgcn_readfirstlane(grp);
-    long alpha = grp / G, sigma = grp % G;
-    size_t pin0 = alpha * 2 * G + 2 * sigma;          // pairs pin0, pin0 + 1
-    size_t pout0 = 2 * alpha * G + sigma;             // pairs pout0, pout0 + G
-    size_t src0 = ADJ ? pout0 : pin0, src1 = ADJ ? pout0 + G : pin0 + 1;
-    size_t dst0 = ADJ ? pin0 : pout0, dst1 = ADJ ? pin0 + 1 : pout0 + G;
-    C x[Q2];
-#pragma unroll
-    for (int t = 0; t < Q; ++t) {
-        x[t] = in[(src0 * Q + t) * nrhs + col];
-        x[Q + t] = in[(src1 * Q + t) * nrhs + col];
-    }
-    const C *a = A + (size_t)grp * Q2 * Q2;
-#pragma unroll
-    for (int r = 0; r < Q2; ++r) {
-        C acc = czero<C>();
-#pragma unroll
-        for (int c = 0; c < Q2; ++c) {
-            if (ADJ)
-                cfmac(acc, a[c * Q2 + r], x[c]);
-            else
-                cfma(acc, a[r * Q2 + c], x[c]);
-        }
-        size_t dst = (r < Q) ? dst0 : dst1;
-        out[(dst * Q + (r % Q)) * nrhs + col] = acc;
-    }
-}
-
-template <typename T, int Q, bool ADJ, bool UNI>
-__global__ void __launch_bounds__(256) k_middle(const cpx<T> *__restrict__ M, const cpx<T> *__restrict__ in,
-                                                cpx<T> *__restrict__ out, long npairs, int nrhs) {
-    using C = cpx<T>;
-    size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (id >= (size_t)npairs * nrhs) return;
-    int col = id % nrhs;
-    long p = id / nrhs;
-    if (UNI) p = __builtin_amdgcn_readfirstlane(p);
-    C x[Q];
-#pragma unroll
-    for (int j = 0; j < Q; ++j) x[j] = in[(p * Q + j) * nrhs + col];
-    const C *m = M + (size_t)p * Q * Q;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        C acc = czero<C>();
-#pragma unroll
-        for (int j = 0; j < Q; ++j) {
-            if (ADJ)
-                cfmac(acc, m[j * Q + i], x[j]);
-            else
-                cfma(acc, m[i * Q + j], x[j]);
-        }
-        out[(p * Q + i) * nrhs + col] = acc;
-    }
-}
-
-// U (forward): y[tau b + s] = sum_sigma sum_i U[tau][sigma][s][i] coef[(tau nsl + sigma) q + i]
-template <typename T, int Q>
-__global__ void k_leaf_out_fwd(Geo g, const cpx<T> *__restrict__ U, const cpx<T> *__restrict__ in,
-                               double2 *__restrict__ Y, long ldy, int nrhs) {
-    using C = cpx<T>;
-    size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    size_t nunit = (size_t)1 << g.Lp;
-    if (id >= nunit * nrhs) return;
-    int col = id % nrhs;
-    long tau = id / nrhs;
-    C acc[kLeafPts];
-#pragma unroll
-    for (int s = 0; s < kLeafPts; ++s) acc[s] = czero<C>();
-    for (int sg = 0; sg < g.nsl; ++sg) {
-        size_t p = (size_t)tau * g.nsl + sg;
-        C d[Q];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) d[i] = in[(p * Q + i) * nrhs + col];
-        const C *blk = U + p * (size_t)kLeafPts * Q;
-#pragma unroll
-        for (int s = 0; s < kLeafPts; ++s) {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) cfma(acc[s], blk[s * Q + i], d[i]);
-        }
-    }
-    double2 *yp = Y + (size_t)col * ldy + tau * kLeafPts;
-#pragma unroll
-    for (int s = 0; s < kLeafPts; ++s) yp[s] = zc((double)acc[s].x, (double)acc[s].y);
-}
-
-// V^* (adjoint): f[sigma b + s] = sum_tau sum_j conj(V[sigma][tau][j][s]) coef[(tau 2^L' + sigma) q + j]
-template <typename T, int Q>
-__global__ void k_leaf_out_adj(Geo g, const cpx<T> *__restrict__ V, const cpx<T> *__restrict__ in,
-                               double2 *__restrict__ Y, long ldy, int nrhs) {
-    using C = cpx<T>;
-    size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    size_t nunit = (size_t)1 << g.Lp;
-    if (id >= nunit * nrhs) return;
-    int col = id % nrhs;
-    long sigma = id / nrhs;
-    C acc[kLeafPts];
-#pragma unroll
-    for (int s = 0; s < kLeafPts; ++s) acc[s] = czero<C>();
-    for (int t = 0; t < g.nsl; ++t) {
-        size_t p = (size_t)t * (1L << g.Lp) + sigma;
-        C c[Q];
-#pragma unroll
-        for (int j = 0; j < Q; ++j) c[j] = in[(p * Q + j) * nrhs + col];
-        const C *blk = V + ((size_t)sigma * g.nsl + t) * Q * kLeafPts;
-#pragma unroll
-        for (int j = 0; j < Q; ++j)
-#pragma unroll
-            for (int s = 0; s < kLeafPts; ++s) cfmac(acc[s], blk[j * kLeafPts + s], c[j]);
-    }
-    double2 *yp = Y + (size_t)col * ldy + sigma * kLeafPts;
-#pragma unroll
-    for (int s = 0; s < kLeafPts; ++s) yp[s] = zc((double)acc[s].x, (double)acc[s].y);
-}
-
-template <typename T, int Q>
-static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs,
-                    const cpx<T> *F, cpx<T> *c0, cpx<T> *c1, hipStream_t s) {
-    Geo g = geo_of(bf);
-    const unsigned TB = 256;
-    const bool uni = (nrhs % 64) == 0;
-    const size_t nleaf = (size_t)(1L << bf->Lp) * bf->nsl;
-    const long ng = bf->N / 2, np = bf->N;
-    cpx<T> *cur = c0, *nxt = c1;
-    const bool f64 = sizeof(T) == 8;
-    auto transfer = [&](size_t off, long G, bool a) {
-        size_t nt = (size_t)ng * nrhs;
-        FIO_TIMED(f64 ? "bf_transfer_f64" : "bf_transfer_f32", s);
-        if (a) {
-            if (uni)
-                k_transfer<T, Q, true, true><<<grid1d(nt, TB), TB, 0, s>>>(F + off, G, cur, nxt, ng, nrhs);
-            else
-                k_transfer<T, Q, true, false><<<grid1d(nt, TB), TB, 0, s>>>(F + off, G, cur, nxt, ng, nrhs);
-        } else {
-            if (uni)
-                k_transfer<T, Q, false, true><<<grid1d(nt, TB), TB, 0, s>>>(F + off, G, cur, nxt, ng, nrhs);
-            else
-                k_transfer<T, Q, false, false><<<grid1d(nt, TB), TB, 0, s>>>(F + off, G, cur, nxt, ng, nrhs);
-        }
-        std::swap(cur, nxt);
-    };
-    auto middle = [&](bool a) {
-        size_t nt = (size_t)np * nrhs;
-        FIO_TIMED(f64 ? "bf_middle_f64" : "bf_middle_f32", s);
-        if (a) {
-            if (uni)
-                k_middle<T, Q, true, true><<<grid1d(nt, TB), TB, 0, s>>>(F + bf->offM, cur, nxt, np, nrhs);
-            else
-                k_middle<T, Q, true, false><<<grid1d(nt, TB), TB, 0, s>>>(F + bf->offM, cur, nxt, np, nrhs);
-        } else {
-            if (uni)
-                k_middle<T, Q, false, true><<<grid1d(nt, TB), TB, 0, s>>>(F + bf->offM, cur, nxt, np, nrhs);
-            else
-                k_middle<T, Q, false, false><<<grid1d(nt, TB), TB, 0, s>>>(F + bf->offM, cur, nxt, np, nrhs);
-        }
-        std::swap(cur, nxt);
-    };
-    if (!adj) {
-        {
-            FIO_TIMED(f64 ? "bf_leaf_in_f64" : "bf_leaf_in_f32", s);
-            k_leaf_in_fwd<T, Q><<<grid1d(nleaf * nrhs, TB), TB, 0, s>>>(g, F + bf->offV, X, ldx, cur, nrhs);
-        }
-        for (int lev = bf->nl - 1; lev >= 0; --lev) transfer(bf->offC[lev], 1L << (bf->h + lev), false);
-        middle(false);
-        for (int lev = 0; lev < bf->nl; ++lev) transfer(bf->offB[lev], 1L << (bf->L - bf->h - lev - 1), false);
-        FIO_TIMED(f64 ? "bf_leaf_out_f64" : "bf_leaf_out_f32", s);
-        k_leaf_out_fwd<T, Q><<<grid1d(((size_t)1 << bf->Lp) * nrhs, TB), TB, 0, s>>>(g, F + bf->offU, cur, Y,
-                                                                                       ldy, nrhs);
-    } else {
-        {
-            FIO_TIMED(f64 ? "bf_leaf_in_f64" : "bf_leaf_in_f32", s);
-            k_leaf_in_adj<T, Q><<<grid1d(nleaf * nrhs, TB), TB, 0, s>>>(g, F + bf->offU, X, ldx, cur, nrhs);
-        }
-        for (int lev = bf->nl - 1; lev >= 0; --lev) transfer(bf->offB[lev], 1L << (bf->L - bf->h - lev - 1), true);
-        middle(true);
-        for (int lev = 0; lev < bf->nl; ++lev) transfer(bf->offC[lev], 1L << (bf->h + lev), true);
-        FIO_TIMED(f64 ? "bf_leaf_out_f64" : "bf_leaf_out_f32", s);
-        k_leaf_out_adj<T, Q><<<grid1d(((size_t)1 << bf->Lp) * nrhs, TB), TB, 0, s>>>(g, F + bf->offV, cur, Y,
-                                                                                       ldy, nrhs);
-    }
-    FIO_HIP(hipGetLastError());
-}
-
-template <typename T>
-static void apply_t(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs,
-                    const cpx<T> *F, void *ws, hipStream_t s) {
-    cpx<T> *c0 = reinterpret_cast<cpx<T> *>(ws);
-    cpx<T> *c1 = c0 + bf_coef_elems(bf, nrhs);
-    switch (bf->q) {
-#define FIO_Q(QQ) \
-    case QQ: apply_q<T, QQ>(bf, adj, X, ldx, Y, ldy, nrhs, F, c0, c1, s); break;
-        FIO_Q(2) FIO_Q(3) FIO_Q(4) FIO_Q(5) FIO_Q(6) FIO_Q(7) FIO_Q(8) FIO_Q(9)
-        FIO_Q(10) FIO_Q(11) FIO_Q(12) FIO_Q(13) FIO_Q(14) FIO_Q(15) FIO_Q(16)
-#undef FIO_Q
-        default: throw Err{FIO_ERR_UNSUPPORTED};
-    }
-}
+void bf_apply_f64(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs,
+                 const double2 *F, void *ws, hipStream_t s);
+void bf_apply_f32(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs,
+                 const float2 *F, void *ws, hipStream_t s);
 
 void bf_apply_split16(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs,
                       void *ws, hipStream_t s);   // bf_lowprec.hip
@@ -562,11 +378,11 @@ void bf_apply_impl(fio_bf_s *bf, bool adjoint, const double2 *X, long ldx, doubl
     if (nrhs <= 0) return;
     switch (prec) {
         case FIO_PREC_FP64:
-            apply_t<double>(bf, adjoint, X, ldx, Y, ldy, nrhs, bf->f64.as<double2>(), ws, s);
+            bf_apply_f64(bf, adjoint, X, ldx, Y, ldy, nrhs, bf->f64.as<double2>(), ws, s);
             break;
         case FIO_PREC_FP32:
             if (!bf->f32.p) throw Err{FIO_ERR_ARG};
-            apply_t<float>(bf, adjoint, X, ldx, Y, ldy, nrhs, bf->f32.as<float2>(), ws, s);
+            bf_apply_f32(bf, adjoint, X, ldx, Y, ldy, nrhs, bf->f32.as<float2>(), ws, s);
             break;
         case FIO_PREC_SPLIT_FP16:
             if (!bf->f16.p) throw Err{FIO_ERR_ARG};
@@ -698,6 +514,8 @@ extern "C" fio_status fio_bf_apply_adj(fio_bf_t bf, const void *X, long ldx, voi
 }
 
 extern "C" void fio_bf_destroy(fio_bf_t bf) { delete bf; }
+
+extern "C" void fio_set_fused(int on) { set_fused_disabled(on == 0); }
 
 extern "C" const char *fio_status_str(fio_status s) {
     switch (s) {

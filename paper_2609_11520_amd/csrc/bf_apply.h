@@ -1,0 +1,833 @@
+// Apply kernels of the butterfly factorization (Section 2.2, eq. bf), shared by the
+// per-precision translation units bf_apply_f64.hip and bf_apply_f32.hip.
+#pragma once
+#include "bf.h"
+#include "timing.h"
+
+namespace fio {
+
+constexpr int kLeafPts = 8;
+bool fused_disabled();
+
+// ---------------------------------------------------------------------------
+// geometry passed to the kernels by value
+struct Geo {
+    long N;
+    int L, h, Lp, q, b, nsl;
+    double c0, c1;
+};
+
+
+inline Geo geo_of(const fio_bf_s *bf) {
+    return Geo{bf->N, bf->L, bf->h, bf->Lp, bf->q, bf->b, bf->nsl, bf->desc.c0, bf->desc.c1};
+}
+
+// ---------------------------------------------------------------------------
+// apply kernels.  One thread per (unit, column); a unit is a leaf box, a
+// transfer group or a middle-level pair.  Template Q = q keeps the 2q input
+// and output coefficients of a unit in registers.
+template <typename T> __device__ __forceinline__ cpx<T> ld_in(const double2 *p) {
+    double2 v = *p;
+    return cmake<cpx<T>>((T)v.x, (T)v.y);
+}
+
+// V (forward): coef[(tau 2^L' + sigma) q + j] = sum_s V[sigma][tau][j][s] x[sigma b + s]
+template <typename T, int Q>
+__global__ void k_leaf_in_fwd(Geo g, const cpx<T> *__restrict__ V, const double2 *__restrict__ X, long ldx,
+                              cpx<T> *__restrict__ out, int nrhs) {
+    using C = cpx<T>;
+    size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    size_t nunit = (size_t)(1L << g.Lp) * g.nsl;
+    if (id >= nunit * nrhs) return;
+    int col = id % nrhs;
+    size_t unit = id / nrhs;
+    int tau = unit % g.nsl;
+    long sigma = unit / g.nsl;
+    C x[kLeafPts];
+    const double2 *xp = X + (size_t)col * ldx + sigma * kLeafPts;
+#pragma unroll
+    for (int s = 0; s < kLeafPts; ++s) x[s] = ld_in<T>(xp + s);
+    const C *blk = V + (sigma * g.nsl + tau) * (size_t)Q * kLeafPts;
+    size_t p = (size_t)tau * (1L << g.Lp) + sigma;
+    C *op = out + p * Q * nrhs + col;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        C acc = czero<C>();
+#pragma unroll
+        for (int s = 0; s < kLeafPts; ++s) cfma(acc, blk[j * kLeafPts + s], x[s]);
+        op[(size_t)j * nrhs] = acc;
+    }
+}
+
+// U^* (adjoint): coef[(tau nsl + sigma) q + i] = sum_s conj(U[tau][sigma][s][i]) u[tau b + s]
+template <typename T, int Q>
+__global__ void k_leaf_in_adj(Geo g, const cpx<T> *__restrict__ U, const double2 *__restrict__ X, long ldx,
+                              cpx<T> *__restrict__ out, int nrhs) {
+    using C = cpx<T>;
+    size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    size_t nunit = (size_t)(1L << g.Lp) * g.nsl;
+    if (id >= nunit * nrhs) return;
+    int col = id % nrhs;
+    size_t unit = id / nrhs;              // = tau * nsl + sigma = pair index at U-level L'
+    long tau = unit / g.nsl;
+    C x[kLeafPts];
+    const double2 *xp = X + (size_t)col * ldx + tau * kLeafPts;
+#pragma unroll
+    for (int s = 0; s < kLeafPts; ++s) x[s] = ld_in<T>(xp + s);
+    const C *blk = U + unit * (size_t)kLeafPts * Q;
+    C *op = out + unit * Q * nrhs + col;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        C acc = czero<C>();
+#pragma unroll
+        for (int s = 0; s < kLeafPts; ++s) cfmac(acc, blk[s * Q + i], x[s]);
+        op[(size_t)i * nrhs] = acc;
+    }
+}
+
+// One transfer factor (B or C, forward or conjugate-transposed).
+// Group grp = alpha G + sigma; forward inputs at pairs alpha 2G + 2 sigma + c,
+// outputs at pairs (2 alpha + c) G + sigma.
+template <typename T, int Q, bool ADJ, bool UNI>
+__global__ void __launch_bounds__(256) k_transfer(const cpx<T> *__restrict__ A, long G,
+                                                  const cpx<T> *__restrict__ in, cpx<T> *__restrict__ out,
+                                                  long ngroups, int nrhs) {
+    using C = cpx<T>;
+    constexpr int Q2 = 2 * Q;
+    size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (id >= (size_t)ngroups * nrhs) return;
+    int col = id % nrhs;
+    long grp = id / nrhs;
+    if (UNI) grp = __builtin_amdgcn_readfirstlane(grp);
+    long alpha = grp / G, sigma = grp % G;
+    size_t pin0 = alpha * 2 * G + 2 * sigma;          // pairs pin0, pin0 + 1
+    size_t pout0 = 2 * alpha * G + sigma;             // pairs pout0, pout0 + G
+    size_t src0 = ADJ ? pout0 : pin0, src1 = ADJ ? pout0 + G : pin0 + 1;
+    size_t dst0 = ADJ ? pin0 : pout0, dst1 = ADJ ? pin0 + 1 : pout0 + G;
+    C x[Q2];
+#pragma unroll
+    for (int t = 0; t < Q; ++t) {
+        x[t] = in[(src0 * Q + t) * nrhs + col];
+        x[Q + t] = in[(src1 * Q + t) * nrhs + col];
+    }
+    const C *a = A + (size_t)grp * Q2 * Q2;
+#pragma unroll
+    for (int r = 0; r < Q2; ++r) {
+        C acc = czero<C>();
+#pragma unroll
+        for (int c = 0; c < Q2; ++c) {
+            if (ADJ)
+                cfmac(acc, a[c * Q2 + r], x[c]);
+            else
+                cfma(acc, a[r * Q2 + c], x[c]);
+        }
+        size_t dst = (r < Q) ? dst0 : dst1;
+        out[(dst * Q + (r % Q)) * nrhs + col] = acc;
+    }
+}
+
+template <typename T, int Q, bool ADJ, bool UNI>
+__global__ void __launch_bounds__(256) k_middle(const cpx<T> *__restrict__ M, const cpx<T> *__restrict__ in,
+                                                cpx<T> *__restrict__ out, long npairs, int nrhs) {
+    using C = cpx<T>;
+    size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (id >= (size_t)npairs * nrhs) return;
+    int col = id % nrhs;
+    long p = id / nrhs;
+    if (UNI) p = __builtin_amdgcn_readfirstlane(p);
+    C x[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) x[j] = in[(p * Q + j) * nrhs + col];
+    const C *m = M + (size_t)p * Q * Q;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        C acc = czero<C>();
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+            if (ADJ)
+                cfmac(acc, m[j * Q + i], x[j]);
+            else
+                cfma(acc, m[i * Q + j], x[j]);
+        }
+        out[(p * Q + i) * nrhs + col] = acc;
+    }
+}
+
+// U (forward): y[tau b + s] = sum_sigma sum_i U[tau][sigma][s][i] coef[(tau nsl + sigma) q + i]
+template <typename T, int Q>
+__global__ void k_leaf_out_fwd(Geo g, const cpx<T> *__restrict__ U, const cpx<T> *__restrict__ in,
+                               double2 *__restrict__ Y, long ldy, int nrhs) {
+    using C = cpx<T>;
+    size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    size_t nunit = (size_t)1 << g.Lp;
+    if (id >= nunit * nrhs) return;
+    int col = id % nrhs;
+    long tau = id / nrhs;
+    C acc[kLeafPts];
+#pragma unroll
+    for (int s = 0; s < kLeafPts; ++s) acc[s] = czero<C>();
+    for (int sg = 0; sg < g.nsl; ++sg) {
+        size_t p = (size_t)tau * g.nsl + sg;
+        C d[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) d[i] = in[(p * Q + i) * nrhs + col];
+        const C *blk = U + p * (size_t)kLeafPts * Q;
+#pragma unroll
+        for (int s = 0; s < kLeafPts; ++s) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) cfma(acc[s], blk[s * Q + i], d[i]);
+        }
+    }
+    double2 *yp = Y + (size_t)col * ldy + tau * kLeafPts;
+#pragma unroll
+    for (int s = 0; s < kLeafPts; ++s) yp[s] = zc((double)acc[s].x, (double)acc[s].y);
+}
+
+// V^* (adjoint): f[sigma b + s] = sum_tau sum_j conj(V[sigma][tau][j][s]) coef[(tau 2^L' + sigma) q + j]
+template <typename T, int Q>
+__global__ void k_leaf_out_adj(Geo g, const cpx<T> *__restrict__ V, const cpx<T> *__restrict__ in,
+                               double2 *__restrict__ Y, long ldy, int nrhs) {
+    using C = cpx<T>;
+    size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    size_t nunit = (size_t)1 << g.Lp;
+    if (id >= nunit * nrhs) return;
+    int col = id % nrhs;
+    long sigma = id / nrhs;
+    C acc[kLeafPts];
+#pragma unroll
+    for (int s = 0; s < kLeafPts; ++s) acc[s] = czero<C>();
+    for (int t = 0; t < g.nsl; ++t) {
+        size_t p = (size_t)t * (1L << g.Lp) + sigma;
+        C c[Q];
+#pragma unroll
+        for (int j = 0; j < Q; ++j) c[j] = in[(p * Q + j) * nrhs + col];
+        const C *blk = V + ((size_t)sigma * g.nsl + t) * Q * kLeafPts;
+#pragma unroll
+        for (int j = 0; j < Q; ++j)
+#pragma unroll
+            for (int s = 0; s < kLeafPts; ++s) cfmac(acc[s], blk[j * kLeafPts + s], c[j]);
+    }
+    double2 *yp = Y + (size_t)col * ldy + sigma * kLeafPts;
+#pragma unroll
+    for (int s = 0; s < kLeafPts; ++s) yp[s] = zc((double)acc[s].x, (double)acc[s].y);
+}
+
+// ---------------------------------------------------------------------------
+// Fused transfer pass: KL consecutive transfer factors on closed sub-butterflies.
+// In the pair numbering of the first factor of a pass (G0 = number of sigma per
+// alpha there), subproblem (A, S) owns the 2^KL input pairs A 2 G0 + S 2^KL + b
+// and, after KL factors, the 2^KL output pairs (A 2^KL + a) (G0 / 2^(KL-1)) + S;
+// every intermediate pair stays inside the subproblem.  A workgroup of 2^KL
+// waves keeps the subproblem's coefficients for 64 right-hand sides in LDS
+// (lane = column); at every factor two waves share one 2q x 2q block (q output
+// rows each), read through the scalar cache (the block index is uniform per
+// wave) after the whole workgroup has pulled the step's blocks into L2.  ADJ runs the
+// pass backwards with conjugate-transposed blocks.  EPI_M applies the middle
+// factor (or its adjoint) to the pass's output pairs before they are stored.
+template <typename T> struct FusedArgs {
+    const cpx<T> *A[4];      // factor array of forward step j
+    const cpx<T> *M;         // middle factor (EPI_M)
+    long G0;
+    const cpx<T> *in;
+    cpx<T> *out;
+    int nrhs;
+    int sink;                // always 0 (keeps the L2 warm-up loads alive)
+    double *sink_ptr;
+};
+
+template <typename T, int Q, int KL, bool ADJ, bool EPI_M>
+__global__ void __launch_bounds__((1 << KL) * 64, 4) k_transfer_fused(FusedArgs<T> a) {
+    using C = cpx<T>;
+    constexpr int P = 1 << KL, NG = P / 2, NW = P, Q2 = 2 * Q;
+    __shared__ C lds[P * Q * 64];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int col = blockIdx.y * 64 + lane;
+    const bool act = col < a.nrhs;
+    const long nS = (2 * a.G0) >> KL;
+    const long A = blockIdx.x / nS, S = blockIdx.x % nS;
+    const long Glast = a.G0 >> (KL - 1);
+    const size_t ld = (size_t)a.nrhs;
+    // L2 prefetch of a step's factor blocks: every thread loads a few 16-byte chunks of the
+    // step's NG blocks into registers; they are consumed (stored only when sink != 0, i.e.
+    // never) after the step's compute, so the loads overlap it and the scalar loads of the
+    // following step hit L2.
+    constexpr int NT = 64 * P;
+    constexpr int CPB = (int)((size_t)Q2 * Q2 * sizeof(C) / 16);   // 16-byte chunks per block
+    constexpr int NPF = (NG * CPB + NT - 1) / NT;
+    double2 pf[NPF];
+    auto issue = [&](int j) {
+        const int Gl = P >> (j + 1);
+        const long Gj = a.G0 >> j;
+#pragma unroll
+        for (int k = 0; k < NPF; ++k) {
+            const int e = tid + k * NT;
+            pf[k] = zc(0.0, 0.0);
+            if (e < NG * CPB) {
+                const int b = e / CPB, off = e % CPB;
+                const long g = (A * (1L << j) + b / Gl) * Gj + S * Gl + b % Gl;
+                pf[k] = reinterpret_cast<const double2 *>(a.A[j] + (size_t)g * Q2 * Q2)[off];
+            }
+        }
+    };
+    auto consume = [&]() {
+        if (a.sink) {
+#pragma unroll
+            for (int k = 0; k < NPF; ++k) a.sink_ptr[tid * NPF + k] = pf[k].x + pf[k].y;
+        }
+    };
+    issue(ADJ ? KL - 1 : 0);
+    // load: forward input positions (or forward output positions for ADJ)
+    for (int lp = wave; lp < P; lp += NW) {
+        const long gp = ADJ ? (A * P + lp) * Glast + S : A * 2 * a.G0 + S * P + lp;
+        const C *src = a.in + (size_t)gp * Q * ld + col;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) lds[(lp * Q + i) * 64 + lane] = act ? src[i * ld] : czero<C>();
+    }
+    __syncthreads();
+    // two waves per group: wave = 2 * group + half, half selects output rows [half Q, half Q + Q)
+    const int grp = wave >> 1, half = wave & 1;
+#pragma unroll
+    for (int st = 0; st < KL; ++st) {
+        const int j = ADJ ? KL - 1 - st : st;
+        consume();
+        if (st + 1 < KL) issue(ADJ ? j - 1 : j + 1);
+        const int Gl = P >> (j + 1);
+        const long Gj = a.G0 >> j;
+        const int aj = grp / Gl, sj = grp % Gl;
+        const long g = (A * (1L << j) + aj) * Gj + (S * Gl + sj);
+        const int lin0 = aj * 2 * Gl + 2 * sj, lout0 = 2 * aj * Gl + sj;
+        const int src0 = ADJ ? lout0 : lin0, src1 = ADJ ? lout0 + Gl : lin0 + 1;
+        const int dst = half ? (ADJ ? lin0 + 1 : lout0 + Gl) : (ADJ ? lin0 : lout0);
+        C x[Q2];
+#pragma unroll
+        for (int t = 0; t < Q; ++t) {
+            x[t] = lds[(src0 * Q + t) * 64 + lane];
+            x[Q + t] = lds[(src1 * Q + t) * 64 + lane];
+        }
+        __syncthreads();
+        const C *blk = a.A[j] + (size_t)g * Q2 * Q2;
+#pragma unroll 1
+        for (int rr = 0; rr < Q; ++rr) {
+            const int r = half * Q + rr;
+            C acc = czero<C>();
+#pragma unroll
+            for (int c = 0; c < Q2; ++c) {
+                if (ADJ)
+                    cfmac(acc, blk[c * Q2 + r], x[c]);
+                else
+                    cfma(acc, blk[r * Q2 + c], x[c]);
+            }
+            lds[(dst * Q + rr) * 64 + lane] = acc;
+        }
+        __syncthreads();
+    }
+    // store: forward output positions (or forward input positions for ADJ); one pair per wave
+    for (int lp = wave; lp < P; lp += NW) {
+        const long gp = ADJ ? A * 2 * a.G0 + S * P + lp : (A * P + lp) * Glast + S;
+        C *dstp = a.out + (size_t)gp * Q * ld + col;
+        if (EPI_M) {
+            C x[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) x[i] = lds[(lp * Q + i) * 64 + lane];
+            const C *m = a.M + (size_t)gp * Q * Q;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                C acc = czero<C>();
+#pragma unroll
+                for (int jj = 0; jj < Q; ++jj) {
+                    if (ADJ)
+                        cfmac(acc, m[jj * Q + i], x[jj]);
+                    else
+                        cfma(acc, m[i * Q + jj], x[jj]);
+                }
+                if (act) dstp[i * ld] = acc;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                if (act) dstp[i * ld] = lds[(lp * Q + i) * 64 + lane];
+        }
+    }
+}
+
+template <typename T, int Q, int KL>
+static void launch_fused(const FusedArgs<T> &fa, bool adj, bool epi, long N, hipStream_t s) {
+    dim3 grid((unsigned)(N >> KL), (unsigned)((fa.nrhs + 63) / 64));
+    dim3 block((1 << KL) * 64);
+    if (adj) {
+        if (epi)
+            k_transfer_fused<T, Q, KL, true, true><<<grid, block, 0, s>>>(fa);
+        else
+            k_transfer_fused<T, Q, KL, true, false><<<grid, block, 0, s>>>(fa);
+    } else {
+        if (epi)
+            k_transfer_fused<T, Q, KL, false, true><<<grid, block, 0, s>>>(fa);
+        else
+            k_transfer_fused<T, Q, KL, false, false><<<grid, block, 0, s>>>(fa);
+    }
+}
+
+// largest pass length whose LDS tile fits (two workgroups per CU)
+template <typename T, int Q> constexpr int fused_max_kl() {
+    return ((size_t)8 * Q * 64 * sizeof(cpx<T>) <= 80 * 1024) ? 3 : 2;
+}
+
+template <typename T, int Q>
+static void run_fused(const FusedArgs<T> &fa, int kl, bool adj, bool epi, long N, hipStream_t s) {
+    switch (kl) {
+        case 1: launch_fused<T, Q, 1>(fa, adj, epi, N, s); break;
+        case 2: launch_fused<T, Q, 2>(fa, adj, epi, N, s); break;
+        case 3:
+            if constexpr (fused_max_kl<T, Q>() >= 3) {
+                launch_fused<T, Q, 3>(fa, adj, epi, N, s);
+                break;
+            }
+            [[fallthrough]];
+        default: throw Err{FIO_ERR_UNSUPPORTED};
+    }
+}
+
+template <int Q> constexpr bool fused_q() { return Q == 5 || Q == 9 || Q == 13; }
+
+// Structured fused pass: same sub-butterfly decomposition as k_transfer_fused, with every
+// 2q x 2q block applied as four quadrants diag(a) P diag(b) (see gen_TW_B / gen_TW_C):
+// the per-group twiddles (8q complex) come through the scalar cache, the two shared q x q
+// Lagrange matrices travel in the kernel arguments.  Wave 2g + h handles group g:
+// forward it produces output child c_out = h, adjoint it produces input child c_in = h.
+template <typename T, int Q> struct StructArgs {
+    const cpx<T> *TW[4];     // twiddles of forward step j
+    const cpx<T> *M;         // middle factor (EPI_M)
+    long G0;
+    const cpx<T> *in;
+    cpx<T> *out;
+    int nrhs;
+    int cside;               // 1: C factors (P transposed, child index c_in)
+    T P[2][Q][Q];            // P_c(i, t)
+};
+
+template <typename T, int Q, int KL, bool ADJ, bool EPI_M>
+__global__ void __launch_bounds__((1 << KL) * 64, 4) k_struct_fused(StructArgs<T, Q> a) {
+    using C = cpx<T>;
+    constexpr int P = 1 << KL;
+    __shared__ C lds[P * Q * 64];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int col = blockIdx.y * 64 + lane;
+    const bool act = col < a.nrhs;
+    const long nS = (2 * a.G0) >> KL;
+    const long A = blockIdx.x / nS, S = blockIdx.x % nS;
+    const long Glast = a.G0 >> (KL - 1);
+    const size_t ld = (size_t)a.nrhs;
+    {
+        const int lp = wave;
+        const long gp = ADJ ? (A * P + lp) * Glast + S : A * 2 * a.G0 + S * P + lp;
+        const C *src = a.in + (size_t)gp * Q * ld + col;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) lds[(lp * Q + i) * 64 + lane] = act ? src[i * ld] : czero<C>();
+    }
+    __syncthreads();
+    const int grp = wave >> 1, h = wave & 1;
+    const bool cs = a.cside != 0;
+#pragma unroll
+    for (int st = 0; st < KL; ++st) {
+        const int j = ADJ ? KL - 1 - st : st;
+        const int Gl = P >> (j + 1);
+        const long Gj = a.G0 >> j;
+        const int aj = grp / Gl, sj = grp % Gl;
+        const long g = (A * (1L << j) + aj) * Gj + (S * Gl + sj);
+        const int lin0 = aj * 2 * Gl + 2 * sj, lout0 = 2 * aj * Gl + sj;
+        const C *tw = a.TW[j] + (size_t)g * 8 * Q;
+        C acc[Q];
+#pragma unroll
+        for (int r = 0; r < Q; ++r) acc[r] = czero<C>();
+#pragma unroll
+        for (int o = 0; o < 2; ++o) {
+            // FWD: o = c_in, output child c_out = h.  ADJ: o = c_out, input child c_in = h.
+            const int cout = ADJ ? o : h, cin = ADJ ? h : o;
+            const int srcp = ADJ ? (o ? lout0 + Gl : lout0) : lin0 + o;
+            const C *ta = tw + cout * 4 * Q + cin * Q;          // a(c_out, c_in, .)
+            const C *tb = tw + cout * 4 * Q + (2 + cin) * Q;    // b(c_out, c_in, .)
+            const int pc = cs ? cin : cout;
+            C w[Q];
+#pragma unroll
+            for (int t = 0; t < Q; ++t) {
+                const C x = lds[(srcp * Q + t) * 64 + lane];
+                if (ADJ) {
+                    C aa = ta[t];
+                    w[t] = cmul(cconj(aa), x);
+                } else {
+                    w[t] = cmul(tb[t], x);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < Q; ++r) {
+                C v = czero<C>();
+#pragma unroll
+                for (int t = 0; t < Q; ++t) {
+                    // forward block quadrant M(r, t); the adjoint applies M^T
+                    const T m = ADJ ? (cs ? a.P[pc][r][t] : a.P[pc][t][r]) : (cs ? a.P[pc][t][r] : a.P[pc][r][t]);
+                    v.x = fma(m, w[t].x, v.x);
+                    v.y = fma(m, w[t].y, v.y);
+                }
+                if (ADJ)
+                    cfmac(acc[r], tb[r], v);
+                else
+                    cfma(acc[r], ta[r], v);
+            }
+        }
+        __syncthreads();
+        const int dst = ADJ ? lin0 + h : (h ? lout0 + Gl : lout0);
+#pragma unroll
+        for (int r = 0; r < Q; ++r) lds[(dst * Q + r) * 64 + lane] = acc[r];
+        __syncthreads();
+    }
+    {
+        const int lp = wave;
+        const long gp = ADJ ? A * 2 * a.G0 + S * P + lp : (A * P + lp) * Glast + S;
+        C *dstp = a.out + (size_t)gp * Q * ld + col;
+        if (EPI_M) {
+            C x[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) x[i] = lds[(lp * Q + i) * 64 + lane];
+            const C *m = a.M + (size_t)gp * Q * Q;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                C acc = czero<C>();
+#pragma unroll
+                for (int jj = 0; jj < Q; ++jj) {
+                    if (ADJ)
+                        cfmac(acc, m[jj * Q + i], x[jj]);
+                    else
+                        cfma(acc, m[i * Q + jj], x[jj]);
+                }
+                if (act) dstp[i * ld] = acc;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                if (act) dstp[i * ld] = lds[(lp * Q + i) * 64 + lane];
+        }
+    }
+}
+
+template <typename T, int Q, int KL>
+static void launch_struct(const StructArgs<T, Q> &sa, bool adj, bool epi, long N, hipStream_t s) {
+    dim3 grid((unsigned)(N >> KL), (unsigned)((sa.nrhs + 63) / 64));
+    dim3 block((1 << KL) * 64);
+    if (adj) {
+        if (epi)
+            k_struct_fused<T, Q, KL, true, true><<<grid, block, 0, s>>>(sa);
+        else
+            k_struct_fused<T, Q, KL, true, false><<<grid, block, 0, s>>>(sa);
+    } else {
+        if (epi)
+            k_struct_fused<T, Q, KL, false, true><<<grid, block, 0, s>>>(sa);
+        else
+            k_struct_fused<T, Q, KL, false, false><<<grid, block, 0, s>>>(sa);
+    }
+}
+
+template <typename T, int Q>
+static void run_struct(const StructArgs<T, Q> &sa, int kl, bool adj, bool epi, long N, hipStream_t s) {
+    switch (kl) {
+        case 1: launch_struct<T, Q, 1>(sa, adj, epi, N, s); break;
+        case 2: launch_struct<T, Q, 2>(sa, adj, epi, N, s); break;
+        case 3:
+            if constexpr (fused_max_kl<T, Q>() >= 3) {
+                launch_struct<T, Q, 3>(sa, adj, epi, N, s);
+                break;
+            }
+            [[fallthrough]];
+        default: throw Err{FIO_ERR_UNSUPPORTED};
+    }
+}
+
+
+// Leaf factors with coalesced block I/O.  A workgroup (256 threads) owns 4 leaf boxes
+// (32 consecutive rows of the N x nrhs block) and 64 right-hand sides.  The block is
+// moved between HBM and LDS with lanes along rows (coalesced in the column-major
+// layout) and used with lanes along columns, as the coefficient buffers are.
+//   IN  = true : coefficients of the 8 boxes x 8 coarse partners from the vector
+//                (V forward, U^* adjoint);
+//   IN  = false: the vector from the coefficients (U forward, V^* adjoint).
+// Coarse partner c of leaf box b has pair index b nsl + c (U side) or c 2^L' + b (V side).
+template <typename T, int Q, bool IN, bool VSIDE>
+__global__ void __launch_bounds__(256) k_leaf_io(Geo g, const cpx<T> *__restrict__ Fblk,
+                                                 const double2 *__restrict__ Xin, long ldx,
+                                                 const cpx<T> *__restrict__ cin, cpx<T> *__restrict__ cout,
+                                                 double2 *__restrict__ Yout, long ldy, int nrhs) {
+    using C = cpx<T>;
+    constexpr int NB = 4;                           // leaf boxes per workgroup
+    constexpr int R = NB * kLeafPts;                // rows per workgroup
+    __shared__ C tile[64][R + 1];                   // [column][row]
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const long box0 = (long)blockIdx.x * NB;        // first leaf box of the workgroup
+    const int c0 = blockIdx.y * 64;
+    const int ncol = nrhs - c0 < 64 ? nrhs - c0 : 64;
+    const int col = c0 + lane;
+    const bool act = lane < ncol;
+    const long Lp2 = 1L << g.Lp;
+    if (IN) {
+        for (int e = tid; e < R * 64; e += 256) {
+            const int r = e % R, cc = e / R;
+            double2 v = cc < ncol ? Xin[(box0 * kLeafPts + r) + (size_t)(c0 + cc) * ldx] : zc(0.0, 0.0);
+            tile[cc][r] = cmake<C>((T)v.x, (T)v.y);
+        }
+        __syncthreads();
+        // unit = (local box b, coarse partner c)
+        for (int u = wave; u < NB * g.nsl; u += 4) {
+            const int b = u / g.nsl, c = u % g.nsl;
+            const long box = box0 + b;
+            C x[kLeafPts];
+#pragma unroll
+            for (int s = 0; s < kLeafPts; ++s) x[s] = tile[lane][b * kLeafPts + s];
+            size_t p;
+            const C *blk;
+            if (VSIDE) {    // V: block V[sigma = box][tau = c] (q x 8), pair c 2^L' + box
+                p = (size_t)c * Lp2 + box;
+                blk = Fblk + ((size_t)box * g.nsl + c) * Q * kLeafPts;
+            } else {        // U^*: block U[tau = box][sigma = c] (8 x q), pair box nsl + c
+                p = (size_t)box * g.nsl + c;
+                blk = Fblk + p * (size_t)kLeafPts * Q;
+            }
+            C *op = cout + p * Q * (size_t)nrhs + col;
+#pragma unroll
+            for (int j = 0; j < Q; ++j) {
+                C acc = czero<C>();
+#pragma unroll
+                for (int s = 0; s < kLeafPts; ++s) {
+                    if (VSIDE)
+                        cfma(acc, blk[j * kLeafPts + s], x[s]);
+                    else
+                        cfmac(acc, blk[s * Q + j], x[s]);
+                }
+                if (act) op[(size_t)j * nrhs] = acc;
+            }
+        }
+    } else {
+        // each wave produces one box's rows for its lane's column
+        for (int b = wave; b < NB; b += 4) {
+            const long box = box0 + b;
+            C acc[kLeafPts];
+#pragma unroll
+            for (int s = 0; s < kLeafPts; ++s) acc[s] = czero<C>();
+            for (int c = 0; c < g.nsl; ++c) {
+                size_t p;
+                const C *blk;
+                if (VSIDE) {    // V^*: block V[sigma = box][tau = c], pair c 2^L' + box
+                    p = (size_t)c * Lp2 + box;
+                    blk = Fblk + ((size_t)box * g.nsl + c) * Q * kLeafPts;
+                } else {        // U: block U[tau = box][sigma = c], pair box nsl + c
+                    p = (size_t)box * g.nsl + c;
+                    blk = Fblk + p * (size_t)kLeafPts * Q;
+                }
+                C d[Q];
+                const C *ip = cin + p * Q * (size_t)nrhs + col;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) d[i] = act ? ip[(size_t)i * nrhs] : czero<C>();
+#pragma unroll
+                for (int s = 0; s < kLeafPts; ++s)
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) {
+                        if (VSIDE)
+                            cfmac(acc[s], blk[i * kLeafPts + s], d[i]);
+                        else
+                            cfma(acc[s], blk[s * Q + i], d[i]);
+                    }
+            }
+#pragma unroll
+            for (int s = 0; s < kLeafPts; ++s) tile[lane][b * kLeafPts + s] = acc[s];
+        }
+        __syncthreads();
+        for (int e = tid; e < R * 64; e += 256) {
+            const int r = e % R, cc = e / R;
+            if (cc < ncol) {
+                C v = tile[cc][r];
+                Yout[(box0 * kLeafPts + r) + (size_t)(c0 + cc) * ldy] = zc((double)v.x, (double)v.y);
+            }
+        }
+    }
+}
+
+template <typename T, int Q>
+static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs,
+                    const cpx<T> *F, cpx<T> *c0, cpx<T> *c1, hipStream_t s) {
+    Geo g = geo_of(bf);
+    const unsigned TB = 256;
+    const bool uni = (nrhs % 64) == 0;
+    const size_t nleaf = (size_t)(1L << bf->Lp) * bf->nsl;
+    const long ng = bf->N / 2, np = bf->N;
+    cpx<T> *cur = c0, *nxt = c1;
+    const bool f64 = sizeof(T) == 8;
+    auto transfer = [&](size_t off, long G, bool a) {
+        size_t nt = (size_t)ng * nrhs;
+        FIO_TIMED(f64 ? "bf_transfer_f64" : "bf_transfer_f32", s);
+        if (a) {
+            if (uni)
+                k_transfer<T, Q, true, true><<<grid1d(nt, TB), TB, 0, s>>>(F + off, G, cur, nxt, ng, nrhs);
+            else
+                k_transfer<T, Q, true, false><<<grid1d(nt, TB), TB, 0, s>>>(F + off, G, cur, nxt, ng, nrhs);
+        } else {
+            if (uni)
+                k_transfer<T, Q, false, true><<<grid1d(nt, TB), TB, 0, s>>>(F + off, G, cur, nxt, ng, nrhs);
+            else
+                k_transfer<T, Q, false, false><<<grid1d(nt, TB), TB, 0, s>>>(F + off, G, cur, nxt, ng, nrhs);
+        }
+        std::swap(cur, nxt);
+    };
+    // fused passes: levels [lo, hi) of the C side (cside) or the B side; forward C passes
+    // run C^[h+hi] .. C^[h+lo+1], forward B passes run B^[h+lo+1] .. B^[h+hi]
+    bool fused = false;
+    int kmax = 1;
+    if constexpr (fused_q<Q>()) {
+        fused = bf->nl > 0 && !fused_disabled();
+        kmax = fused_max_kl<T, Q>();
+    }
+    auto pass = [&](bool a, bool cside, int lo, int hi, bool epi) {
+        if constexpr (fused_q<Q>()) {
+            const int kl = hi - lo;
+            if (bf->structured) {
+                StructArgs<T, Q> sa;
+                const cpx<T> *TWb = f64 ? reinterpret_cast<const cpx<T> *>(bf->tw64.p)
+                                        : reinterpret_cast<const cpx<T> *>(bf->tw32.p);
+                for (int jj = 0; jj < 4; ++jj) sa.TW[jj] = nullptr;
+                for (int jj = 0; jj < kl; ++jj)
+                    sa.TW[jj] = TWb + bf_tw_off(bf, cside, cside ? hi - 1 - jj : lo + jj);
+                sa.M = F + bf->offM;
+                sa.G0 = cside ? (1L << (bf->h + hi - 1)) : (1L << (bf->L - (bf->h + lo) - 1));
+                sa.in = cur;
+                sa.out = nxt;
+                sa.nrhs = nrhs;
+                sa.cside = cside ? 1 : 0;
+                for (int c = 0; c < 2; ++c)
+                    for (int i = 0; i < Q; ++i)
+                        for (int t = 0; t < Q; ++t) sa.P[c][i][t] = (T)bf->Pchild[(c * Q + i) * Q + t];
+                FIO_TIMED(f64 ? "bf_struct_f64" : "bf_struct_f32", s);
+                run_struct<T, Q>(sa, kl, a, epi, bf->N, s);
+                std::swap(cur, nxt);
+                return;
+            }
+            FusedArgs<T> fa;
+            for (int j = 0; j < 4; ++j) fa.A[j] = nullptr;
+            for (int j = 0; j < kl; ++j)
+                fa.A[j] = F + (cside ? bf->offC[hi - 1 - j] : bf->offB[lo + j]);
+            fa.M = F + bf->offM;
+            fa.G0 = cside ? (1L << (bf->h + hi - 1)) : (1L << (bf->L - (bf->h + lo) - 1));
+            fa.in = cur;
+            fa.out = nxt;
+            fa.nrhs = nrhs;
+            fa.sink = 0;
+            fa.sink_ptr = reinterpret_cast<double *>(nxt);
+            FIO_TIMED(f64 ? "bf_fused_f64" : "bf_fused_f32", s);
+            run_fused<T, Q>(fa, kl, a, epi, bf->N, s);
+            std::swap(cur, nxt);
+        }
+    };
+    auto middle = [&](bool a) {
+        size_t nt = (size_t)np * nrhs;
+        FIO_TIMED(f64 ? "bf_middle_f64" : "bf_middle_f32", s);
+        if (a) {
+            if (uni)
+                k_middle<T, Q, true, true><<<grid1d(nt, TB), TB, 0, s>>>(F + bf->offM, cur, nxt, np, nrhs);
+            else
+                k_middle<T, Q, true, false><<<grid1d(nt, TB), TB, 0, s>>>(F + bf->offM, cur, nxt, np, nrhs);
+        } else {
+            if (uni)
+                k_middle<T, Q, false, true><<<grid1d(nt, TB), TB, 0, s>>>(F + bf->offM, cur, nxt, np, nrhs);
+            else
+                k_middle<T, Q, false, false><<<grid1d(nt, TB), TB, 0, s>>>(F + bf->offM, cur, nxt, np, nrhs);
+        }
+        std::swap(cur, nxt);
+    };
+    const bool tiled = ((1L << bf->Lp) % 4) == 0;
+    const dim3 tgrid((unsigned)((1L << bf->Lp) / 4), (unsigned)((nrhs + 63) / 64));
+    if (!adj) {
+        {
+            FIO_TIMED(f64 ? "bf_leaf_in_f64" : "bf_leaf_in_f32", s);
+            if (tiled)
+                k_leaf_io<T, Q, true, true><<<tgrid, 256, 0, s>>>(g, F + bf->offV, X, ldx, nullptr, cur, nullptr, 0,
+                                                                  nrhs);
+            else
+                k_leaf_in_fwd<T, Q><<<grid1d(nleaf * nrhs, TB), TB, 0, s>>>(g, F + bf->offV, X, ldx, cur, nrhs);
+        }
+        if (fused) {
+            // C^[L'] .. C^[h+1] in passes from the top; the last pass also applies M
+            for (int hi = bf->nl; hi > 0;) {
+                const int lo = hi - kmax > 0 ? hi - kmax : 0;
+                pass(false, true, lo, hi, lo == 0);
+                hi = lo;
+            }
+            for (int lo = 0; lo < bf->nl;) {
+                const int hi = lo + kmax < bf->nl ? lo + kmax : bf->nl;
+                pass(false, false, lo, hi, false);
+                lo = hi;
+            }
+        } else {
+            for (int lev = bf->nl - 1; lev >= 0; --lev) transfer(bf->offC[lev], 1L << (bf->h + lev), false);
+            middle(false);
+            for (int lev = 0; lev < bf->nl; ++lev) transfer(bf->offB[lev], 1L << (bf->L - bf->h - lev - 1), false);
+        }
+        FIO_TIMED(f64 ? "bf_leaf_out_f64" : "bf_leaf_out_f32", s);
+        if (tiled)
+            k_leaf_io<T, Q, false, false><<<tgrid, 256, 0, s>>>(g, F + bf->offU, nullptr, 0, cur, nullptr, Y, ldy,
+                                                                nrhs);
+        else
+            k_leaf_out_fwd<T, Q><<<grid1d(((size_t)1 << bf->Lp) * nrhs, TB), TB, 0, s>>>(g, F + bf->offU, cur, Y,
+                                                                                           ldy, nrhs);
+    } else {
+        {
+            FIO_TIMED(f64 ? "bf_leaf_in_f64" : "bf_leaf_in_f32", s);
+            if (tiled)
+                k_leaf_io<T, Q, true, false><<<tgrid, 256, 0, s>>>(g, F + bf->offU, X, ldx, nullptr, cur, nullptr, 0,
+                                                                   nrhs);
+            else
+                k_leaf_in_adj<T, Q><<<grid1d(nleaf * nrhs, TB), TB, 0, s>>>(g, F + bf->offU, X, ldx, cur, nrhs);
+        }
+        if (fused) {
+            // B^[L']* .. B^[h+1]* in passes from the top; the last pass also applies M*
+            for (int hi = bf->nl; hi > 0;) {
+                const int lo = hi - kmax > 0 ? hi - kmax : 0;
+                pass(true, false, lo, hi, lo == 0);
+                hi = lo;
+            }
+            for (int lo = 0; lo < bf->nl;) {
+                const int hi = lo + kmax < bf->nl ? lo + kmax : bf->nl;
+                pass(true, true, lo, hi, false);
+                lo = hi;
+            }
+        } else {
+            for (int lev = bf->nl - 1; lev >= 0; --lev) transfer(bf->offB[lev], 1L << (bf->L - bf->h - lev - 1), true);
+            middle(true);
+            for (int lev = 0; lev < bf->nl; ++lev) transfer(bf->offC[lev], 1L << (bf->h + lev), true);
+        }
+        FIO_TIMED(f64 ? "bf_leaf_out_f64" : "bf_leaf_out_f32", s);
+        if (tiled)
+            k_leaf_io<T, Q, false, true><<<tgrid, 256, 0, s>>>(g, F + bf->offV, nullptr, 0, cur, nullptr, Y, ldy,
+                                                               nrhs);
+        else
+            k_leaf_out_adj<T, Q><<<grid1d(((size_t)1 << bf->Lp) * nrhs, TB), TB, 0, s>>>(g, F + bf->offV, cur, Y,
+                                                                                           ldy, nrhs);
+    }
+    FIO_HIP(hipGetLastError());
+}
+
+template <typename T>
+void apply_t(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs,
+                    const cpx<T> *F, void *ws, hipStream_t s) {
+    cpx<T> *c0 = reinterpret_cast<cpx<T> *>(ws);
+    cpx<T> *c1 = c0 + bf_coef_elems(bf, nrhs);
+    switch (bf->q) {
+#define FIO_Q(QQ) \
+    case QQ: apply_q<T, QQ>(bf, adj, X, ldx, Y, ldy, nrhs, F, c0, c1, s); break;
+        FIO_Q(2) FIO_Q(3) FIO_Q(4) FIO_Q(5) FIO_Q(6) FIO_Q(7) FIO_Q(8) FIO_Q(9)
+        FIO_Q(10) FIO_Q(11) FIO_Q(12) FIO_Q(13) FIO_Q(14) FIO_Q(15) FIO_Q(16)
+#undef FIO_Q
+        default: throw Err{FIO_ERR_UNSUPPORTED};
+    }
+}
+
+}  // namespace fio

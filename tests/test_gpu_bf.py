@@ -102,3 +102,55 @@ def test_edge_cases_and_errors():
     # FP32 factors were not requested
     with pytest.raises(F.FioError):
         B.apply(dev(x), prec=F.FIO_PREC_FP32)
+
+
+@pytest.mark.parametrize("n", [1024, 4096, 1 << 14, 1 << 16])
+def test_fused_passes_match_per_level_kernels(n):
+    # the fused multi-level passes (with M folded in) against one kernel per factor,
+    # on imported oracle factors, for every pass split of nl = 2..5 transfer levels
+    F = fiohss()
+    step("fused vs per-level n=%d" % n)
+    B = gpu_bf(F, n, 9, "sin16", imported=True, precs=(F.FIO_PREC_FP64, F.FIO_PREC_FP32))
+    ob = oracle_bf(n, 9, "sin16")
+    x = fi.complex_gaussian(14, fi.PURPOSE_PROBE, n, 3)
+    ref_f, ref_a = ob.apply(x), ob.apply_adj(x)
+    for fused in (True, False):
+        F.set_fused(fused)
+        try:
+            assert rel(host(B.apply(dev(x))), ref_f) < 1e-12
+            assert rel(host(B.apply_adj(dev(x))), ref_a) < 1e-12
+            assert rel(host(B.apply(dev(x), prec=F.FIO_PREC_FP32)), ref_f) < 1e-5
+        finally:
+            F.set_fused(True)
+
+
+@pytest.mark.parametrize("n,q", [(1024, 9), (4096, 9), (1 << 14, 9), (1 << 16, 9), (4096, 13), (1 << 14, 5)])
+def test_structured_passes_match_explicit_blocks(n, q):
+    # GPU-built factors: the structured passes (twiddles x shared Lagrange matrices) against
+    # the explicit 2q x 2q blocks applied one factor per kernel
+    F = fiohss()
+    step("structured vs explicit n=%d q=%d" % (n, q))
+    c0, c1 = PHASES["sin16"]
+    B = F.BF(n, q, c0, c1, precs=(F.FIO_PREC_FP64, F.FIO_PREC_FP32))
+    x = dev(fi.complex_gaussian(15, fi.PURPOSE_PROBE, n, 65))
+    ys, ysa = host(B.apply(x)), host(B.apply_adj(x))
+    ys32 = host(B.apply(x, prec=F.FIO_PREC_FP32))
+    F.set_fused(False)
+    try:
+        ye, yea = host(B.apply(x)), host(B.apply_adj(x))
+    finally:
+        F.set_fused(True)
+    assert rel(ys, ye) < 1e-13 and rel(ysa, yea) < 1e-13
+    assert rel(ys32, ye) < 1e-5
+
+
+@pytest.mark.parametrize("k", [1, 37, 64, 130])
+def test_leaf_tiles_ragged_columns(k):
+    # ragged right-hand-side counts through the tiled leaf kernels (partial 64-column tiles)
+    F = fiohss()
+    n = 4096
+    B = gpu_bf(F, n, 9, "sin16", imported=True)
+    ob = oracle_bf(n, 9, "sin16")
+    x = fi.complex_gaussian(16, fi.PURPOSE_PROBE, n, k)
+    assert rel(host(B.apply(dev(x))), ob.apply(x)) < 1e-12
+    assert rel(host(B.apply_adj(dev(x))), ob.apply_adj(x)) < 1e-12
