@@ -407,7 +407,7 @@ template <typename T, int Q> struct StructArgs {
     T P[2][Q][Q];            // P_c(i, t)
 };
 
-template <typename T, int Q, int KL, bool ADJ, bool EPI_M>
+template <typename T, int Q, int KL, bool ADJ, bool EPI_M, bool CS>
 __global__ void __launch_bounds__((1 << KL) * 64, 4) k_struct_fused(StructArgs<T, Q> a) {
     using C = cpx<T>;
     constexpr int P = 1 << KL;
@@ -430,7 +430,9 @@ __global__ void __launch_bounds__((1 << KL) * 64, 4) k_struct_fused(StructArgs<T
     }
     __syncthreads();
     const int grp = wave >> 1, h = wave & 1;
-    const bool cs = a.cside != 0;
+    // quadrant matrix M(r, t) = P_pc(r, t) (B side) or P_pc(t, r) (C side); the adjoint uses
+    // M^T, so the stored matrix is read transposed when ADJ != CS
+    constexpr bool TRANS = ADJ != CS;
 #pragma unroll
     for (int st = 0; st < KL; ++st) {
         const int j = ADJ ? KL - 1 - st : st;
@@ -450,7 +452,7 @@ __global__ void __launch_bounds__((1 << KL) * 64, 4) k_struct_fused(StructArgs<T
             const int srcp = ADJ ? (o ? lout0 + Gl : lout0) : lin0 + o;
             const C *ta = tw + cout * 4 * Q + cin * Q;          // a(c_out, c_in, .)
             const C *tb = tw + cout * 4 * Q + (2 + cin) * Q;    // b(c_out, c_in, .)
-            const int pc = cs ? cin : cout;
+            const T *Pm = &a.P[0][0][0] + (CS ? cin : cout) * Q * Q;
             C w[Q];
 #pragma unroll
             for (int t = 0; t < Q; ++t) {
@@ -467,8 +469,7 @@ __global__ void __launch_bounds__((1 << KL) * 64, 4) k_struct_fused(StructArgs<T
                 C v = czero<C>();
 #pragma unroll
                 for (int t = 0; t < Q; ++t) {
-                    // forward block quadrant M(r, t); the adjoint applies M^T
-                    const T m = ADJ ? (cs ? a.P[pc][r][t] : a.P[pc][t][r]) : (cs ? a.P[pc][t][r] : a.P[pc][r][t]);
+                    const T m = TRANS ? Pm[t * Q + r] : Pm[r * Q + t];
                     v.x = fma(m, w[t].x, v.x);
                     v.y = fma(m, w[t].y, v.y);
                 }
@@ -513,21 +514,29 @@ __global__ void __launch_bounds__((1 << KL) * 64, 4) k_struct_fused(StructArgs<T
     }
 }
 
+template <typename T, int Q, int KL, bool CS>
+static void launch_struct_cs(const StructArgs<T, Q> &sa, bool adj, bool epi, dim3 grid, dim3 block, hipStream_t s) {
+    if (adj) {
+        if (epi)
+            k_struct_fused<T, Q, KL, true, true, CS><<<grid, block, 0, s>>>(sa);
+        else
+            k_struct_fused<T, Q, KL, true, false, CS><<<grid, block, 0, s>>>(sa);
+    } else {
+        if (epi)
+            k_struct_fused<T, Q, KL, false, true, CS><<<grid, block, 0, s>>>(sa);
+        else
+            k_struct_fused<T, Q, KL, false, false, CS><<<grid, block, 0, s>>>(sa);
+    }
+}
+
 template <typename T, int Q, int KL>
 static void launch_struct(const StructArgs<T, Q> &sa, bool adj, bool epi, long N, hipStream_t s) {
     dim3 grid((unsigned)(N >> KL), (unsigned)((sa.nrhs + 63) / 64));
     dim3 block((1 << KL) * 64);
-    if (adj) {
-        if (epi)
-            k_struct_fused<T, Q, KL, true, true><<<grid, block, 0, s>>>(sa);
-        else
-            k_struct_fused<T, Q, KL, true, false><<<grid, block, 0, s>>>(sa);
-    } else {
-        if (epi)
-            k_struct_fused<T, Q, KL, false, true><<<grid, block, 0, s>>>(sa);
-        else
-            k_struct_fused<T, Q, KL, false, false><<<grid, block, 0, s>>>(sa);
-    }
+    if (sa.cside)
+        launch_struct_cs<T, Q, KL, true>(sa, adj, epi, grid, block, s);
+    else
+        launch_struct_cs<T, Q, KL, false>(sa, adj, epi, grid, block, s);
 }
 
 template <typename T, int Q>
