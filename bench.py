@@ -39,16 +39,42 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def pass_plan(n, kmax=3):
+    """Structured butterfly passes of one apply: (levels, applies M) per launch (see the design notes)."""
+    L = int(np.log2(n))
+    nl = max(L - 3, L // 2) - L // 2
+    plan = []
+    hi = nl
+    while hi > 0:                       # C side (or B* side) from the top, M on the last pass
+        lo = max(hi - kmax, 0)
+        plan.append((hi - lo, lo == 0))
+        hi = lo
+    lo = 0
+    while lo < nl:
+        hi = min(lo + kmax, nl)
+        plan.append((hi - lo, False))
+        lo = hi
+    return plan
+
+
 def kernel_model(name, n, q, k):
-    """Algorithmic (bytes, flops) of one launch of a BF level kernel (see the design notes)."""
+    """Average algorithmic (bytes, flops) per launch of the dominant kernel kinds.
+
+    bf_struct_*: one structured pass = read and write the N q k coefficients once, read the
+    8q twiddles of every group of each of its levels (and the q x q middle blocks when it applies
+    M); per group and column 4 quadrants of q complex scalings, a real q x q product and q complex
+    multiply-adds (6q + 4q^2 + 8q flops each), plus 8 q^2 flops per pair for M."""
     es = 16 if name.endswith("f64") else 8
+    if name.startswith("bf_struct"):
+        plan = pass_plan(n)
+        byts = flops = 0.0
+        for kl, epi in plan:
+            byts += 2 * n * q * k * es + kl * (n // 2) * 8 * q * es + (n * q * q * es if epi else 0)
+            flops += kl * (n // 2) * k * 4 * (14 * q + 4 * q * q) + (8.0 * n * q * q * k if epi else 0)
+        return byts / len(plan), flops / len(plan)
     if name.startswith("bf_transfer"):
         groups = n // 2
-        fac = groups * (2 * q) ** 2 * es
-        coef = 2 * n * q * k * es
-        return fac + coef, 8.0 * groups * (2 * q) ** 2 * k
-    if name.startswith("bf_middle"):
-        return n * q * q * es + 2 * n * q * k * es, 8.0 * n * q * q * k
+        return groups * (2 * q) ** 2 * es + 2 * n * q * k * es, 8.0 * groups * (2 * q) ** 2 * k
     return None
 
 
@@ -98,6 +124,69 @@ def synthetic_hss(n, leaf, r):
     return h
 
 
+def serving(F, torch, fi, duration, rate, seed=4, rel_res=5e-9):
+    """Serving workload: three resident operators N = 2^14, 2^16, 2^18 (same phase, q = 9, HSS
+    tolerance 1e-3), Poisson arrivals at `rate` requests/s for `duration` s, each request 1..32
+    right-hand sides (uniform) for an operator drawn uniformly; the mixed-precision refinement
+    with the step count calibrated per operator; batches of up to 64 columns on 2 streams,
+    replayed from captured hipGraphs.  Latency = completion - submission (host clock)."""
+    dev = torch.device("cuda")
+    ops = []
+    for e in (14, 16, 18):
+        n = 1 << e
+        B = F.BF(n, 9, 2.0 / 16, 1.0 / 16, precs=(F.FIO_PREC_FP64, F.FIO_PREC_FP32))
+        U = F.ULV(F.HSS.from_bf(B, tol=1e-3, p=10, seed=1003))
+        fpool = fi.rhs(seed + e, n, 32)
+        fd = torch.from_numpy(np.ascontiguousarray(fpool.T)).to(dev).t()
+        upool = B.apply(fd)
+        _, info = F.approx_solve(B, U, upool, mode=F.FIO_SOLVE_IR, prec=F.FIO_PREC_FP32, rel_res_tol=rel_res,
+                                 max_ir=6)
+        ops.append({"n": n, "B": B, "U": U, "u": upool, "f": fpool, "nir": max(1, info.ir_steps)})
+    srv = F.Server(max_batch_rhs=64, streams=2, use_graphs=True, width_bucket=16)
+    ids = [srv.add_operator(o["B"], o["U"], mode=F.FIO_SOLVE_IR, prec=F.FIO_PREC_FP32, max_ir=o["nir"])
+           for o in ops]
+    arr = fi.poisson_arrivals(seed, rate, duration)
+    ks = fi.integers(seed, fi.PURPOSE_DATA, 1, 32, len(arr))
+    which = fi.integers(seed + 1, fi.PURPOSE_DATA, 0, 2, len(arr))
+    # every request gets its own output block; inputs are column slices of the operator's pool
+    outs = [F.empty(ops[w]["n"], int(k)) for w, k in zip(which, ks)]
+    torch.cuda.synchronize()
+    # warm-up request per operator (captures happen at the first submission)
+    for i, o in enumerate(ops):
+        srv.submit(ids[i], o["u"][:, :1], F.empty(o["n"], 1))
+    srv.wait_all()
+    nwarm = len(ops)
+    t0 = srv.now()
+    rids = []
+    for t, w, k, out in zip(arr, which, ks, outs):
+        while srv.now() - t0 < t:
+            time.sleep(min(2e-4, max(0.0, t - (srv.now() - t0))))
+        rids.append(srv.submit(ids[w], ops[w]["u"][:, :int(k)], out))
+    srv.wait_all()
+    lat, first, last = [], None, 0.0
+    for r in rids:
+        i = srv.info(r)
+        lat.append((i["t_done"] - i["t_submit"]) * 1e3)
+        first = i["t_submit"] if first is None else min(first, i["t_submit"])
+        last = max(last, i["t_done"])
+    err = 0.0
+    for w, k, out in zip(which, ks, outs):
+        fh = out.cpu().numpy()
+        f = ops[w]["f"][:, :int(k)]
+        err = max(err, float((np.linalg.norm(fh - f, axis=0) / np.linalg.norm(f, axis=0)).max()))
+    st = srv.stats()
+    srv.close()
+    lat = np.array(lat)
+    return {"workload": "3 resident 1D FIOs N=2^14,2^16,2^18; Poisson %g req/s for %g s (seed %d); "
+                        "1-32 RHS per request; mixed refinement; 64-column batches, 2 streams, hipGraphs"
+                        % (rate, duration, seed),
+            "requests": len(rids), "rhs": int(np.sum(ks)), "rhs_per_s": float(np.sum(ks) / (last - first)),
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                           "mean": float(lat.mean()), "max": float(lat.max())},
+            "batches": st["batches"] - nwarm, "max_queue": st["max_queue"],
+            "max_col_rel_err": err, "ir_steps": [o["nir"] for o in ops]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +198,9 @@ def main():
     ap.add_argument("--hss-tol", type=float, default=1e-3)
     ap.add_argument("--rel-res", type=float, default=5e-9)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see the design notes on "
@@ -240,6 +332,14 @@ def main():
         roof.update({"kernel": dom, "avg_launch_ms": round(avg_ms, 4), "launches": cnt,
                      "algorithmic_bytes_per_launch": int(byts), "algorithmic_flops_per_launch": float(flops)})
 
+    serve = None
+    if not a.no_serve:
+        del B, H, U
+        torch.cuda.empty_cache()
+        log("serving workload")
+        serve = serving(F, torch, fi, a.serve_seconds, a.serve_rate)
+        log("serving", json.dumps(serve))
+
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(n, q, k, results["fp64"]["ir_steps"])
@@ -263,7 +363,7 @@ def main():
         "latency_ms": mixed["latency_ms"],
         "offline_s": {"bf": round(t_bf, 3), "hss": round(t_hss, 3), "ulv": round(t_ulv, 3)},
         "kernels_ms": {p: {kn: [c, round(m, 3)] for kn, (c, m) in d.items()} for p, d in kernel_stats.items()},
-        "roofline": roof, "cpu_baseline": cpu,
+        "serving": serve, "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 

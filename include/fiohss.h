@@ -241,6 +241,48 @@ fio_status fio_approx_solve(fio_bf_t bf, hss_ulv_t f, const void *U, long ldu, v
 const char *fio_status_str(fio_status s);
 
 /* ---------------------------------------------------------------------------
+ * Solve server (continuous batching).  Operators (a BF handle and the ULV
+ * factors of its HSS approximation) stay resident.  fio_server_submit queues a
+ * request (nrhs columns for one operator) and returns at once; a dispatcher
+ * thread forms a batch whenever one of `streams` slots is free: the oldest
+ * waiting request plus later requests for the same operator, in arrival order,
+ * while the batch has at most max_batch_rhs columns and the bytes of all
+ * batches in flight (solve workspace + batch input/output) stay within
+ * mem_budget (0: no budget).  The batch runs as one fio_approx_solve on the
+ * slot's stream (replayed from a captured hipGraph when use_graphs != 0);
+ * U must be complete (the work producing it finished) when it is submitted;
+ * batches on different slots overlap on the device.  Every column is solved
+ * independently, so with a fixed refinement step count (solve mode DIRECT, or
+ * IR with rel_res_tol <= 0, which add_operator requires) a request's result is
+ * bitwise the same alone and in any batch.  U must stay valid and F untouched
+ * until the request completes (fio_server_wait_all).  Times are seconds since
+ * fio_server_create.
+ * ------------------------------------------------------------------------- */
+typedef struct fio_server_s *fio_server_t;
+typedef struct {
+    int max_batch_rhs;     /* columns per batch */
+    int streams;           /* concurrent batch slots (1..8) */
+    size_t mem_budget;     /* bytes of batches in flight; 0 = unlimited */
+    int use_graphs;        /* replay captured hipGraphs per (operator, batch width) */
+    int width_bucket;      /* > 1: batch widths rounded up to a multiple (zero columns appended), and
+                              with use_graphs every (slot, operator, width) graph is captured when the
+                              first request arrives; <= 1: exact widths, graphs captured on first use */
+} fio_server_opts;
+
+fio_status fio_server_create(const fio_server_opts *opts, fio_server_t *out);
+fio_status fio_server_add_operator(fio_server_t s, fio_bf_t bf, hss_ulv_t f, const fio_solve_opts *opts,
+                                   int *op_id);
+fio_status fio_server_submit(fio_server_t s, int op_id, const void *U, long ldu, void *F, long ldf, int nrhs,
+                             long long *req_id);
+fio_status fio_server_wait_all(fio_server_t s);
+fio_status fio_server_request_info(fio_server_t s, long long req_id, double *t_submit, double *t_start,
+                                   double *t_done, int *batch, int *status);
+fio_status fio_server_stats(fio_server_t s, long *completed, long *batches, long *max_queue,
+                            size_t *peak_bytes);
+double fio_server_now(fio_server_t s);
+void fio_server_destroy(fio_server_t s);
+
+/* ---------------------------------------------------------------------------
  * Measurement hooks.  While enabled, the library brackets each of its hot
  * kernel launches (BF levels, ULV levels) with HIP events recorded on the
  * launch stream and accumulates the durations per kernel name

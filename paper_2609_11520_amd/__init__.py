@@ -341,3 +341,60 @@ def timing_names():
 def set_fused(on=True):
     """Fused multi-level butterfly passes (default) or one kernel per factor."""
     lib().fio_set_fused(1 if on else 0)
+
+
+class Server:
+    """Continuous-batching solve server (fio_server_* in the C ABI)."""
+
+    def __init__(self, max_batch_rhs=64, streams=2, mem_budget=0, use_graphs=True, width_bucket=16):
+        o = _lib.ServerOpts(max_batch_rhs, streams, mem_budget, 1 if use_graphs else 0, width_bucket)
+        h = C.c_void_p()
+        _lib.check(lib().fio_server_create(C.byref(o), C.byref(h)), "fio_server_create")
+        self.h = h
+        self._keep = []
+
+    def add_operator(self, bf, ulv, mode=FIO_SOLVE_IR, prec=FIO_PREC_FP32, max_ir=1):
+        o = _lib.SolveOpts(mode, prec, 0.0, max_ir)
+        op = C.c_int()
+        _lib.check(lib().fio_server_add_operator(self.h, bf.h, ulv.h, C.byref(o), C.byref(op)),
+                   "fio_server_add_operator")
+        self._keep.append((bf, ulv))
+        return op.value
+
+    def submit(self, op, U, F):
+        """Queues F <- solve(U); U and F are column-major (N, k) device tensors kept alive by the caller."""
+        U, ldu = colmajor(U)
+        F, ldf = colmajor(F)
+        rid = C.c_longlong()
+        _lib.check(lib().fio_server_submit(self.h, op, _ptr(U), ldu, _ptr(F), ldf, U.shape[1], C.byref(rid)),
+                   "fio_server_submit")
+        return rid.value
+
+    def wait_all(self):
+        _lib.check(lib().fio_server_wait_all(self.h), "fio_server_wait_all")
+
+    def info(self, rid):
+        ts, t0, td = C.c_double(), C.c_double(), C.c_double()
+        b, st = C.c_int(), C.c_int()
+        _lib.check(lib().fio_server_request_info(self.h, rid, C.byref(ts), C.byref(t0), C.byref(td), C.byref(b),
+                                                 C.byref(st)), "fio_server_request_info")
+        return {"t_submit": ts.value, "t_start": t0.value, "t_done": td.value, "batch": b.value, "status": st.value}
+
+    def stats(self):
+        c, b, q = C.c_long(), C.c_long(), C.c_long()
+        pk = C.c_size_t()
+        _lib.check(lib().fio_server_stats(self.h, C.byref(c), C.byref(b), C.byref(q), C.byref(pk)),
+                   "fio_server_stats")
+        return {"completed": c.value, "batches": b.value, "max_queue": q.value, "peak_bytes": pk.value}
+
+    def now(self):
+        return lib().fio_server_now(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fio_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        if _lib._lib is not None:
+            self.close()

@@ -34,6 +34,11 @@ class SolveOpts(C.Structure):
     _fields_ = [("mode", C.c_int), ("prec", C.c_int), ("rel_res_tol", C.c_double), ("max_ir", C.c_int)]
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("max_batch_rhs", C.c_int), ("streams", C.c_int), ("mem_budget", C.c_size_t),
+                ("use_graphs", C.c_int), ("width_bucket", C.c_int)]
+
+
 class SolveInfo(C.Structure):
     _fields_ = [("ir_steps", C.c_int), ("rel_res", C.c_double)]
 
@@ -69,6 +74,15 @@ PROTOS = {
     "fio_solve_workspace_size": (i32, [vp, vp, i32, C.POINTER(SolveOpts), C.POINTER(sz)]),
     "fio_approx_solve": (i32, [vp, vp, vp, lg, vp, lg, i32, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp, sz, vp]),
     "fio_status_str": (C.c_char_p, [i32]),
+    "fio_server_create": (i32, [C.POINTER(ServerOpts), C.POINTER(vp)]),
+    "fio_server_add_operator": (i32, [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(i32)]),
+    "fio_server_submit": (i32, [vp, i32, vp, lg, vp, lg, i32, C.POINTER(C.c_longlong)]),
+    "fio_server_wait_all": (i32, [vp]),
+    "fio_server_request_info": (i32, [vp, C.c_longlong, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double), C.POINTER(i32), C.POINTER(i32)]),
+    "fio_server_stats": (i32, [vp, C.POINTER(lg), C.POINTER(lg), C.POINTER(lg), C.POINTER(sz)]),
+    "fio_server_now": (C.c_double, [vp]),
+    "fio_server_destroy": (None, [vp]),
     "fio_timing_enable": (None, [i32]),
     "fio_timing_reset": (None, []),
     "fio_timing_query": (i32, [C.c_char_p, C.POINTER(lg), C.POINTER(C.c_double)]),
