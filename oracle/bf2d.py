@@ -1,0 +1,222 @@
+"""Butterfly factorization of a 2D discrete FIO without transfer levels, and its apply.
+
+Oracle (test infrastructure only).  Section 2.2, eq. (bf) and (bf_mid), with
+the quadtree of Section 2.2 in two dimensions, the outermost factors at level
+L' = max(L - 3, h) (implementation note of Section 5.3), and L = log2 n.
+
+Odd L (a reading; Section 2.2 assumes L even while Section 5.3 reports 2D runs
+with L = 7): the middle level is h = ceil(L/2) on both sides, lc = L - h.
+  U side: pairs (tau at spatial level h, sigma' at frequency level lc).
+  V side: pairs (tau' at spatial level lc, sigma at frequency level h).
+  M couples U pair (tau, sigma') with the V pairs (anc(tau), sigma) for the
+  4^(2h - L) frequency boxes sigma of level h inside sigma', through
+  k(Z_tau, Gamma_sigma); for even L that is the single block of eq. (bf_mid).
+Only L' = h is built (no B or C factor), which is the case for n <= 128 at the
+paper's level offset of 3.
+
+Boxes: spatial box (t1, t2) at level l is [t1 2^-l, (t1+1) 2^-l] x [..], frequency
+box (s1, s2) at level l is [-n/2 + s1 n 2^-l, ..] x [..]; Chebyshev grids are
+tensor products of the first-kind points of cheb.py, index i = i1 q + i2; the
+Lagrange basis is the product of the 1D bases.
+
+Factor entries (Section 2.2), y, eta box centers:
+  V_{tau',sigma}(i, xi) = exp(2 pi i (Phi(y_tau', xi) - Phi(y_tau', gamma_sigma,i))) q_sigma,i(xi)
+  M_{tau,sigma}(i, j)   = k(z_tau,i, gamma_sigma,j)
+  U_{tau,sigma'}(x, i)  = exp(2 pi i (Phi(x, eta_sigma') - Phi(z_tau,i, eta_sigma'))) p_tau,i(x)
+
+export_factors() writes them in the library's import layout (Morton box order,
+column-major blocks, see the header of the C interface).
+"""
+import numpy as np
+
+from . import cheb
+from .fio2d import phase, kernel, morton_code, morton_decode
+
+
+class BF2D:
+    def __init__(self, n, q, params, level_offset=3):
+        L = int(round(np.log2(n)))
+        if 2 ** L != n or L < 2:
+            raise ValueError("n must be 2^L, L >= 2")
+        self.n, self.N, self.L, self.q, self.params = n, n * n, L, q, params
+        self.h = (L + 1) // 2
+        self.lc = L - self.h
+        self.Lp = max(L - level_offset, self.h)
+        if self.Lp != self.h:
+            raise NotImplementedError("2D butterflies with transfer levels (L - offset > ceil(L/2))")
+        self.b = n >> self.h                  # points per leaf box and dimension
+        self.r = 2 ** (self.h - self.lc)      # frequency children of a level-lc box per dimension
+
+    # --- geometry --------------------------------------------------------------
+    def _s_cheb(self, level):
+        w = 2.0 ** (-level)
+        return cheb.cheb_points((np.arange(2 ** level) * w)[:, None], w, self.q)       # (box, q)
+
+    def _f_cheb(self, level):
+        w = self.n * 2.0 ** (-level)
+        return cheb.cheb_points((-self.n / 2 + np.arange(2 ** level) * w)[:, None], w, self.q)
+
+    def _s_center(self, level):
+        return (np.arange(2 ** level) + 0.5) * 2.0 ** (-level)
+
+    def _f_center(self, level):
+        w = self.n * 2.0 ** (-level)
+        return -self.n / 2 + (np.arange(2 ** level) + 0.5) * w
+
+    def _leaf_freqs(self):
+        """Frequencies of every level-h box per dimension: (2^h, b)."""
+        return (np.arange(self.n) - self.n // 2).astype(np.float64).reshape(2 ** self.h, self.b)
+
+    def _leaf_points(self):
+        return (np.arange(self.n) / self.n).reshape(2 ** self.h, self.b)
+
+    # --- factor blocks ------------------------------------------------------------
+    def V_blocks(self, t1, t2):
+        """V_{tau',sigma} for tau' = (t1, t2) at level lc and every sigma at level h:
+        array [s1, s2, i1, i2, a1, a2] (a = frequency offset inside sigma)."""
+        P = self.params
+        y = self._s_center(self.lc)
+        y1, y2 = y[t1], y[t2]
+        g = self._f_cheb(self.h)                       # (s, i)
+        xi = self._leaf_freqs()                        # (s, a)
+        Q = cheb.lagrange_values(g, xi)                # (s, a, i) = q_i(xi_a)
+        S = g.shape[0]
+        # phase at the frequencies and at the Chebyshev points of sigma
+        ph_xi = phase(y1, y2, xi[:, None, :, None], xi[None, :, None, :], P)        # (s1, s2, a1, a2)
+        ph_g = phase(y1, y2, g[:, None, :, None], g[None, :, None, :], P)           # (s1, s2, i1, i2)
+        lag = Q.transpose(0, 2, 1)[:, None, :, None, :, None] * Q.transpose(0, 2, 1)[None, :, None, :, None, :]
+        return (np.exp(2j * np.pi * (ph_xi[:, :, None, None, :, :] - ph_g[:, :, :, :, None, None]))
+                * lag.reshape(S, S, self.q, self.q, self.b, self.b))
+
+    def M_blocks(self, u1, u2):
+        """k(Z_tau, Gamma_sigma) for tau = (u1, u2) at level h and every sigma at level h:
+        array [s1, s2, i1, i2, j1, j2]."""
+        z = self._s_cheb(self.h)
+        g = self._f_cheb(self.h)
+        return kernel(z[u1][None, None, :, None, None, None], z[u2][None, None, None, :, None, None],
+                      g[:, None, None, None, :, None], g[None, :, None, None, None, :], self.params)
+
+    def U_blocks(self, u1, u2):
+        """U_{tau,sigma'} for tau = (u1, u2) at level h and every sigma' at level lc:
+        array [v1, v2, a1, a2, i1, i2] (a = point offset inside tau)."""
+        P = self.params
+        z = self._s_cheb(self.h)
+        x = self._leaf_points()
+        Pm = cheb.lagrange_values(z, x)                # (u, a, i) = p_i(x_a)
+        eta = self._f_center(self.lc)
+        z1, z2, x1, x2 = z[u1], z[u2], x[u1], x[u2]
+        ph_x = phase(x1[None, None, :, None], x2[None, None, None, :],
+                     eta[:, None, None, None], eta[None, :, None, None], P)           # (v1, v2, a1, a2)
+        ph_z = phase(z1[None, None, :, None], z2[None, None, None, :],
+                     eta[:, None, None, None], eta[None, :, None, None], P)           # (v1, v2, i1, i2)
+        lag = Pm[u1][:, None, :, None] * Pm[u2][None, :, None, :]                     # (a1, a2, i1, i2)
+        return (np.exp(2j * np.pi * (ph_x[:, :, :, :, None, None] - ph_z[:, :, None, None, :, :]))
+                * lag[None, None])
+
+    # --- apply (eq. bf: K~ = U M V) -----------------------------------------------
+    def apply(self, f):
+        """K~ f for f of shape (N,) or (N, k) in user order."""
+        f = np.asarray(f, np.complex128)
+        vec = f.ndim == 1
+        n, q, b, h, lc, r = self.n, self.q, self.b, self.h, self.lc, self.r
+        k = f.reshape(self.N, -1).shape[1]
+        F = f.reshape(2 ** h, b, 2 ** h, b, k)                       # [s1, a1, s2, a2, col]
+        S, T = 2 ** h, 2 ** lc
+        cV = np.empty((T, T, S, S, q, q, k), np.complex128)         # V side: (tau', sigma)
+        for t1 in range(T):
+            for t2 in range(T):
+                cV[t1, t2] = np.einsum('stijab,satbk->stijk', self.V_blocks(t1, t2), F, optimize=True)
+        cU = np.empty((S, S, T, T, q, q, k), np.complex128)         # U side: (tau, sigma')
+        for u1 in range(S):
+            for u2 in range(S):
+                W = np.einsum('stijlm,stlmk->stijk', self.M_blocks(u1, u2), cV[u1 // r, u2 // r], optimize=True)
+                cU[u1, u2] = W.reshape(T, r, T, r, q, q, k).sum(axis=(1, 3))
+        out = np.empty((S, b, S, b, k), np.complex128)
+        for u1 in range(S):
+            for u2 in range(S):
+                out[u1, :, u2, :] = np.einsum('vwabij,vwijk->abk', self.U_blocks(u1, u2), cU[u1, u2], optimize=True)
+        out = out.reshape(self.N, k)
+        return out[:, 0] if vec else out
+
+    def apply_adj(self, g):
+        """K~* g (reversed conjugate-transposed factors, Section 2.2)."""
+        g = np.asarray(g, np.complex128)
+        vec = g.ndim == 1
+        n, q, b, h, lc, r = self.n, self.q, self.b, self.h, self.lc, self.r
+        k = g.reshape(self.N, -1).shape[1]
+        G = g.reshape(2 ** h, b, 2 ** h, b, k)                       # [u1, a1, u2, a2, col]
+        S, T = 2 ** h, 2 ** lc
+        cU = np.empty((S, S, T, T, q, q, k), np.complex128)
+        for u1 in range(S):
+            for u2 in range(S):
+                cU[u1, u2] = np.einsum('vwabij,abk->vwijk', np.conj(self.U_blocks(u1, u2)), G[u1, :, u2, :],
+                                       optimize=True)
+        cV = np.zeros((T, T, S, S, q, q, k), np.complex128)
+        for u1 in range(S):
+            for u2 in range(S):
+                # coefficient of U pair (tau, parent(sigma)) for every sigma at level h
+                src = np.repeat(np.repeat(cU[u1, u2], r, axis=0), r, axis=1)          # (s1, s2, i, k)
+                cV[u1 // r, u2 // r] += np.einsum('stijlm,stijk->stlmk', np.conj(self.M_blocks(u1, u2)), src,
+                                                  optimize=True)
+        out = np.zeros((S, b, S, b, k), np.complex128)
+        for t1 in range(T):
+            for t2 in range(T):
+                out += np.einsum('stijab,stijk->satbk', np.conj(self.V_blocks(t1, t2)), cV[t1, t2], optimize=True)
+        out = out.reshape(self.N, k)
+        return out[:, 0] if vec else out
+
+    # --- rows of K~ f for sampled error estimates ------------------------------------
+    def apply_rows(self, f, boxes):
+        """(K~ f) at every point of the given level-h spatial boxes [(u1, u2), ...].
+        Returns (user indices, values)."""
+        f = np.asarray(f, np.complex128).reshape(self.N, -1)
+        n, q, b, h, lc, r = self.n, self.q, self.b, self.h, self.lc, self.r
+        k = f.shape[1]
+        F = f.reshape(2 ** h, b, 2 ** h, b, k)
+        T = 2 ** lc
+        idx, vals, cache = [], [], {}
+        for (u1, u2) in boxes:
+            t = (u1 // r, u2 // r)
+            if t not in cache:
+                cache[t] = np.einsum('stijab,satbk->stijk', self.V_blocks(*t), F, optimize=True)
+            W = np.einsum('stijlm,stlmk->stijk', self.M_blocks(u1, u2), cache[t], optimize=True)
+            cU = W.reshape(T, r, T, r, q, q, k).sum(axis=(1, 3))
+            vals.append(np.einsum('vwabij,vwijk->abk', self.U_blocks(u1, u2), cU, optimize=True).reshape(b * b, k))
+            a = np.arange(b)
+            idx.append(((u1 * b + a)[:, None] * n + (u2 * b + a)[None, :]).reshape(-1))
+        return np.concatenate(idx), np.concatenate(vals)
+
+    # --- explicit factors in the library's import layout ------------------------------
+    def export_factors(self):
+        """V, M, U as one complex128 vector (Morton box order, column-major blocks):
+        V: pair p = tau' * 4^h + sigma, block (q^2 x b^2), entry (i, s) at p*q^2*b^2 + s*q^2 + i
+        M: block m = tau * 4^h + sigma (both level h), entry (i, j) at m*q^4 + j*q^2 + i
+        U: pair p = tau * 4^lc + sigma', block (b^2 x q^2), entry (s, i) at p*q^2*b^2 + i*b^2 + s
+        with s the Morton index of the point inside its box and i = i1 q + i2."""
+        q, b, h, lc = self.q, self.b, self.h, self.lc
+        r2, b2 = q * q, b * b
+        S, T = 2 ** h, 2 ** lc
+        hb = int(round(np.log2(b)))
+        a1, a2 = morton_decode(np.arange(b2), hb)                    # local Morton -> (a1, a2)
+        V = np.empty((T * T, S * S, b2, r2), np.complex128)          # [tau', sigma, s, i]
+        M = np.empty((S * S, S * S, r2, r2), np.complex128)          # [tau, sigma, j, i]
+        U = np.empty((S * S, T * T, r2, b2), np.complex128)          # [tau, sigma', i, s]
+        sig1, sig2 = morton_decode(np.arange(S * S), h)
+        for tt in range(T * T):
+            t1, t2 = morton_decode(tt, lc)
+            Vb = self.V_blocks(int(t1), int(t2))                     # [s1, s2, i1, i2, a1, a2]
+            Vb = Vb[sig1, sig2][:, :, :, a1, a2]                     # [sigma, i1, i2, s]
+            V[tt] = Vb.reshape(S * S, r2, b2).transpose(0, 2, 1)
+        for uu in range(S * S):
+            u1, u2 = morton_decode(uu, h)
+            Mb = self.M_blocks(int(u1), int(u2))[sig1, sig2]         # [sigma, i1, i2, j1, j2]
+            M[uu] = Mb.reshape(S * S, r2, r2).transpose(0, 2, 1)
+            v1, v2 = morton_decode(np.arange(T * T), lc)
+            Ub = self.U_blocks(int(u1), int(u2))[v1, v2][:, a1, a2]  # [sigma', s, i1, i2]
+            U[uu] = Ub.reshape(T * T, b2, r2).transpose(0, 2, 1)
+        return np.concatenate([V.reshape(-1), M.reshape(-1), U.reshape(-1)])
+
+    def factor_count(self):
+        S, T = 4 ** self.h, 4 ** self.lc
+        r2, b2 = self.q ** 2, self.b ** 2
+        return T * S * r2 * b2 + S * S * r2 * r2 + S * T * r2 * b2

@@ -1,0 +1,117 @@
+"""Discrete 2D FIO: grids, phase, kernel, dense rows, index maps.
+
+Oracle (test infrastructure only).  Section 1, eq. (fio) and (fio_mat) in two
+dimensions with n points per dimension, N = n^2: X = {(i1/n, i2/n)},
+Xi = {(j1 - n/2, j2 - n/2)}, 0 <= i, j < n, K = exp(2 pi i Phi(x, xi)) (a = 1).
+
+User ordering (a reading; the paper defines only the sets): entry i1*n + i2 of a
+spatial vector is x = (i1/n, i2/n); entry j1*n + j2 of a frequency vector is
+xi = (j1 - n/2, j2 - n/2) ("lexicographic, first coordinate major").
+
+Phase family of Section 5.3 (constant amplitude):
+    Phi(x, xi) = x . xi + sqrt(c1(x)^2 xi1^2 + c2(x)^2 xi2^2),
+    c1(x) = a0 + a1 sin(2 pi x1) sin(2 pi x2),  c2(x) = a0 + a1 cos(2 pi x1) cos(2 pi x2),
+with (a0, a1) = (2/16, 1/16) for the paper's workload and (0, 0) for the plain
+2D DFT.
+
+Internal ordering (library-private, used by the HSS tree): Morton order, the
+bits of the first coordinate above those of the second at every level, so the
+points of every dyadic box are contiguous and the box index at level l is the
+Morton code of the box coordinates.
+"""
+import numpy as np
+
+PHASE2_DFT = (0.0, 0.0)
+PHASE2_ANISO16 = (2.0 / 16.0, 1.0 / 16.0)
+
+
+def spatial_grid(n):
+    """(x1, x2) of every spatial point in user order, each of shape (n*n,)."""
+    i = np.arange(n * n)
+    return (i // n) / n, (i % n) / n
+
+
+def frequency_grid(n):
+    j = np.arange(n * n)
+    return (j // n - n // 2).astype(np.float64), (j % n - n // 2).astype(np.float64)
+
+
+def coeffs(x1, x2, params):
+    a0, a1 = params
+    s1, s2 = np.sin(2 * np.pi * x1), np.sin(2 * np.pi * x2)
+    c1_, c2_ = np.cos(2 * np.pi * x1), np.cos(2 * np.pi * x2)
+    return a0 + a1 * s1 * s2, a0 + a1 * c1_ * c2_
+
+
+def phase(x1, x2, k1, k2, params):
+    """Phi(x, xi), broadcasting over all four arguments."""
+    x1, x2 = np.asarray(x1, np.float64), np.asarray(x2, np.float64)
+    k1, k2 = np.asarray(k1, np.float64), np.asarray(k2, np.float64)
+    c1, c2 = coeffs(x1, x2, params)
+    return x1 * k1 + x2 * k2 + np.sqrt(c1 * c1 * k1 * k1 + c2 * c2 * k2 * k2)
+
+
+def kernel(x1, x2, k1, k2, params):
+    return np.exp(2j * np.pi * phase(x1, x2, k1, k2, params))
+
+
+def dense_K(n, params):
+    x1, x2 = spatial_grid(n)
+    k1, k2 = frequency_grid(n)
+    return kernel(x1[:, None], x2[:, None], k1[None, :], k2[None, :], params)
+
+
+def dense_K_rows(n, rows, params):
+    x1, x2 = spatial_grid(n)
+    rows = np.asarray(rows)
+    k1, k2 = frequency_grid(n)
+    return kernel(x1[rows][:, None], x2[rows][:, None], k1[None, :], k2[None, :], params)
+
+
+def dft2_apply(f, n):
+    """Closed form for a0 = a1 = 0: K f = (-1)^(i1+i2) n^2 ifft2(f) (user order, f is (N,) or (N, k))."""
+    f = np.asarray(f, np.complex128)
+    F = f.reshape((n, n) + f.shape[1:])
+    i = np.arange(n)
+    sign = np.where((i[:, None] + i[None, :]) % 2 == 0, 1.0, -1.0)
+    sign = sign.reshape((n, n) + (1,) * (f.ndim - 1))
+    return (sign * n * n * np.fft.ifft2(F, axes=(0, 1))).reshape(f.shape)
+
+
+# --- index maps ---------------------------------------------------------------
+def morton_code(j1, j2, bits):
+    """Interleave the bits of (j1, j2); bit b of j1 goes to position 2b + 1, of j2 to 2b."""
+    j1, j2 = np.asarray(j1, np.int64), np.asarray(j2, np.int64)
+    m = np.zeros(np.broadcast(j1, j2).shape, np.int64)
+    for b in range(bits):
+        m |= ((j1 >> b) & 1) << (2 * b + 1)
+        m |= ((j2 >> b) & 1) << (2 * b)
+    return m
+
+
+def morton_decode(m, bits):
+    m = np.asarray(m, np.int64)
+    j1 = np.zeros_like(m)
+    j2 = np.zeros_like(m)
+    for b in range(bits):
+        j1 |= ((m >> (2 * b + 1)) & 1) << b
+        j2 |= ((m >> (2 * b)) & 1) << b
+    return j1, j2
+
+
+def lex_of_internal(n):
+    """lex_of_internal[m] = user index of the point with Morton code m."""
+    L = int(round(np.log2(n)))
+    j1, j2 = morton_decode(np.arange(n * n), L)
+    return j1 * n + j2
+
+
+def to_internal(v, n):
+    """User order -> Morton order along axis 0."""
+    return np.asarray(v)[lex_of_internal(n)]
+
+
+def to_user(v, n):
+    out = np.empty_like(np.asarray(v))
+    out[lex_of_internal(n)] = v
+    return out
