@@ -57,18 +57,32 @@ typedef struct hss_ulv_s *hss_ulv_t;
 /* ---------------------------------------------------------------------------
  * Butterfly factorization (Section 2.2, eq. bf):
  *   K~ = U^[L'] B^[L'] ... B^[h+1] M^[h] C^[h+1] ... C^[L'] V^[L'],
- * with N = 2^L (L even), h = L/2, L' = max(L - level_offset, h) (the outer
- * level of Section 5.2's implementation note), q first-kind Chebyshev points
- * per box on the closed box, and the 1D phase
- *   Phi(x, xi) = x xi + (c0 + c1 sin(2 pi x)) |xi|,  amplitude 1.
- * (c0, c1) = (0, 0) is the shifted DFT; (1/8, 1/16) is c(x) = (2 + sin 2 pi x)/16.
+ * with q first-kind Chebyshev points per box and dimension on the closed box,
+ * L' = max(L - level_offset, h) (the outer level of the implementation notes of
+ * Sections 5.2 and 5.3), amplitude 1, and
+ *
+ * dim = 1: N = n = 2^L points (L even), h = L/2, phase
+ *     Phi(x, xi) = x xi + (c0 + c1 sin(2 pi x)) |xi|;
+ *   (c0, c1) = (0, 0) is the shifted DFT; (1/8, 1/16) is c(x) = (2 + sin 2 pi x)/16.
+ *
+ * dim = 2: n = 2^L points per dimension, N = n^2, quadtrees in space and
+ *   frequency, h = ceil(L/2) (odd L: the U and V sides both stop at level h and
+ *   M couples each U pair with the 4 V pairs of its parent spatial box and the
+ *   frequency children of its box), phase of Section 5.3
+ *     Phi(x, xi) = x.xi + sqrt(c1(x)^2 xi1^2 + c2(x)^2 xi2^2),
+ *     c1(x) = c0 + c1 sin(2 pi x1) sin(2 pi x2),  c2(x) = c0 + c1 cos(2 pi x1) cos(2 pi x2);
+ *   (c0, c1) = (1/8, 1/16) is the paper's 2D workload, (0, 0) the 2D DFT.
+ *   Vectors are in the user order of the 2D grid: entry i1 n + i2 is
+ *   x = (i1/n, i2/n) or xi = (i1 - n/2, i2 - n/2).  Only L - level_offset <= h
+ *   is built (no B or C factor; n <= 128 at level_offset 3), leaf boxes of at most
+ *   128 points and q^2 <= 128: other descriptors return FIO_ERR_UNSUPPORTED.
  * ------------------------------------------------------------------------- */
 typedef struct {
-    int dim;                 /* 1 (the only dimension this build implements) */
-    long n;                  /* N = 2^L, L even, N >= 64 */
+    int dim;                 /* 1 or 2 */
+    long n;                  /* points per dimension: 2^L (1D: L even, n >= 64; 2D: 4 <= n <= 2^15) */
     double c0, c1;           /* phase parameters, see above */
-    int q;                   /* Chebyshev points per box (rank r = q), 2 <= q <= 16 */
-    int level_offset;        /* L' = max(L - level_offset, L/2); 3 gives leaf boxes of 8 points */
+    int q;                   /* Chebyshev points per box and dimension, 2 <= q <= 16 */
+    int level_offset;        /* L' = max(L - level_offset, h); 3 gives leaf boxes of 8 points per dimension */
     unsigned prec_mask;      /* bit p set: keep a copy of the factors in fio_prec p resident */
 } fio_bf_desc;
 
@@ -97,6 +111,17 @@ fio_status fio_bf_build(const fio_bf_desc *desc, void *stream, fio_bf_t *out);
  *   block row c_out q + i (output pair tau = 2 alpha + c_out), column c_in q + t (input pair
  *   beta = 2 sigma + c_in), entries as defined in Section 2.2 (eq. bf_left_func_low_rank and
  *   its frequency-side mirror).
+ * For dim = 2 the layout is V, M, U with column-major blocks:
+ *   V block p = tau' 4^h + sigma (tau' at spatial level L-h, sigma at frequency level h),
+ *     q^2 x b^2, entry (i, s) at p q^2 b^2 + s q^2 + i;
+ *   M block u 4^h + sigma (both at level h), q^2 x q^2, entry (i, j) at blk q^4 + j q^2 + i,
+ *     equal to k(z_u,i, gamma_sigma,j);
+ *   U block p = tau 4^(L-h) + sigma' (tau at spatial level h, sigma' at frequency level L-h),
+ *     b^2 x q^2, entry (s, i) at p q^2 b^2 + i b^2 + s;
+ * with b = n / 2^h, box indices the Morton codes of the box coordinates (bit k of
+ * the first coordinate at position 2k + 1, of the second at 2k), s the Morton
+ * code of a point inside its box and i = i1 q + i2.  The conjugate-transposed
+ * copies used by fio_bf_apply_adj are derived on the device.
  * Used to apply factors produced elsewhere (e.g. to test the apply kernels on
  * factors of a reference implementation).  Synchronous. */
 fio_status fio_bf_import(const fio_bf_desc *desc, const void *host_factors, size_t count,
@@ -122,6 +147,16 @@ fio_status fio_bf_apply_adj(fio_bf_t bf, const void *X, long ldx, void *Y, long 
                             fio_prec prec, void *ws, size_t ws_bytes, void *stream);
 
 void fio_bf_destroy(fio_bf_t bf);
+
+/* Index map of the 2D grids: reorders the rows of X (n^2 x nrhs, device) into Y
+ * between the user's lexicographic order (row i1 n + i2) and the Morton order
+ * (row = Morton code of (i1, i2), bit k of i1 at position 2k + 1), in which every
+ * dyadic box is a contiguous run of rows; the HSS representation of
+ * K~^* K~ built by fio_hss_build for dim = 2 uses the binary tree over this
+ * order.  to_internal != 0: Y[morton(i1, i2)] = X[i1 n + i2]; else the inverse.
+ * n a power of two <= 2^15; X and Y must not overlap. */
+fio_status fio_permute2d(long n, int to_internal, const void *X, long ldx, void *Y, long ldy, int nrhs,
+                         void *stream);
 
 /* Selects the apply kernels: on != 0 (default) runs consecutive transfer factors
  * as fused multi-level passes on closed sub-butterflies held in LDS, with the

@@ -114,55 +114,77 @@ class BF2D:
                 * lag[None, None])
 
     # --- apply (eq. bf: K~ = U M V) -----------------------------------------------
+    # Blocks are contracted with numpy's matmul over stacks of boxes; box indices are
+    # (index along the first dimension, index along the second) in row-major order.
+    def _Vmat(self, t1, t2):
+        """V_{tau',sigma} for all sigma as a stack (S^2, q^2, b^2)."""
+        S, q, b = 2 ** self.h, self.q, self.b
+        return self.V_blocks(t1, t2).reshape(S * S, q * q, b * b)
+
+    def _Mmat(self, u1, u2):
+        S, q = 2 ** self.h, self.q
+        return self.M_blocks(u1, u2).reshape(S * S, q * q, q * q)
+
+    def _Umat(self, u1, u2):
+        """[U_{tau,sigma'}]_{sigma'} side by side: (b^2, T^2 q^2)."""
+        T, q, b = 2 ** self.lc, self.q, self.b
+        return self.U_blocks(u1, u2).reshape(T * T, b * b, q * q).transpose(1, 0, 2).reshape(b * b, T * T * q * q)
+
+    def _group(self, W, k):
+        """Sum of per-sigma (level h) terms over the level-lc box containing sigma: (S^2, r, k) -> (T^2, r, k)."""
+        T, r = 2 ** self.lc, self.r
+        S = 2 ** self.h
+        return W.reshape(T, r, T, r, -1, k).sum(axis=(1, 3)).reshape(T * T, -1, k)
+
+    def _coef_V(self, t1, t2, Fb):
+        return np.matmul(self._Vmat(t1, t2), Fb)                              # (S^2, q^2, k)
+
+    def _coef_U(self, u1, u2, cVt, k):
+        return self._group(np.matmul(self._Mmat(u1, u2), cVt), k)             # (T^2, q^2, k)
+
+    def _boxes(self, v, k):
+        """User-order vector (N, k) -> per leaf box (S^2, b^2, k)."""
+        S, b = 2 ** self.h, self.b
+        return v.reshape(S, b, S, b, k).transpose(0, 2, 1, 3, 4).reshape(S * S, b * b, k)
+
+    def _unboxes(self, w, k):
+        S, b = 2 ** self.h, self.b
+        return w.reshape(S, S, b, b, k).transpose(0, 2, 1, 3, 4).reshape(self.N, k)
+
     def apply(self, f):
         """K~ f for f of shape (N,) or (N, k) in user order."""
         f = np.asarray(f, np.complex128)
         vec = f.ndim == 1
-        n, q, b, h, lc, r = self.n, self.q, self.b, self.h, self.lc, self.r
         k = f.reshape(self.N, -1).shape[1]
-        F = f.reshape(2 ** h, b, 2 ** h, b, k)                       # [s1, a1, s2, a2, col]
-        S, T = 2 ** h, 2 ** lc
-        cV = np.empty((T, T, S, S, q, q, k), np.complex128)         # V side: (tau', sigma)
-        for t1 in range(T):
-            for t2 in range(T):
-                cV[t1, t2] = np.einsum('stijab,satbk->stijk', self.V_blocks(t1, t2), F, optimize=True)
-        cU = np.empty((S, S, T, T, q, q, k), np.complex128)         # U side: (tau, sigma')
+        S, T, r = 2 ** self.h, 2 ** self.lc, self.r
+        Fb = self._boxes(f.reshape(self.N, k), k)
+        cV = {(t1, t2): self._coef_V(t1, t2, Fb) for t1 in range(T) for t2 in range(T)}
+        out = np.empty((S * S, self.b * self.b, k), np.complex128)
         for u1 in range(S):
             for u2 in range(S):
-                W = np.einsum('stijlm,stlmk->stijk', self.M_blocks(u1, u2), cV[u1 // r, u2 // r], optimize=True)
-                cU[u1, u2] = W.reshape(T, r, T, r, q, q, k).sum(axis=(1, 3))
-        out = np.empty((S, b, S, b, k), np.complex128)
-        for u1 in range(S):
-            for u2 in range(S):
-                out[u1, :, u2, :] = np.einsum('vwabij,vwijk->abk', self.U_blocks(u1, u2), cU[u1, u2], optimize=True)
-        out = out.reshape(self.N, k)
+                cU = self._coef_U(u1, u2, cV[(u1 // r, u2 // r)], k)
+                out[u1 * S + u2] = self._Umat(u1, u2) @ cU.reshape(-1, k)
+        out = self._unboxes(out, k)
         return out[:, 0] if vec else out
 
     def apply_adj(self, g):
         """K~* g (reversed conjugate-transposed factors, Section 2.2)."""
         g = np.asarray(g, np.complex128)
         vec = g.ndim == 1
-        n, q, b, h, lc, r = self.n, self.q, self.b, self.h, self.lc, self.r
         k = g.reshape(self.N, -1).shape[1]
-        G = g.reshape(2 ** h, b, 2 ** h, b, k)                       # [u1, a1, u2, a2, col]
-        S, T = 2 ** h, 2 ** lc
-        cU = np.empty((S, S, T, T, q, q, k), np.complex128)
+        S, T, r, q = 2 ** self.h, 2 ** self.lc, self.r, self.q
+        Gb = self._boxes(g.reshape(self.N, k), k)
+        cV = {(t1, t2): np.zeros((S * S, q * q, k), np.complex128) for t1 in range(T) for t2 in range(T)}
         for u1 in range(S):
             for u2 in range(S):
-                cU[u1, u2] = np.einsum('vwabij,abk->vwijk', np.conj(self.U_blocks(u1, u2)), G[u1, :, u2, :],
-                                       optimize=True)
-        cV = np.zeros((T, T, S, S, q, q, k), np.complex128)
-        for u1 in range(S):
-            for u2 in range(S):
-                # coefficient of U pair (tau, parent(sigma)) for every sigma at level h
-                src = np.repeat(np.repeat(cU[u1, u2], r, axis=0), r, axis=1)          # (s1, s2, i, k)
-                cV[u1 // r, u2 // r] += np.einsum('stijlm,stijk->stlmk', np.conj(self.M_blocks(u1, u2)), src,
-                                                  optimize=True)
-        out = np.zeros((S, b, S, b, k), np.complex128)
-        for t1 in range(T):
-            for t2 in range(T):
-                out += np.einsum('stijab,stijk->satbk', np.conj(self.V_blocks(t1, t2)), cV[t1, t2], optimize=True)
-        out = out.reshape(self.N, k)
+                cU = (self._Umat(u1, u2).conj().T @ Gb[u1 * S + u2]).reshape(T, 1, T, 1, q * q, k)
+                # the coefficient of U pair (tau, parent(sigma)) for every sigma at level h
+                src = np.broadcast_to(cU, (T, r, T, r, q * q, k)).reshape(S * S, q * q, k)
+                cV[(u1 // r, u2 // r)] += np.matmul(self._Mmat(u1, u2).conj().transpose(0, 2, 1), src)
+        out = np.zeros((S * S, self.b * self.b, k), np.complex128)
+        for (t1, t2), c in cV.items():
+            out += np.matmul(self._Vmat(t1, t2).conj().transpose(0, 2, 1), c)
+        out = self._unboxes(out, k)
         return out[:, 0] if vec else out
 
     # --- rows of K~ f for sampled error estimates ------------------------------------
@@ -170,18 +192,16 @@ class BF2D:
         """(K~ f) at every point of the given level-h spatial boxes [(u1, u2), ...].
         Returns (user indices, values)."""
         f = np.asarray(f, np.complex128).reshape(self.N, -1)
-        n, q, b, h, lc, r = self.n, self.q, self.b, self.h, self.lc, self.r
+        n, b, r = self.n, self.b, self.r
         k = f.shape[1]
-        F = f.reshape(2 ** h, b, 2 ** h, b, k)
-        T = 2 ** lc
+        Fb = self._boxes(f, k)
         idx, vals, cache = [], [], {}
         for (u1, u2) in boxes:
             t = (u1 // r, u2 // r)
             if t not in cache:
-                cache[t] = np.einsum('stijab,satbk->stijk', self.V_blocks(*t), F, optimize=True)
-            W = np.einsum('stijlm,stlmk->stijk', self.M_blocks(u1, u2), cache[t], optimize=True)
-            cU = W.reshape(T, r, T, r, q, q, k).sum(axis=(1, 3))
-            vals.append(np.einsum('vwabij,vwijk->abk', self.U_blocks(u1, u2), cU, optimize=True).reshape(b * b, k))
+                cache[t] = self._coef_V(t[0], t[1], Fb)
+            cU = self._coef_U(u1, u2, cache[t], k)
+            vals.append(self._Umat(u1, u2) @ cU.reshape(-1, k))
             a = np.arange(b)
             idx.append(((u1 * b + a)[:, None] * n + (u2 * b + a)[None, :]).reshape(-1))
         return np.concatenate(idx), np.concatenate(vals)

@@ -15,6 +15,34 @@ from . import ulv as ulv_mod
 from . import hss as hss_mod
 
 
+class MortonFrequencies:
+    """A 2D K~ whose frequency-side vectors are in Morton order (the order of the binary HSS
+    tree over 2D frequencies, a reading of Section 2.3's quadtree remark): apply takes and
+    apply_adj returns Morton-ordered vectors; spatial vectors stay in user order."""
+
+    def __init__(self, bf):
+        from . import fio2d
+        self.bf, self.N, self.n = bf, bf.N, bf.n
+        self._in, self._out = fio2d.to_user, fio2d.to_internal
+
+    def apply(self, X):
+        return self.bf.apply(self._in(X, self.n))
+
+    def apply_adj(self, Y):
+        return self._out(self.bf.apply_adj(Y), self.n)
+
+
+def build_hss_for_bf2d(bf, omega, tol, p=5, leaf=64, norm_est=None, rhat=None):
+    """HSS of G~ = K~^* K~ for a 2D K~, in the Morton order of the frequencies."""
+    return build_hss_for_bf(MortonFrequencies(bf), omega, tol, p=p, leaf=leaf, norm_est=norm_est, rhat=rhat)
+
+
+def direct_solve2d(bf, fac, u):
+    """f^ = F K~^* u for a 2D K~ and F factored in Morton order; f^ in user order."""
+    from . import fio2d
+    return fio2d.to_user(direct_solve(MortonFrequencies(bf), fac, u), bf.n)
+
+
 def build_hss_for_bf(bf, omega, tol, p=5, leaf=64, norm_est=None, rhat=None):
     """Algorithm alg:fio_inv, step 2: HSS of G~ = K~^* K~ from BF applies."""
     return hss_mod.build(bf.N, lambda X: bf.apply_adj(bf.apply(X)), omega, tol,

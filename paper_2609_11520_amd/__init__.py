@@ -64,15 +64,20 @@ def _workspace(nbytes):
 
 
 class BF:
-    """Butterfly factorization K~ of the 1D FIO Phi = x xi + (c0 + c1 sin 2 pi x)|xi| (Section 2.2)."""
+    """Butterfly factorization K~ (Section 2.2) of
+    dim 1: Phi = x xi + (c0 + c1 sin 2 pi x)|xi|, n points;
+    dim 2: Phi = x.xi + sqrt(c1(x)^2 xi1^2 + c2(x)^2 xi2^2) with c1 = c0 + c1 sin sin,
+           c2 = c0 + c1 cos cos (Section 5.3), n points per dimension, N = n^2."""
 
-    def __init__(self, n, q=9, c0=2.0 / 16, c1=1.0 / 16, level_offset=3, precs=(FIO_PREC_FP64,), factors=None):
+    def __init__(self, n, q=9, c0=2.0 / 16, c1=1.0 / 16, level_offset=3, precs=(FIO_PREC_FP64,), factors=None,
+                 dim=1):
         L = lib()
         mask = 0
         for p in precs:
             mask |= 1 << p
-        self.desc = _lib.BfDesc(1, n, c0, c1, q, level_offset, mask)
-        self.n, self.q = n, q
+        self.desc = _lib.BfDesc(dim, n, c0, c1, q, level_offset, mask)
+        self.dim, self.q = dim, q
+        self.n = n if dim == 1 else n * n          # vector length
         h = C.c_void_p()
         if factors is None:
             st = L.fio_bf_build(C.byref(self.desc), _stream(), C.byref(h))
@@ -117,9 +122,21 @@ class BF:
         return self._apply(lib().fio_bf_apply_adj, X, prec, out, ws)
 
     def __del__(self):
-        if getattr(self, "h", None) and _lib._lib is not None:
+        if getattr(self, "h", None) and _lib is not None and _lib._lib is not None:
             _lib._lib.fio_bf_destroy(self.h)
             self.h = None
+
+
+def permute2d(n, X, to_internal=True, out=None):
+    """Reorders the rows of X (n^2 x k) between the user's lexicographic order and the
+    library's Morton order of an n x n grid."""
+    X, ldx = colmajor(X)
+    k = X.shape[1]
+    Y = empty(n * n, k) if out is None else out
+    Y, ldy = colmajor(Y)
+    _lib.check(lib().fio_permute2d(n, 1 if to_internal else 0, _ptr(X), ldx, _ptr(Y), ldy, k, _stream()),
+               "fio_permute2d")
+    return Y
 
 
 class _DeviceView:
@@ -257,7 +274,7 @@ class HSS:
         return Y
 
     def __del__(self):
-        if getattr(self, "h", None) and _lib._lib is not None:
+        if getattr(self, "h", None) and _lib is not None and _lib._lib is not None:
             _lib._lib.hss_destroy(self.h)
             self.h = None
 
@@ -287,7 +304,7 @@ class ULV:
         return Cm
 
     def __del__(self):
-        if getattr(self, "h", None) and _lib._lib is not None:
+        if getattr(self, "h", None) and _lib is not None and _lib._lib is not None:
             _lib._lib.hss_ulv_destroy(self.h)
             self.h = None
 
@@ -396,5 +413,5 @@ class Server:
             self.h = None
 
     def __del__(self):
-        if _lib._lib is not None:
+        if _lib is not None and _lib._lib is not None:
             self.close()

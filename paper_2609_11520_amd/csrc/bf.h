@@ -4,8 +4,11 @@
 
 struct fio_bf_s {
     fio_bf_desc desc;
-    long N = 0;
+    int dim = 1;
+    long N = 0;                        // vector length (n in 1D, n^2 in 2D)
+    long n1 = 0;                       // points per dimension
     int L = 0, h = 0, Lp = 0, nl = 0, q = 0, b = 0, nsl = 0;
+    int lc = 0, hb = 0;                // 2D: coarse level L - h, log2 of the leaf box width
     // element offsets (complex entries) of each factor inside the packed arrays
     size_t offV = 0, offM = 0, offU = 0, total = 0;
     std::vector<size_t> offC, offB;   // offC[lev] = C^[h+1+lev], offB[lev] = B^[h+1+lev]
@@ -17,6 +20,7 @@ struct fio_bf_s {
     bool structured = false;
     fio::DevBuf tw64, tw32;
     double Pchild[2 * 16 * 16] = {};
+    fio::DevBuf adj64, adj32;          // 2D: conjugate-transposed factor copies read by the adjoint
     fio::DevBuf ws;                    // handle-owned workspace (ws == NULL in the applies)
     std::mutex ws_mu;
 };
@@ -26,8 +30,19 @@ namespace fio {
 fio_status bf_plan(const fio_bf_desc *d, fio_bf_s *bf);
 size_t bf_coef_elems(const fio_bf_s *bf, int nrhs);   // complex entries of one coefficient buffer
 // Internal apply used by the HSS construction and the solver (workspace given explicitly).
+// freq_internal (2D only): frequency-side vectors are in the library's Morton order instead of
+// the user's lexicographic order (the order of the HSS tree over frequencies).
 void bf_apply_impl(fio_bf_s *bf, bool adjoint, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs,
-                   fio_prec prec, void *ws, hipStream_t s);
+                   fio_prec prec, void *ws, hipStream_t s, bool freq_internal = false);
+// 2D butterflies (bf2d.hip)
+fio_status bf2d_plan(const fio_bf_desc *d, fio_bf_s *bf);
+size_t bf2d_ws_bytes(const fio_bf_s *bf, int nrhs, fio_prec prec);
+void bf2d_generate(fio_bf_s *bf, hipStream_t s);
+void bf2d_finish(fio_bf_s *bf, hipStream_t s);
+void bf2d_apply(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs, fio_prec prec,
+                void *ws, bool freq_internal, hipStream_t s);
+// permutation between user order and Morton order of a 2D grid (bf2d.hip)
+void permute2d(int n, bool to_internal, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs, hipStream_t s);
 size_t bf_ws_bytes(const fio_bf_s *bf, int nrhs, fio_prec prec);
 size_t bf_tw_off(const fio_bf_s *bf, bool cside, int lev);   // element offset of a level's twiddles
 }  // namespace fio

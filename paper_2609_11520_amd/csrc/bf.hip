@@ -18,6 +18,7 @@ namespace fio {
 // ---------------------------------------------------------------------------
 // geometry
 fio_status bf_plan(const fio_bf_desc *d, fio_bf_s *bf) {
+    if (d && d->dim == 2) return bf2d_plan(d, bf);
     if (!d || d->dim != 1) return d ? FIO_ERR_UNSUPPORTED : FIO_ERR_ARG;
     if (d->n < 64 || (d->n & (d->n - 1))) return FIO_ERR_ARG;
     int L = 0;
@@ -26,6 +27,7 @@ fio_status bf_plan(const fio_bf_desc *d, fio_bf_s *bf) {
     if (d->q < 2 || d->q > 16 || d->level_offset < 1) return FIO_ERR_ARG;
     bf->desc = *d;
     bf->N = d->n;
+    bf->n1 = d->n;
     bf->L = L;
     bf->h = L / 2;
     bf->Lp = (L - d->level_offset > bf->h) ? L - d->level_offset : bf->h;
@@ -306,6 +308,7 @@ __global__ void cvt_f64_f32(const double2 *in, float2 *out, size_t n) {
 }
 
 static void bf_generate(fio_bf_s *bf, hipStream_t s) {
+    if (bf->dim == 2) return bf2d_generate(bf, s);
     Geo g = geo_of(bf);
     double2 *base = bf->f64.as<double2>();
     const unsigned T = 256;
@@ -340,6 +343,7 @@ static void bf_generate(fio_bf_s *bf, hipStream_t s) {
 void bf_make_lowprec(fio_bf_s *bf, hipStream_t s);   // bf_lowprec.hip
 
 static void bf_make_copies(fio_bf_s *bf, hipStream_t s) {
+    if (bf->dim == 2) return bf2d_finish(bf, s);
     if (bf->desc.prec_mask & (1u << FIO_PREC_FP32)) {
         bf->f32.alloc(bf->total * sizeof(float2));
         cvt_f64_f32<<<grid1d(bf->total, 256), 256, 0, s>>>(bf->f64.as<double2>(), bf->f32.as<float2>(),
@@ -364,6 +368,7 @@ void bf_apply_split16(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double
 size_t bf_ws_bytes_split16(const fio_bf_s *bf, int nrhs);
 
 size_t bf_ws_bytes(const fio_bf_s *bf, int nrhs, fio_prec prec) {
+    if (bf->dim == 2) return bf2d_ws_bytes(bf, nrhs, prec);
     size_t e = bf_coef_elems(bf, nrhs);
     switch (prec) {
         case FIO_PREC_FP64: return 2 * e * sizeof(double2);
@@ -374,8 +379,12 @@ size_t bf_ws_bytes(const fio_bf_s *bf, int nrhs, fio_prec prec) {
 }
 
 void bf_apply_impl(fio_bf_s *bf, bool adjoint, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs,
-                   fio_prec prec, void *ws, hipStream_t s) {
+                   fio_prec prec, void *ws, hipStream_t s, bool freq_internal) {
     if (nrhs <= 0) return;
+    if (bf->dim == 2) {
+        if ((prec == FIO_PREC_FP32 && !bf->f32.p) || prec == FIO_PREC_SPLIT_FP16) throw Err{FIO_ERR_ARG};
+        return bf2d_apply(bf, adjoint, X, ldx, Y, ldy, nrhs, prec, ws, freq_internal, s);
+    }
     switch (prec) {
         case FIO_PREC_FP64:
             bf_apply_f64(bf, adjoint, X, ldx, Y, ldy, nrhs, bf->f64.as<double2>(), ws, s);

@@ -18,8 +18,12 @@
 
 namespace fio {
 
-constexpr int kMaxM = 1024;     // largest effective leaf size handled by the node kernel
-constexpr int kMaxNW = 2048;    // largest number of sample columns beyond m
+constexpr int kMaxM = 2048;     // largest effective leaf size handled by the node kernel
+constexpr int kMaxNW = 2304;    // largest number of sample columns beyond m
+
+// Node kernels run one workgroup per node; nodes of the upper levels of 2D trees are
+// large (hundreds to thousands of rows), so their workgroups get 16 waves instead of 4.
+inline unsigned node_threads(int m) { return m >= 192 ? 1024u : 256u; }
 
 // ---------------------------------------------------------------------------
 // workgroup helpers (blockDim.x == 256, four waves)
@@ -142,8 +146,8 @@ struct NodeArgs {
 };
 
 // Section 3.1 for one node (blockIdx.x), or the root solve of Section 3.2.
-__global__ void __launch_bounds__(256) k_node_step(NodeArgs a) {
-    __shared__ double sh[8];
+__global__ void __launch_bounds__(1024) k_node_step(NodeArgs a) {
+    __shared__ double sh[16];
     __shared__ double s_tau[kMaxM];
     __shared__ double s_tauw[kMaxM];
     __shared__ double s_nrm[kMaxNW];
@@ -346,7 +350,7 @@ struct PostArgs {
     size_t tstride;
 };
 
-__global__ void __launch_bounds__(256) k_post(PostArgs a) {
+__global__ void __launch_bounds__(1024) k_post(PostArgs a) {
     const int c = blockIdx.x, par = c >> 1, tid = threadIdx.x, nt = blockDim.x;
     const int mp = a.mpar[par], mc = a.mch[c], r = a.rch[c];
     const int r1 = a.rch[par * 2];
@@ -601,7 +605,7 @@ static fio_status build_impl(long n, const hss_opts *o, const Sampler &sm, hipSt
             na.Dres = Dres[l]->as<double2>();
             na.doff = ddo->as<size_t>();
             na.root = root ? 1 : 0;
-            k_node_step<<<nn, 256, 0, s>>>(na);
+            k_node_step<<<nn, node_threads(mmax), 0, s>>>(na);
             FIO_HIP(hipGetLastError());
             if (!root) {
                 h->rank[l].assign(nn, 0);
@@ -662,7 +666,9 @@ static fio_status build_impl(long n, const hss_opts *o, const Sampler &sm, hipSt
             pa.boff = d8->as<size_t>();
             pa.tmp = tmp.as<double2>();
             pa.tstride = tmax;
-            k_post<<<nc, 256, 0, s>>>(pa);
+            int mcmax = 0;
+            for (int c = 0; c < nc; ++c) mcmax = h->m[l + 1][c] > mcmax ? h->m[l + 1][c] : mcmax;
+            k_post<<<nc, node_threads(mcmax), 0, s>>>(pa);
             FIO_HIP(hipGetLastError());
             FIO_HIP(hipStreamSynchronize(s));
             for (DevBuf *d : {d1, d2, d3, d4, d5, d6, d7, d8}) delete d;
@@ -704,13 +710,21 @@ int bf_gram_matvec(void *ctx, const void *X, long ldx, void *Y, long ldy, int nc
     BfGram *g = static_cast<BfGram *>(ctx);
     fio_status st = guarded([&] {
         hipStream_t s = as_stream(stream);
-        size_t need = bf_ws_bytes(g->bf, ncols, FIO_PREC_FP64);
-        g->ws.ensure(need);
-        g->tmp.ensure((size_t)g->bf->N * ncols * sizeof(double2));
-        bf_apply_impl(g->bf, false, (const double2 *)X, ldx, g->tmp.as<double2>(), g->bf->N, ncols, FIO_PREC_FP64,
-                      g->ws.p, s);
-        bf_apply_impl(g->bf, true, g->tmp.as<double2>(), g->bf->N, (double2 *)Y, ldy, ncols, FIO_PREC_FP64, g->ws.p,
-                      s);
+        // 2D: the HSS tree runs over the Morton order of the frequencies, and the sample
+        // blocks are applied in chunks of 64 columns (the 2D coefficient buffers hold
+        // 81 N entries per column)
+        const bool fint = g->bf->dim == 2;
+        const int chunk = fint ? 64 : ncols;
+        const int c1 = ncols < chunk ? ncols : chunk;
+        g->ws.ensure(bf_ws_bytes(g->bf, c1, FIO_PREC_FP64));
+        g->tmp.ensure((size_t)g->bf->N * c1 * sizeof(double2));
+        for (int c0 = 0; c0 < ncols; c0 += chunk) {
+            const int nc = ncols - c0 < chunk ? ncols - c0 : chunk;
+            bf_apply_impl(g->bf, false, (const double2 *)X + (size_t)c0 * ldx, ldx, g->tmp.as<double2>(), g->bf->N,
+                          nc, FIO_PREC_FP64, g->ws.p, s, fint);
+            bf_apply_impl(g->bf, true, g->tmp.as<double2>(), g->bf->N, (double2 *)Y + (size_t)c0 * ldy, ldy, nc,
+                          FIO_PREC_FP64, g->ws.p, s, fint);
+        }
         return FIO_OK;
     });
     return st == FIO_OK ? 0 : 1;

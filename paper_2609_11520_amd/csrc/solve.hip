@@ -87,9 +87,17 @@ static fio_status solve_impl(fio_bf_s *bf, hss_ulv_s *f, const double2 *U, long 
     const fio_prec lp = (fio_prec)o->prec;
     const unsigned TB = 256;
     const size_t ne = (size_t)N * nrhs;
+    // 2D: the HSS factorization F lives in the Morton order of the frequencies, so K~^*
+    // writes that order and the solution is mapped back to the user's order
+    const bool d2 = bf->dim == 2;
     // f0 = F K~^*_prec u
-    bf_apply_impl(bf, true, U, ldu, w.t, N, nrhs, lp, w.bfws, s);
-    ulv_solve_impl(f, w.t, N, F, ldf, nrhs, w.ulvws, s);
+    bf_apply_impl(bf, true, U, ldu, w.t, N, nrhs, lp, w.bfws, s, d2);
+    if (d2) {
+        ulv_solve_impl(f, w.t, N, w.t, N, nrhs, w.ulvws, s);
+        permute2d((int)bf->n1, false, w.t, N, F, ldf, nrhs, s);
+    } else {
+        ulv_solve_impl(f, w.t, N, F, ldf, nrhs, w.ulvws, s);
+    }
     if (info) {
         info->ir_steps = 0;
         info->rel_res = -1.0;
@@ -121,9 +129,14 @@ static fio_status solve_impl(fio_bf_s *bf, hss_ulv_s *f, const double2 *U, long 
             if (step == o->max_ir) return FIO_ERR_NOT_CONVERGED;
         }
         // f += F K~^*_prec r
-        bf_apply_impl(bf, true, w.R, N, w.t, N, nrhs, lp, w.bfws, s);
+        bf_apply_impl(bf, true, w.R, N, w.t, N, nrhs, lp, w.bfws, s, d2);
         ulv_solve_impl(f, w.t, N, w.t, N, nrhs, w.ulvws, s);
-        k_axpy<<<grid1d(ne, TB), TB, 0, s>>>(F, ldf, w.t, N, N, nrhs);
+        if (d2) {
+            permute2d((int)bf->n1, false, w.t, N, w.R, N, nrhs, s);
+            k_axpy<<<grid1d(ne, TB), TB, 0, s>>>(F, ldf, w.R, N, N, nrhs);
+        } else {
+            k_axpy<<<grid1d(ne, TB), TB, 0, s>>>(F, ldf, w.t, N, N, nrhs);
+        }
         if (info && !measure) info->ir_steps = step + 1;
     }
     FIO_HIP(hipGetLastError());

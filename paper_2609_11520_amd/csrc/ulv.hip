@@ -34,6 +34,10 @@ struct hss_ulv_s {
 
 namespace fio {
 
+constexpr int kUlvMaxM = 2048;   // largest node size of the factorization
+// one workgroup per node; large nodes (upper levels of 2D trees) get 16 waves
+inline unsigned ulv_threads(int m) { return m >= 192 ? 1024u : 256u; }
+
 __device__ __forceinline__ double wsum(double v, double *sh) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -106,9 +110,9 @@ struct FactArgs {
 };
 
 // Basis elimination, partial Cholesky and the node's W (one workgroup per node).
-__global__ void __launch_bounds__(256) k_ulv_node(FactArgs a) {
-    __shared__ double sh[8];
-    __shared__ double s_tau[1024];
+__global__ void __launch_bounds__(1024) k_ulv_node(FactArgs a) {
+    __shared__ double sh[16];
+    __shared__ double s_tau[kUlvMaxM];
     __shared__ int s_flag;
     const int node = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
     const int m = a.msz[node], r = a.rsz[node], k = m - r;
@@ -279,7 +283,7 @@ struct MergeArgs {
     const size_t *toff;
 };
 
-__global__ void __launch_bounds__(256) k_ulv_merge(MergeArgs a) {
+__global__ void __launch_bounds__(1024) k_ulv_merge(MergeArgs a) {
     const int par = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
     const int c1 = 2 * par, c2 = 2 * par + 1;
     const int r1 = a.rch[c1], r2 = a.rch[c2], m = r1 + r2;
@@ -334,8 +338,8 @@ __global__ void __launch_bounds__(256) k_ulv_merge(MergeArgs a) {
 }
 
 // Root: Cholesky of D+ and the explicit inverse Linv of the lower factor.
-__global__ void __launch_bounds__(256) k_ulv_root(double2 *D, int m, double2 *Linv, int *fail) {
-    __shared__ double sh[8];
+__global__ void __launch_bounds__(1024) k_ulv_root(double2 *D, int m, double2 *Linv, int *fail) {
+    __shared__ double sh[16];
     __shared__ int s_flag;
     if (!wg_potrf(D, m, m, sh, &s_flag)) {
         if (threadIdx.x == 0) atomicAdd(fail, 1);
@@ -501,13 +505,15 @@ static fio_status factor_impl(hss_s *h, hipStream_t s, hss_ulv_t *out) {
             const int nn = h->nodes(l);
             std::vector<size_t> soff(nn), scoff(nn);
             size_t stot = 0, sctot = 0;
+            int mlev = 0;
             for (int j = 0; j < nn; ++j) {
                 int m = f->m[l][j];
+                mlev = m > mlev ? m : mlev;
                 soff[j] = stot;
                 stot += (size_t)m * m;
                 scoff[j] = sctot;
                 sctot += (size_t)3 * m * m;
-                if (m > 1024) throw Err{FIO_ERR_UNSUPPORTED};
+                if (m > kUlvMaxM) throw Err{FIO_ERR_UNSUPPORTED};
             }
             D22.alloc(stot * sizeof(double2) + 16);
             U2.alloc(stot * sizeof(double2) + 16);
@@ -534,7 +540,7 @@ static fio_status factor_impl(hss_s *h, hipStream_t s, hss_ulv_t *out) {
             fa.scratch = scr.as<double2>();
             fa.scoff = (const size_t *)(mb + o_sc);
             fa.fail = failb.as<int>();
-            k_ulv_node<<<nn, 256, 0, s>>>(fa);
+            k_ulv_node<<<nn, ulv_threads(mlev), 0, s>>>(fa);
             FIO_HIP(hipGetLastError());
             // merge into level l-1
             const int np = h->nodes(l - 1);
@@ -579,7 +585,7 @@ static fio_status factor_impl(hss_s *h, hipStream_t s, hss_ulv_t *out) {
             ma.uooff = (const size_t *)(m2 + q_uo);
             ma.tmp = tmp.as<double2>();
             ma.toff = (const size_t *)(m2 + q_t);
-            k_ulv_merge<<<np, 256, 0, s>>>(ma);
+            k_ulv_merge<<<np, ulv_threads(mlev), 0, s>>>(ma);
             FIO_HIP(hipGetLastError());
             FIO_HIP(hipStreamSynchronize(s));
             int fail = 0;
@@ -593,7 +599,7 @@ static fio_status factor_impl(hss_s *h, hipStream_t s, hss_ulv_t *out) {
             uin_off = uooff;
         }
         if (f->m0 > 0) {
-            k_ulv_root<<<1, 256, 0, s>>>(Dcur.as<double2>(), f->m0, f->Linv.as<double2>(), failb.as<int>());
+            k_ulv_root<<<1, ulv_threads(f->m0), 0, s>>>(Dcur.as<double2>(), f->m0, f->Linv.as<double2>(), failb.as<int>());
             FIO_HIP(hipGetLastError());
             FIO_HIP(hipStreamSynchronize(s));
             int fail = 0;
