@@ -222,6 +222,102 @@ def serving(F, torch, fi, duration, rate, seed=4, rel_res=5e-9):
             "max_col_rel_err": err, "ir_steps": [o["nir"] for o in ops]}
 
 
+def workload_2d(F, torch, fi, steps, warmup, rel_res=5e-9, solve=True):
+    """2D workload (Section 5.3 phase, a = 1): n = 128 per dimension (N = 16384, odd L), q = 9
+    (r = 81), 8 right-hand sides.  Times the BF applies (FP64 and FP32, forward and adjoint) with
+    per-kernel events, and, after the offline HSS (tolerance 1e-3, p = 10) and ULV construction,
+    the direct FP64 solve and the refinement to a relative residual of 5e-9 (FP64 and mixed)."""
+    n, k, q = 128, 8, 9
+    N = n * n
+    dev = torch.device("cuda")
+    t = time.perf_counter()
+    B = F.BF(n, q, 2.0 / 16, 1.0 / 16, precs=(F.FIO_PREC_FP64, F.FIO_PREC_FP32), dim=2)
+    torch.cuda.synchronize()
+    t_bf = time.perf_counter() - t
+    f_host = fi.rhs(1, N, k)
+    f = torch.from_numpy(np.ascontiguousarray(f_host.T)).to(dev).t()
+    out = F.empty(N, k)
+    ws = torch.empty(B.workspace_size(k, F.FIO_PREC_FP64), dtype=torch.uint8, device=dev)
+    applies, kstats = {}, {}
+    for prec, pn in ((F.FIO_PREC_FP64, "fp64"), (F.FIO_PREC_FP32, "fp32")):
+        for adj in (False, True):
+            fn = B.apply_adj if adj else B.apply
+            for _ in range(warmup):
+                fn(f, prec=prec, out=out, ws=ws)
+            torch.cuda.synchronize()
+            F.timing_reset()
+            F.timing_enable(True)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                fn(f, prec=prec, out=out, ws=ws)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            F.timing_enable(False)
+            key = "%s_%s" % (pn, "adj" if adj else "fwd")
+            applies[key] = {"ms": round(ms, 4), "rhs_per_s": k / (ms / 1e3)}
+            kstats[key] = {kn: F.timing_query(kn) for kn in F.timing_names()}
+    # roofline of the dominant 2D kernel: the FP64 middle factor, explicit q^2 x q^2 blocks streamed once
+    # per 8-column chunk, plus the coefficients in and out
+    L = 7
+    h = (L + 1) // 2
+    S = 4 ** h
+    nM = S * S * q ** 4
+    chunks = (k + 7) // 8
+    byts = nM * 16 * chunks + 2 * N * q * q * k * 16
+    flops = 8.0 * nM * k
+    cnt, tot = kstats["fp64_fwd"]["bf2_M_f64"]
+    avg = tot / cnt
+    roof = {"kernel": "bf2_M_f64", "bound": "hbm", "achieved": round(byts / (avg * 1e-3) / 1e9, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(byts / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "avg_launch_ms": round(avg, 4), "algorithmic_bytes_per_launch": int(byts),
+            "algorithmic_flops_per_launch": flops}
+    res = {"workload": "2D FIO n=128 (N=16384), Phi = x.xi + sqrt(c1^2 xi1^2 + c2^2 xi2^2) of Section 5.3, "
+                       "q=9, 8 RHS (seed 1)",
+           "bf_build_s": round(t_bf, 3), "apply": applies, "roofline_middle": roof,
+           "kernels_ms": {kk: {kn: [c, round(m, 3)] for kn, (c, m) in v.items()} for kk, v in kstats.items()}}
+    if solve:
+        t = time.perf_counter()
+        H = F.HSS.from_bf(B, tol=1e-3, p=10, seed=1003)
+        torch.cuda.synchronize()
+        t_hss = time.perf_counter() - t
+        t = time.perf_counter()
+        U = F.ULV(H)
+        torch.cuda.synchronize()
+        t_ulv = time.perf_counter() - t
+        u = B.apply(f)
+        sol = {}
+        fd = F.empty(N, k)
+        for _ in range(warmup):
+            F.approx_solve(B, U, u, out=fd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            F.approx_solve(B, U, u, out=fd)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        err = np.linalg.norm(fd.cpu().numpy() - f_host, axis=0) / np.linalg.norm(f_host, axis=0)
+        sol["direct_fp64"] = {"ms": round(ms, 3), "rhs_per_s": k / (ms / 1e3), "max_col_rel_err": float(err.max())}
+        for name, prec in (("fp64", F.FIO_PREC_FP64), ("mixed", F.FIO_PREC_FP32)):
+            _, info = F.approx_solve(B, U, u, mode=F.FIO_SOLVE_IR, prec=prec, rel_res_tol=rel_res, max_ir=10, out=fd)
+            nir = max(1, info.ir_steps)
+            kw = dict(mode=F.FIO_SOLVE_IR, prec=prec, rel_res_tol=0.0, max_ir=nir, out=fd)
+            for _ in range(warmup):
+                F.approx_solve(B, U, u, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                F.approx_solve(B, U, u, **kw)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            err = np.linalg.norm(fd.cpu().numpy() - f_host, axis=0) / np.linalg.norm(f_host, axis=0)
+            sol[name] = {"ms": round(ms, 3), "rhs_per_s": k / (ms / 1e3), "ir_steps": nir,
+                         "max_col_rel_err": float(err.max())}
+        res.update({"offline_s": {"hss": round(t_hss, 2), "ulv": round(t_ulv, 2)},
+                    "hss_max_rank_per_level": {str(l): int(max(v)) for l, v in H.ranks().items()},
+                    "solve": sol})
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,6 +332,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--no-2d", action="store_true", help="skip the 2D workload")
+    ap.add_argument("--no-2d-solve", action="store_true", help="2D: time the applies only")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see the design notes on "
@@ -376,6 +474,13 @@ def main():
         serve = serving(F, torch, fi, a.serve_seconds, a.serve_rate)
         log("serving", json.dumps(serve))
 
+    w2d = None
+    if not a.no_2d:
+        torch.cuda.empty_cache()
+        log("2D workload")
+        w2d = workload_2d(F, torch, fi, a.steps, a.warmup, solve=not a.no_2d_solve)
+        log("2d", json.dumps(w2d))
+
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(n, q, k, results["fp64"]["ir_steps"])
@@ -399,7 +504,7 @@ def main():
         "latency_ms": mixed["latency_ms"],
         "offline_s": {"bf": round(t_bf, 3), "hss": round(t_hss, 3), "ulv": round(t_ulv, 3)},
         "kernels_ms": {p: {kn: [c, round(m, 3)] for kn, (c, m) in d.items()} for p, d in kernel_stats.items()},
-        "serving": serve, "roofline": roof, "cpu_baseline": cpu,
+        "serving": serve, "workload_2d": w2d, "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 

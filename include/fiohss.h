@@ -248,8 +248,15 @@ void hss_ulv_destroy(hss_ulv_t f);
  *                R = U - K~ F (FP64), F += G~^{-1} K~^*_prec R, stopping when the
  *                largest column ratio ||R_j|| / ||U_j|| <= rel_res_tol
  *                (rel_res_tol <= 0: exactly max_ir steps, no host sync).
+ *   mode PCG:    conjugate gradients on K~^* K~ F = K~^* U (Section 4.1, eq.
+ *                fio_approx_normal_eq) preconditioned by G~^{-1}, from F = 0, each
+ *                column its own recurrence, every apply in FP64 (prec must be
+ *                FP64); at most max_ir iterations, stopping when the largest column
+ *                ratio ||B_j - K~^* K~ F_j|| / ||B_j|| <= rel_res_tol with B = K~^* U
+ *                (rel_res_tol <= 0: exactly max_ir iterations, no host sync).
+ *                FIO_ERR_NOT_CONVERGED when the limit is reached first.
  * ------------------------------------------------------------------------- */
-typedef enum { FIO_SOLVE_DIRECT = 0, FIO_SOLVE_IR = 1 } fio_solve_mode;
+typedef enum { FIO_SOLVE_DIRECT = 0, FIO_SOLVE_IR = 1, FIO_SOLVE_PCG = 2 } fio_solve_mode;
 
 typedef struct {
     int mode;             /* fio_solve_mode */
@@ -259,9 +266,9 @@ typedef struct {
 } fio_solve_opts;
 
 typedef struct {
-    int ir_steps;         /* refinement steps taken */
-    double rel_res;       /* largest column relative residual after the last step (IR with
-                             rel_res_tol > 0 only; -1 otherwise) */
+    int ir_steps;         /* refinement steps (IR) or iterations (PCG) taken */
+    double rel_res;       /* largest column relative residual after the last step (IR and PCG
+                             with rel_res_tol > 0 only; -1 otherwise) */
 } fio_solve_info;
 
 fio_status fio_solve_workspace_size(fio_bf_t bf, hss_ulv_t f, int nrhs, const fio_solve_opts *opts,

@@ -13,10 +13,10 @@ import numpy as np
 
 from . import _lib
 from ._lib import (FIO_PREC_FP64, FIO_PREC_FP32, FIO_PREC_SPLIT_FP16, FIO_SOLVE_DIRECT, FIO_SOLVE_IR,
-                   FioError)
+                   FIO_SOLVE_PCG, FioError)
 
 __all__ = ["BF", "HSS", "ULV", "approx_solve", "colmajor", "empty", "FIO_PREC_FP64", "FIO_PREC_FP32",
-           "FIO_PREC_SPLIT_FP16", "FIO_SOLVE_DIRECT", "FIO_SOLVE_IR", "FioError", "lib"]
+           "FIO_PREC_SPLIT_FP16", "FIO_SOLVE_DIRECT", "FIO_SOLVE_IR", "FIO_SOLVE_PCG", "FioError", "lib"]
 
 
 def lib():
@@ -318,7 +318,8 @@ def solve_workspace_size(bf, ulv, nrhs, mode=FIO_SOLVE_DIRECT, prec=FIO_PREC_FP6
 
 def approx_solve(bf, ulv, U, mode=FIO_SOLVE_DIRECT, prec=FIO_PREC_FP64, rel_res_tol=0.0, max_ir=0, out=None,
                  ws=None, info=None, raise_on_nonconv=True):
-    """F ~ K^{-1} U = G~^{-1} K~^* U (Section 4.1), optionally refined (mode IR)."""
+    """F ~ K^{-1} U = G~^{-1} K~^* U (Section 4.1), optionally refined (mode IR), or preconditioned CG on
+    the normal equation (mode PCG, max_ir = iteration limit)."""
     U, ldu = colmajor(U)
     k = U.shape[1]
     F = empty(bf.n, k) if out is None else out

@@ -8,7 +8,7 @@ LIB_PATH = os.path.join(HERE, "libfiohss.so")
 FIO_OK = 0
 FIO_WARN_RANK_CAP = 1
 FIO_PREC_FP64, FIO_PREC_FP32, FIO_PREC_SPLIT_FP16 = 0, 1, 2
-FIO_SOLVE_DIRECT, FIO_SOLVE_IR = 0, 1
+FIO_SOLVE_DIRECT, FIO_SOLVE_IR, FIO_SOLVE_PCG = 0, 1, 2
 
 STATUS = {0: "FIO_OK", -1: "FIO_ERR_ARG", -2: "FIO_ERR_OOM", -3: "FIO_ERR_HIP", -4: "FIO_ERR_NOT_HPD",
           -5: "FIO_ERR_NOT_CONVERGED", -6: "FIO_ERR_UNSUPPORTED", -7: "FIO_ERR_CALLBACK", 1: "FIO_WARN_RANK_CAP"}

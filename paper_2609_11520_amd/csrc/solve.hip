@@ -3,6 +3,7 @@
 #include "bf.h"
 
 #include <cmath>
+#include <vector>
 
 struct hss_ulv_s;
 
@@ -45,6 +46,77 @@ __global__ void k_colnorm2(const double2 *__restrict__ X, long ldx, long n, doub
     if (threadIdx.x == 0) out[j] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
+// out[j] = sum_i conj(A(i, j)) B(i, j), one workgroup of 256 per column (fixed reduction order)
+__global__ void k_coldot(const double2 *__restrict__ A, long lda, const double2 *__restrict__ B, long ldb, long n,
+                         double2 *out) {
+    __shared__ double shr[4], shi[4];
+    const int j = blockIdx.x;
+    double pr = 0.0, pi = 0.0;
+    for (long i = threadIdx.x; i < n; i += blockDim.x) {
+        const double2 a = A[i + (size_t)j * lda], b = B[i + (size_t)j * ldb];
+        pr += a.x * b.x + a.y * b.y;
+        pi += a.x * b.y - a.y * b.x;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        pr += __shfl_xor(pr, o);
+        pi += __shfl_xor(pi, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        shr[threadIdx.x >> 6] = pr;
+        shi[threadIdx.x >> 6] = pi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) out[j] = zc(shr[0] + shr[1] + shr[2] + shr[3], shi[0] + shi[1] + shi[2] + shi[3]);
+}
+
+__device__ __forceinline__ double2 zdiv(double2 a, double2 b) {
+    const double d = b.x * b.x + b.y * b.y;
+    return zc((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+// CG step: alpha_j = rz_j / pAp_j; X += alpha P; R -= alpha AP (column j of each block)
+__global__ void k_cg_step(double2 *__restrict__ X, long ldx, double2 *__restrict__ R, const double2 *__restrict__ P,
+                          const double2 *__restrict__ AP, long ld, long n, int nrhs, const double2 *__restrict__ rz,
+                          const double2 *__restrict__ pap) {
+    size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (id >= (size_t)n * nrhs) return;
+    const long i = id % n;
+    const int j = id / n;
+    const double2 al = zdiv(rz[j], pap[j]);
+    const size_t e = i + (size_t)j * ld;
+    const double2 pv = P[e], av = AP[e];
+    double2 &x = X[i + (size_t)j * ldx];
+    x = zc(x.x + al.x * pv.x - al.y * pv.y, x.y + al.x * pv.y + al.y * pv.x);
+    double2 &r = R[e];
+    r = zc(r.x - (al.x * av.x - al.y * av.y), r.y - (al.x * av.y + al.y * av.x));
+}
+
+// direction update: beta_j = rz_new_j / rz_j; P = Z + beta P
+__global__ void k_cg_dir(double2 *__restrict__ P, const double2 *__restrict__ Z, long ld, long n, int nrhs,
+                         const double2 *__restrict__ rz_new, const double2 *__restrict__ rz) {
+    size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (id >= (size_t)n * nrhs) return;
+    const long i = id % n;
+    const int j = id / n;
+    const double2 be = zdiv(rz_new[j], rz[j]);
+    const size_t e = i + (size_t)j * ld;
+    const double2 pv = P[e], zv = Z[e];
+    P[e] = zc(zv.x + be.x * pv.x - be.y * pv.y, zv.y + be.x * pv.y + be.y * pv.x);
+}
+
+__global__ void k_zero(double2 *__restrict__ X, long ldx, long n, int nrhs) {
+    size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (id >= (size_t)n * nrhs) return;
+    X[id % n + (size_t)(id / n) * ldx] = zc(0.0, 0.0);
+}
+
+__global__ void k_copy(double2 *__restrict__ Y, const double2 *__restrict__ X, long ld, long n, int nrhs) {
+    size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (id >= (size_t)n * nrhs) return;
+    const size_t e = id % n + (size_t)(id / n) * ld;
+    Y[e] = X[e];
+}
+
 struct SolveWs {
     double2 *t, *R;
     void *bfws, *ulvws;
@@ -53,7 +125,14 @@ struct SolveWs {
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+static size_t pcg_ws_bytes(fio_bf_s *bf, hss_ulv_s *f, int nrhs) {
+    const size_t blk = align256((size_t)bf->N * nrhs * sizeof(double2));
+    return 5 * blk + align256(bf_ws_bytes(bf, nrhs, FIO_PREC_FP64)) + align256(ulv_ws_bytes_pub(f, nrhs)) +
+           align256(3 * nrhs * sizeof(double2)) + align256(2 * nrhs * sizeof(double)) + 256;
+}
+
 static size_t solve_ws_bytes(fio_bf_s *bf, hss_ulv_s *f, int nrhs, const fio_solve_opts *o) {
+    if (o->mode == FIO_SOLVE_PCG) return pcg_ws_bytes(bf, f, nrhs);
     size_t blk = align256((size_t)bf->N * nrhs * sizeof(double2));
     size_t bfw = bf_ws_bytes(bf, nrhs, (fio_prec)o->prec);
     size_t b64 = bf_ws_bytes(bf, nrhs, FIO_PREC_FP64);
@@ -80,8 +159,82 @@ static SolveWs carve(fio_bf_s *bf, hss_ulv_s *f, int nrhs, const fio_solve_opts 
     return w;
 }
 
+// Preconditioned CG on the normal equation K~^* K~ f = K~^* u (Section 4.1, eq.
+// fio_approx_normal_eq) with G~^{-1} (the ULV solve) as the preconditioner, from f = 0,
+// every right-hand side its own recurrence; all applies in FP64.  2D: the iteration runs
+// in the Morton order of the frequencies (the order of G~) and the result is mapped back.
+static fio_status pcg_impl(fio_bf_s *bf, hss_ulv_s *f, const double2 *U, long ldu, double2 *F, long ldf, int nrhs,
+                           const fio_solve_opts *o, fio_solve_info *info, void *ws, hipStream_t s) {
+    const long N = bf->N;
+    const bool d2 = bf->dim == 2;
+    const size_t blk = align256((size_t)N * nrhs * sizeof(double2));
+    char *q = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+    double2 *R = (double2 *)q, *Z = (double2 *)(q + blk), *P = (double2 *)(q + 2 * blk),
+            *AP = (double2 *)(q + 3 * blk), *XT = (double2 *)(q + 4 * blk);
+    q += 5 * blk;
+    void *bfws = q;
+    q += align256(bf_ws_bytes(bf, nrhs, FIO_PREC_FP64));
+    void *ulvws = q;
+    q += align256(ulv_ws_bytes_pub(f, nrhs));
+    double2 *rz[2] = {(double2 *)q, (double2 *)q + nrhs};
+    double2 *pap = (double2 *)q + 2 * nrhs;
+    q += align256(3 * nrhs * sizeof(double2));
+    double *nrm = (double *)q;             // [0, nrhs): ||r_j||^2, [nrhs, 2 nrhs): ||b_j||^2
+    const unsigned TB = 256;
+    const size_t ne = (size_t)N * nrhs;
+    const unsigned g = grid1d(ne, TB);
+    double2 *X = d2 ? XT : F;
+    const long ldxx = d2 ? N : ldf;
+    const bool measure = o->rel_res_tol > 0.0;
+    std::vector<double> hn(2 * nrhs);
+    if (info) {
+        info->ir_steps = 0;
+        info->rel_res = -1.0;
+    }
+    // r = b = K~^* u, x = 0, z = G~^{-1} r, p = z
+    bf_apply_impl(bf, true, U, ldu, R, N, nrhs, FIO_PREC_FP64, bfws, s, d2);
+    if (measure) k_colnorm2<<<nrhs, 256, 0, s>>>(R, N, N, nrm + nrhs);
+    k_zero<<<g, TB, 0, s>>>(X, ldxx, N, nrhs);
+    ulv_solve_impl(f, R, N, Z, N, nrhs, ulvws, s);
+    k_coldot<<<nrhs, 256, 0, s>>>(R, N, Z, N, N, rz[0]);
+    k_copy<<<g, TB, 0, s>>>(P, Z, N, N, nrhs);
+    int cur = 0;
+    fio_status st = FIO_OK;
+    for (int it = 1; it <= o->max_ir; ++it) {
+        // A p = K~^* (K~ p), K~ p staged in Z
+        bf_apply_impl(bf, false, P, N, Z, N, nrhs, FIO_PREC_FP64, bfws, s, d2);
+        bf_apply_impl(bf, true, Z, N, AP, N, nrhs, FIO_PREC_FP64, bfws, s, d2);
+        k_coldot<<<nrhs, 256, 0, s>>>(P, N, AP, N, N, pap);
+        k_cg_step<<<g, TB, 0, s>>>(X, ldxx, R, P, AP, N, N, nrhs, rz[cur], pap);
+        if (info) info->ir_steps = it;
+        if (measure) {
+            k_colnorm2<<<nrhs, 256, 0, s>>>(R, N, N, nrm);
+            FIO_HIP(hipMemcpyAsync(hn.data(), nrm, 2 * nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+            FIO_HIP(hipStreamSynchronize(s));
+            double worst = 0.0;
+            for (int j = 0; j < nrhs; ++j) {
+                const double den = hn[nrhs + j] > 0.0 ? hn[nrhs + j] : 1.0;
+                const double v = std::sqrt(hn[j] / den);
+                worst = v > worst ? v : worst;
+            }
+            if (info) info->rel_res = worst;
+            if (worst <= o->rel_res_tol) break;
+            if (it == o->max_ir) st = FIO_ERR_NOT_CONVERGED;
+        }
+        if (it == o->max_ir) break;
+        ulv_solve_impl(f, R, N, Z, N, nrhs, ulvws, s);
+        k_coldot<<<nrhs, 256, 0, s>>>(R, N, Z, N, N, rz[1 - cur]);
+        k_cg_dir<<<g, TB, 0, s>>>(P, Z, N, N, nrhs, rz[1 - cur], rz[cur]);
+        cur = 1 - cur;
+    }
+    if (d2) permute2d((int)bf->n1, false, XT, N, F, ldf, nrhs, s);
+    FIO_HIP(hipGetLastError());
+    return st;
+}
+
 static fio_status solve_impl(fio_bf_s *bf, hss_ulv_s *f, const double2 *U, long ldu, double2 *F, long ldf, int nrhs,
                              const fio_solve_opts *o, fio_solve_info *info, void *ws, hipStream_t s) {
+    if (o->mode == FIO_SOLVE_PCG) return pcg_impl(bf, f, U, ldu, F, ldf, nrhs, o, info, ws, s);
     SolveWs w = carve(bf, f, nrhs, o, ws);
     const long N = bf->N;
     const fio_prec lp = (fio_prec)o->prec;
@@ -162,7 +315,8 @@ extern "C" fio_status fio_approx_solve(fio_bf_t bf, hss_ulv_t f, const void *U, 
     FIO_CHECK_ARG(bf && f && opts && nrhs >= 0);
     if (nrhs == 0) return FIO_OK;
     FIO_CHECK_ARG(U && F && U != F && ldu >= bf->N && ldf >= bf->N);
-    FIO_CHECK_ARG(opts->mode == FIO_SOLVE_DIRECT || opts->mode == FIO_SOLVE_IR);
+    FIO_CHECK_ARG(opts->mode == FIO_SOLVE_DIRECT || opts->mode == FIO_SOLVE_IR || opts->mode == FIO_SOLVE_PCG);
+    FIO_CHECK_ARG(opts->mode != FIO_SOLVE_PCG || opts->prec == FIO_PREC_FP64);
     FIO_CHECK_ARG(opts->prec >= FIO_PREC_FP64 && opts->prec <= FIO_PREC_SPLIT_FP16);
     FIO_CHECK_ARG(opts->max_ir >= 0);
     if (opts->prec == FIO_PREC_FP32 && !bf->f32.p) return FIO_ERR_ARG;

@@ -178,3 +178,25 @@ def test_full_size_solve_refines_to_1e8():
     fr, info = F.approx_solve(B, U, u, mode=F.FIO_SOLVE_IR, prec=1, rel_res_tol=1e-10, max_ir=20)
     assert osolve.col_rel_err(host(fr), f) < 1e-8
     step("2D n=128 e_direct %.2e, %d refinement steps" % (e_direct, info.ir_steps))
+
+
+def test_pcg_2d_matches_oracle():
+    F = fiohss()
+    n = 16
+    step("2D PCG n=%d" % n)
+    h, fac = oracle_hss2(n, 1e-3, 10, 1002)
+    B = gpu_bf2(F, n, 9, "aniso16", imported=True)
+    H = F.HSS.from_bf(B, tol=1e-3, p=10, omega=F.omega_from(omega_np(1002)))
+    U = F.ULV(H)
+    ob = oracle_bf2(n, 9, "aniso16")
+    f = fi.rhs(5, n * n, 2)
+    u = ob.apply(f)
+    fh, info = F.approx_solve(B, U, dev(u), mode=F.FIO_SOLVE_PCG, rel_res_tol=0.0, max_ir=2)
+    got = host(fh)
+    mf = osolve.MortonFrequencies(ob)
+    for j in range(2):
+        ref, _ = osolve.pcg(mf, fac, u[:, j], tol=0.0, maxit=2)
+        assert rel(got[:, j], of2.to_user(ref, n)) < 1e-12
+    fh, info = F.approx_solve(B, U, dev(u), mode=F.FIO_SOLVE_PCG, rel_res_tol=1e-12, max_ir=50)
+    assert info.ir_steps <= 10
+    assert osolve.col_rel_err(host(fh), f) < 1e-10

@@ -59,3 +59,26 @@ def test_end_to_end_all_gpu_built():
     u = B.apply(dev(f))
     fh, info = F.approx_solve(B, U, u, mode=F.FIO_SOLVE_IR, rel_res_tol=1e-12, max_ir=6)
     assert osolve.col_rel_err(host(fh), f) < 1e-10
+
+
+def test_pcg_matches_oracle_and_converges():
+    """Preconditioned CG on the normal equation (Section 4.1), the paper's iterative solver."""
+    F = fiohss()
+    step("PCG fixed iterations vs oracle")
+    B, U, ob, fac = setup_imported(F)
+    f = fi.rhs(3, 1024, 3)
+    u = ob.apply(f)
+    fh, info = F.approx_solve(B, U, dev(u), mode=F.FIO_SOLVE_PCG, rel_res_tol=0.0, max_ir=3)
+    assert info.ir_steps == 3
+    got = host(fh)
+    for j in range(3):
+        ref, it = osolve.pcg(ob, fac, u[:, j], tol=0.0, maxit=3)
+        assert it == 3
+        assert rel(got[:, j], ref) < 1e-12
+    step("PCG to 1e-12")
+    fh, info = F.approx_solve(B, U, dev(u), mode=F.FIO_SOLVE_PCG, rel_res_tol=1e-12, max_ir=50)
+    # the paper's preconditioned iteration counts are 4-6 (tables of Section 5)
+    assert 2 <= info.ir_steps <= 8 and info.rel_res <= 1e-12
+    assert osolve.col_rel_err(host(fh), f) < 1e-10
+    with pytest.raises(F.FioError):
+        F.approx_solve(B, U, dev(u), mode=F.FIO_SOLVE_PCG, prec=1, rel_res_tol=1e-12, max_ir=5)
