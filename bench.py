@@ -333,6 +333,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D workload")
+    ap.add_argument("--only-2d", action="store_true", help="run the 2D workload alone (for profiling)")
     ap.add_argument("--no-2d-solve", action="store_true", help="2D: time the applies only")
     a = ap.parse_args()
     if a.gpus != 1:
@@ -355,6 +356,10 @@ def main():
 
     log("device", torch.cuda.get_device_name(0))
     copy_calibration(torch)
+    if a.only_2d:
+        w2d = workload_2d(F, torch, fi, a.steps, a.warmup, solve=not a.no_2d_solve)
+        print(json.dumps({"workload_2d": w2d}), flush=True)
+        return
     t = time.perf_counter()
     B = F.BF(n, q, 2.0 / 16, 1.0 / 16, precs=(F.FIO_PREC_FP64, F.FIO_PREC_FP32))
     sync()

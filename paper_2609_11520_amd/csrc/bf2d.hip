@@ -357,6 +357,50 @@ __global__ void __launch_bounds__(128) k2_step(K2Args<T> a) {
     }
 }
 
+// VF / UA: the input is the user vector on one leaf box (b^2 points, gathered through the
+// index map), shared by G consecutive output pairs of the workgroup: it is staged once in
+// LDS and read back as wave-uniform broadcasts, while the G factor blocks stream from HBM.
+//   VF: box sigma, outputs (tau' = t0 + g) * S + sigma;  UA: box tau, outputs tau * T + v0 + g.
+template <typename T, int KC, int STEP, int G>
+__global__ void __launch_bounds__(128) k2_leaf_in(K2Args<T> a) {
+    using C = cpx<T>;
+    const G2 &g = a.g;
+    constexpr int MAXB2 = 128;
+    __shared__ C xs[MAXB2 * KC];
+    const int R = g.q2, CC = g.b2;
+    const int r = threadIdx.x;
+    const long groups = g.T / G;
+    const long box = blockIdx.x / groups;
+    const long first = (blockIdx.x % groups) * G;
+    const int c0 = blockIdx.z * KC;
+    const int nc = min(KC, a.nrhs - c0);
+    const bool internal = STEP == VF && a.fint;
+    for (int e = threadIdx.x; e < CC * KC; e += blockDim.x) {
+        const int j = e / KC, c = e % KC;
+        const long m = box * g.b2 + j;
+        const long row = internal ? m : lex_of(m, g.L, g.n);
+        xs[e] = c < nc ? to_c<C>(a.X[row + (size_t)(c0 + c) * a.ldx]) : czero<C>();
+    }
+    __syncthreads();
+    if (r >= R) return;
+    for (int gg = 0; gg < G; ++gg) {
+        const long o = STEP == VF ? (first + gg) * g.S + box : box * g.T + first + gg;
+        const C *Ab = a.A + (size_t)o * R * CC + r;
+        C acc[KC];
+#pragma unroll
+        for (int c = 0; c < KC; ++c) acc[c] = czero<C>();
+#pragma unroll 4
+        for (int j = 0; j < CC; ++j) {
+            const C av = Ab[(size_t)j * R];
+#pragma unroll
+            for (int c = 0; c < KC; ++c) cfma(acc[c], av, xs[j * KC + c]);
+        }
+        C *cp = a.cout + ((size_t)o * g.q2 + r) * a.ldc + c0;
+#pragma unroll
+        for (int c = 0; c < KC; ++c) cp[c] = acc[c];
+    }
+}
+
 // fixed-order sum of the split partials, scattered to the user vector
 template <typename T>
 __global__ void k2_reduce(G2 g, const cpx<T> *part, int nsplit, long nout, int ldc, int nrhs, int frequency,
@@ -389,6 +433,16 @@ constexpr int KC2 = 8;
 
 int nsplit_of(long nb) { return (int)(nb < 16 ? nb : 16); }
 
+// output pairs per workgroup of the leaf-input steps: 8 when the box has that many partners
+template <typename T, int STEP>
+void launch_leaf_in(const K2Args<T> &a, const G2 &g, unsigned chunks, unsigned blk, hipStream_t s) {
+    const unsigned nbox = (unsigned)g.S;
+    if (g.T >= 8)
+        k2_leaf_in<T, KC2, STEP, 8><<<dim3(nbox * (unsigned)(g.T / 8), 1, chunks), blk, 0, s>>>(a);
+    else
+        k2_leaf_in<T, KC2, STEP, 1><<<dim3(nbox * (unsigned)g.T, 1, chunks), blk, 0, s>>>(a);
+}
+
 template <typename T>
 void apply2(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs, const cpx<T> *F,
             const cpx<T> *Fa, void *ws, bool fint, hipStream_t s) {
@@ -415,7 +469,7 @@ void apply2(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long
             FIO_TIMED(f64 ? "bf2_V_f64" : "bf2_V_f32", s);
             K2Args<T> v = a;
             v.A = V; v.X = X; v.ldx = ldx; v.cout = c1; v.nb = 1; v.nsplit = 1;
-            k2_step<T, KC2, VF><<<dim3((unsigned)NP, 1, chunks), blkq, 0, s>>>(v);
+            launch_leaf_in<T, VF>(v, g, chunks, blkq, s);
         }
         {
             FIO_TIMED(f64 ? "bf2_M_f64" : "bf2_M_f32", s);
@@ -439,7 +493,7 @@ void apply2(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long
             FIO_TIMED(f64 ? "bf2_U_f64" : "bf2_U_f32", s);
             K2Args<T> u = a;
             u.A = Ua; u.X = X; u.ldx = ldx; u.cout = c2; u.nb = 1; u.nsplit = 1;
-            k2_step<T, KC2, UA><<<dim3((unsigned)NP, 1, chunks), blkq, 0, s>>>(u);
+            launch_leaf_in<T, UA>(u, g, chunks, blkq, s);
         }
         {
             FIO_TIMED(f64 ? "bf2_M_f64" : "bf2_M_f32", s);
