@@ -448,6 +448,27 @@ def main():
     ms_direct = (time.perf_counter() - t0) * 1e3 / a.steps
     err_d = float((np.linalg.norm(out.cpu().numpy() - f_host, axis=0) / np.linalg.norm(f_host, axis=0)).max())
 
+    # the paper's iterative solver (Sec. 4.1, Sec. 5): CG on the normal equation preconditioned by F,
+    # to a relative residual of 1e-12; residual-checked, then with the iteration count fixed
+    pcg = {}
+    wsp = torch.empty(F.solve_workspace_size(B, U, k, F.FIO_SOLVE_PCG, F.FIO_PREC_FP64, 1e-12, 30),
+                      dtype=torch.uint8, device=dev)
+    for label, tol in (("residual_checked", 1e-12), ("fixed_iterations", 0.0)):
+        kwp = dict(mode=F.FIO_SOLVE_PCG, prec=F.FIO_PREC_FP64, rel_res_tol=tol,
+                   max_ir=30 if tol > 0 else pcg["residual_checked"]["iterations"], out=out, ws=wsp)
+        for _ in range(a.warmup):
+            _, info = F.approx_solve(B, U, u, **kwp)
+        sync()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            _, info = F.approx_solve(B, U, u, **kwp)
+        sync()
+        ms = (time.perf_counter() - t0) * 1e3 / a.steps
+        e = float((np.linalg.norm(out.cpu().numpy() - f_host, axis=0) / np.linalg.norm(f_host, axis=0)).max())
+        pcg[label] = {"value": k / (ms / 1e3), "ms_per_step": round(ms, 3), "iterations": int(info.ir_steps),
+                      "rel_res": info.rel_res, "max_col_rel_err": e}
+    log("pcg", json.dumps(pcg))
+
     # roofline of the dominant kernel of the headline (mixed) path
     ks = kernel_stats["mixed"]
     dom = max(ks, key=lambda kn: ks[kn][1])
@@ -506,6 +527,7 @@ def main():
         "mixed": mixed, "fp64": results["fp64"],
         "direct_fp64": {"ms_per_step": round(ms_direct, 3), "value": k / (ms_direct / 1e3),
                         "max_col_rel_err": err_d},
+        "pcg_fp64": pcg,
         "latency_ms": mixed["latency_ms"],
         "offline_s": {"bf": round(t_bf, 3), "hss": round(t_hss, 3), "ulv": round(t_ulv, 3)},
         "kernels_ms": {p: {kn: [c, round(m, 3)] for kn, (c, m) in d.items()} for p, d in kernel_stats.items()},
