@@ -145,8 +145,15 @@ struct NodeArgs {
     int root;              // 1: only H0 = Y Omega^+ (made Hermitian) into Dres
 };
 
-// Section 3.1 for one node (blockIdx.x), or the root solve of Section 3.2.
-__global__ void __launch_bounds__(1024) k_node_step(NodeArgs a) {
+// Section 3.1 for one node (blockIdx.x), or the root solve of Section 3.2, in two phases
+// around the dense products of D-breve, which run as batched GEMMs over the level:
+//   k_node_basis: null space of Omega_tau (QR of Omega_tau^*), W = Y_tau Gamma (QRCP, rank,
+//            U_tau), T = Y_tau Omega_tau^+ = Z1 R^{-*}; at the root H0 = (T + T^*)/2 and done;
+//   (batched GEMMs: X = T - U U^* T, then D-breve = X + U (X U)^*, in place in T)
+//   k_node_finish: out = (D-breve + D-breve^*)/2 and U_tau to its slot.
+// Scratch of a node (leading dimensions m): A (s x m), Z (m x s, T = its first m columns),
+// U (m x m slot), P (m x m slot), X (m x m slot).
+__global__ void __launch_bounds__(1024) k_node_basis(NodeArgs a) {
     __shared__ double sh[16];
     __shared__ double s_tau[kMaxM];
     __shared__ double s_tauw[kMaxM];
@@ -163,10 +170,7 @@ __global__ void __launch_bounds__(1024) k_node_step(NodeArgs a) {
     }
     double2 *A = a.scratch + a.stride * node;       // s x m : Omega_tau^*, then reflectors / R
     double2 *Z = A + (size_t)s * m;                  // m x s : Y_tau Q
-    double2 *U = Z + (size_t)m * s;                  // m x m
-    double2 *P = U + (size_t)m * m;                  // m x m
-    double2 *X = P + (size_t)m * m;                  // m x m
-    double2 *Dt = X + (size_t)m * m;                 // m x m
+    double2 *U = Z + (size_t)m * s;                  // m x m slot (first r columns used)
     const double2 *Om = a.Om + a.moff[node];
     const double2 *Yt = a.Y + a.moff[node];
     for (int e = tid; e < s * m; e += nt) {
@@ -277,57 +281,43 @@ __global__ void __launch_bounds__(1024) k_node_step(NodeArgs a) {
             double2 x = T[i + (size_t)j * m], y = T[j + (size_t)i * m];
             out[e] = zc(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
         }
-        return;
     }
-    // P = U^* T (r x m)
-    for (int e = tid; e < r * m; e += nt) {
-        int aa = e % r, c = e / r;
-        double2 acc = zc(0.0, 0.0);
-        for (int i = 0; i < m; ++i) cfmac(acc, U[i + (size_t)aa * m], T[i + (size_t)c * m]);
-        P[aa + (size_t)c * m] = acc;
-    }
-    __syncthreads();
-    // X = T - U P
-    for (int e = tid; e < m * m; e += nt) {
-        int i = e % m, c = e / m;
-        double2 acc = T[i + (size_t)c * m];
-        for (int aa = 0; aa < r; ++aa) {
-            double2 t = cmul(U[i + (size_t)aa * m], P[aa + (size_t)c * m]);
-            acc = csub(acc, t);
-        }
-        X[e] = acc;
-    }
-    __syncthreads();
-    // P = U^* X^*  (r x m): P(a, c) = sum_i conj(U(i, a)) conj(X(c, i))
-    for (int e = tid; e < r * m; e += nt) {
-        int aa = e % r, c = e / r;
-        double2 acc = zc(0.0, 0.0);
-        for (int i = 0; i < m; ++i) {
-            double2 u = U[i + (size_t)aa * m], x = X[c + (size_t)i * m];
-            // conj(u) conj(x) = conj(u x)
-            double2 t = cmul(u, x);
-            acc.x += t.x;
-            acc.y -= t.y;
-        }
-        P[aa + (size_t)c * m] = acc;
-    }
-    __syncthreads();
-    // Dt = X + U P
-    for (int e = tid; e < m * m; e += nt) {
-        int i = e % m, c = e / m;
-        double2 acc = X[e];
-        for (int aa = 0; aa < r; ++aa) cfma(acc, U[i + (size_t)aa * m], P[aa + (size_t)c * m]);
-        Dt[e] = acc;
-    }
-    __syncthreads();
+}
+
+__global__ void __launch_bounds__(1024) k_node_finish(NodeArgs a) {
+    const int node = blockIdx.x;
+    const int m = a.msz[node], s = a.s;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (m == 0) return;
+    const int r = a.rank_out[node];
+    double2 *out = a.Dres + a.doff[node];
+    const double2 *Z = a.scratch + a.stride * node + (size_t)s * m;   // D-breve in Z[:, 0:m]
+    const double2 *U = Z + (size_t)m * s;
     for (int e = tid; e < m * m; e += nt) {
         int i = e % m, j = e / m;
-        double2 x = Dt[i + (size_t)j * m], y = Dt[j + (size_t)i * m];
+        double2 x = Z[i + (size_t)j * m], y = Z[j + (size_t)i * m];
         out[e] = zc(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
     }
     double2 *Uo = a.Uslot + a.uoff[node];
     for (int e = tid; e < m * r; e += nt) Uo[e] = U[e];
 }
+
+// P(a, c) = conj(Y(c, a)) for a < r, c < m, Y = X U in the X slot, P in the P slot of each node
+__global__ void k_node_conj_transpose(NodeArgs a) {
+    const int node = blockIdx.y;
+    const int m = a.msz[node], s = a.s;
+    if (m == 0) return;
+    const int r = a.rank_out[node];
+    const double2 *Z = a.scratch + a.stride * node + (size_t)s * m;
+    double2 *P = const_cast<double2 *>(Z) + (size_t)m * s + (size_t)m * m;
+    const double2 *Y = P + (size_t)m * m;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)r * m; e += (long)gridDim.x * blockDim.x) {
+        const int aa = (int)(e % r), c = (int)(e / r);
+        const double2 y = Y[c + (size_t)aa * m];
+        P[aa + (size_t)c * m] = zc(y.x, -y.y);
+    }
+}
+
 
 // Section 3.3 for the two children of every node of level l (one workgroup per child c):
 //   A = the child's diagonal block of D^[l]_parent; B_{a2,a1} = A_21 (written by the first child);
@@ -582,7 +572,7 @@ static fio_status build_impl(long n, const hss_opts *o, const Sampler &sm, hipSt
                 g = sqrt(ny) / sqrt(no);
             }
             // per-node algebra
-            size_t stride = (size_t)2 * sl * mmax + (size_t)5 * mmax * mmax;
+            size_t stride = (size_t)2 * sl * mmax + (size_t)3 * mmax * mmax;
             scratch.ensure(stride * nn * sizeof(double2));
             std::vector<size_t> uo(nn, 0);
             if (!root) uo = h->uoff[l];
@@ -605,11 +595,42 @@ static fio_status build_impl(long n, const hss_opts *o, const Sampler &sm, hipSt
             na.Dres = Dres[l]->as<double2>();
             na.doff = ddo->as<size_t>();
             na.root = root ? 1 : 0;
-            k_node_step<<<nn, node_threads(mmax), 0, s>>>(na);
+            k_node_basis<<<nn, node_threads(mmax), 0, s>>>(na);
             FIO_HIP(hipGetLastError());
             if (!root) {
                 h->rank[l].assign(nn, 0);
                 FIO_HIP(hipMemcpyAsync(h->rank[l].data(), rk.p, nn * sizeof(int), hipMemcpyDeviceToHost, s));
+                FIO_HIP(hipStreamSynchronize(s));
+                // D-breve = X + U (X U)^*, X = T - U (U^* T), for all nodes of the level
+                ZgemmBatch g1, g2, g3, g4;
+                double2 *sc = scratch.as<double2>();
+                int rmax = 0;
+                for (int j = 0; j < nn; ++j) {
+                    const int m = ms[j], r = h->rank[l][j];
+                    if (m == 0) continue;
+                    rmax = r > rmax ? r : rmax;
+                    double2 *T = sc + stride * j + (size_t)sl * m;
+                    double2 *U = T + (size_t)m * sl, *P = U + (size_t)m * m, *X = P + (size_t)m * m;
+                    g1.add(U, m, T, m, P, m, r, m, m);        // P = U^* T      (r x m)
+                    g2.add(U, m, P, m, T, m, m, m, r);        // T -= U P       (X, m x m)
+                    g3.add(T, m, U, m, X, m, m, r, m);        // X slot = X U   (m x r)
+                    g4.add(U, m, P, m, T, m, m, m, r);        // T += U (X U)^* (D-breve)
+                }
+                g1.upload(s);
+                g2.upload(s);
+                g3.upload(s);
+                g4.upload(s);
+                g1.run(true, zc(1.0, 0.0), zc(0.0, 0.0), s);
+                g2.run(false, zc(-1.0, 0.0), zc(1.0, 0.0), s);
+                g3.run(false, zc(1.0, 0.0), zc(0.0, 0.0), s);
+                if (rmax > 0) {
+                    dim3 gct((unsigned)((rmax * (size_t)mmax + 255) / 256), (unsigned)nn);
+                    k_node_conj_transpose<<<gct, 256, 0, s>>>(na);
+                }
+                g4.run(false, zc(1.0, 0.0), zc(1.0, 0.0), s);
+                k_node_finish<<<nn, node_threads(mmax), 0, s>>>(na);
+                FIO_HIP(hipGetLastError());
+                FIO_HIP(hipStreamSynchronize(s));   // the descriptor lists are released here
             }
             FIO_HIP(hipStreamSynchronize(s));
             delete dmo;

@@ -109,7 +109,12 @@ struct FactArgs {
     int *fail;
 };
 
-// Basis elimination, partial Cholesky and the node's W (one workgroup per node).
+// Basis elimination, partial Cholesky and the node's W (one workgroup per node), in two
+// phases around the two dense products Dchk = Q^* D Q, which run as batched GEMMs over
+// all nodes of the level:
+//   PHASE 0: QL of U_tau (Householder), explicit Q, the reduced basis U2;
+//   PHASE 1: Cholesky of Dchk11, Dhat21, Dhat22 and W = [L11^{-1} Q1^*; Q2^* - Dhat21 L11^{-1} Q1^*].
+template <int PHASE>
 __global__ void __launch_bounds__(1024) k_ulv_node(FactArgs a) {
     __shared__ double sh[16];
     __shared__ double s_tau[kUlvMaxM];
@@ -122,87 +127,74 @@ __global__ void __launch_bounds__(1024) k_ulv_node(FactArgs a) {
     double2 *T = Q + (size_t)m * m;                  // m x m: Q^* D, then Dchk
     const double2 *Uin = a.U + a.uoff[node];
     const double2 *Din = a.D + a.doff[node];
-    for (int e = tid; e < m * r; e += nt) Uw[e] = Uin[e];
-    __syncthreads();
-    // QL: for column jj = r-1..0 eliminate rows 0..p-1 (p = k + jj) into row p
-    for (int jj = r - 1; jj >= 0; --jj) {
-        const int p = k + jj, n = p + 1;
-        double2 *x = Uw + (size_t)jj * m;            // rows 0..p
-        const double2 al = x[p];
-        double part = 0.0;
-        for (int i = tid; i < n; i += nt) part += x[i].x * x[i].x + x[i].y * x[i].y;
-        const double sigma = sqrt(wsum(part, sh));
-        double tau = 0.0;
-        if (sigma > 0.0) {
-            const double aa = sqrt(al.x * al.x + al.y * al.y);
-            double2 ph = aa > 0.0 ? zc(al.x / aa, al.y / aa) : zc(1.0, 0.0);
-            double2 beta = zc(-ph.x * sigma, -ph.y * sigma);
-            double2 den = csub(al, beta);
-            double dn = den.x * den.x + den.y * den.y;
-            double2 inv = zc(den.x / dn, -den.y / dn);
-            for (int i = tid; i < p; i += nt) x[i] = cmul(x[i], inv);
-            __syncthreads();
-            if (tid == 0) x[p] = beta;
-            tau = 1.0 + aa / sigma;
-        }
-        if (tid == 0) s_tau[jj] = tau;
+    double2 *Wm = a.W + a.woff[node];
+    if constexpr (PHASE == 0) {
+        for (int e = tid; e < m * r; e += nt) Uw[e] = Uin[e];
         __syncthreads();
-        // apply H = I - tau v v^*, v = [x[0..p); 1], to columns 0..jj-1 (rows 0..p)
-        if (tau != 0.0) {
-            for (int c = tid; c < jj; c += nt) {
-                double2 *col = Uw + (size_t)c * m;
+        // QL: for column jj = r-1..0 eliminate rows 0..p-1 (p = k + jj) into row p
+        for (int jj = r - 1; jj >= 0; --jj) {
+            const int p = k + jj, n = p + 1;
+            double2 *x = Uw + (size_t)jj * m;            // rows 0..p
+            const double2 al = x[p];
+            double part = 0.0;
+            for (int i = tid; i < n; i += nt) part += x[i].x * x[i].x + x[i].y * x[i].y;
+            const double sigma = sqrt(wsum(part, sh));
+            double tau = 0.0;
+            if (sigma > 0.0) {
+                const double aa = sqrt(al.x * al.x + al.y * al.y);
+                double2 ph = aa > 0.0 ? zc(al.x / aa, al.y / aa) : zc(1.0, 0.0);
+                double2 beta = zc(-ph.x * sigma, -ph.y * sigma);
+                double2 den = csub(al, beta);
+                double dn = den.x * den.x + den.y * den.y;
+                double2 inv = zc(den.x / dn, -den.y / dn);
+                for (int i = tid; i < p; i += nt) x[i] = cmul(x[i], inv);
+                __syncthreads();
+                if (tid == 0) x[p] = beta;
+                tau = 1.0 + aa / sigma;
+            }
+            if (tid == 0) s_tau[jj] = tau;
+            __syncthreads();
+            // apply H = I - tau v v^*, v = [x[0..p); 1], to columns 0..jj-1 (rows 0..p)
+            if (tau != 0.0) {
+                for (int c = tid; c < jj; c += nt) {
+                    double2 *col = Uw + (size_t)c * m;
+                    double2 w = col[p];
+                    for (int i = 0; i < p; ++i) cfmac(w, x[i], col[i]);
+                    double2 tw = zc(tau * w.x, tau * w.y);
+                    col[p] = csub(col[p], tw);
+                    for (int i = 0; i < p; ++i) col[i] = csub(col[i], cmul(x[i], tw));
+                }
+            }
+            __syncthreads();
+        }
+        // Q = H_{r-1} ... H_0 I: apply H_0 first
+        for (int e = tid; e < m * m; e += nt) Q[e] = zc((e % m) == (e / m) ? 1.0 : 0.0, 0.0);
+        __syncthreads();
+        for (int jj = 0; jj < r; ++jj) {
+            const double tau = s_tau[jj];
+            if (tau == 0.0) continue;
+            const int p = k + jj;
+            const double2 *x = Uw + (size_t)jj * m;
+            for (int c = tid; c < m; c += nt) {
+                double2 *col = Q + (size_t)c * m;
                 double2 w = col[p];
                 for (int i = 0; i < p; ++i) cfmac(w, x[i], col[i]);
                 double2 tw = zc(tau * w.x, tau * w.y);
                 col[p] = csub(col[p], tw);
                 for (int i = 0; i < p; ++i) col[i] = csub(col[i], cmul(x[i], tw));
             }
+            __syncthreads();
         }
-        __syncthreads();
-    }
-    // Q = H_{r-1} ... H_0 I: apply H_0 first
-    for (int e = tid; e < m * m; e += nt) Q[e] = zc((e % m) == (e / m) ? 1.0 : 0.0, 0.0);
-    __syncthreads();
-    for (int jj = 0; jj < r; ++jj) {
-        const double tau = s_tau[jj];
-        if (tau == 0.0) continue;
-        const int p = k + jj;
-        const double2 *x = Uw + (size_t)jj * m;
-        for (int c = tid; c < m; c += nt) {
-            double2 *col = Q + (size_t)c * m;
-            double2 w = col[p];
-            for (int i = 0; i < p; ++i) cfmac(w, x[i], col[i]);
-            double2 tw = zc(tau * w.x, tau * w.y);
-            col[p] = csub(col[p], tw);
-            for (int i = 0; i < p; ++i) col[i] = csub(col[i], cmul(x[i], tw));
+        // Uhat2: rows k..m-1 of the transformed U (lower triangular r x r: entries j >= i of the
+        // reflector-free part); the transformed U is [0; L] with L(i, c) at row k + i, column c
+        double2 *U2 = a.U2 + a.soff[node];
+        for (int e = tid; e < r * r; e += nt) {
+            int i = e % r, c = e / r;
+            U2[e] = (c <= i) ? Uw[(k + i) + (size_t)c * m] : zc(0.0, 0.0);
         }
-        __syncthreads();
+        return;
     }
-    // Uhat2: rows k..m-1 of the transformed U (lower triangular r x r: entries j >= i of the
-    // reflector-free part); the transformed U is [0; L] with L(i, c) at row k + i, column c
-    double2 *U2 = a.U2 + a.soff[node];
-    for (int e = tid; e < r * r; e += nt) {
-        int i = e % r, c = e / r;
-        U2[e] = (c <= i) ? Uw[(k + i) + (size_t)c * m] : zc(0.0, 0.0);
-    }
-    // T = Q^* D
-    double2 *Wm = a.W + a.woff[node];
-    for (int e = tid; e < m * m; e += nt) {
-        int i = e % m, j = e / m;
-        double2 acc = zc(0.0, 0.0);
-        for (int l = 0; l < m; ++l) cfmac(acc, Q[l + (size_t)i * m], Din[l + (size_t)j * m]);
-        Wm[e] = acc;                                 // temporary use of the W slot
-    }
-    __syncthreads();
-    // Dchk = (Q^* D) Q
-    for (int e = tid; e < m * m; e += nt) {
-        int i = e % m, j = e / m;
-        double2 acc = zc(0.0, 0.0);
-        for (int l = 0; l < m; ++l) cfma(acc, Wm[i + (size_t)l * m], Q[l + (size_t)j * m]);
-        T[e] = acc;
-    }
-    __syncthreads();
-    // Cholesky of Dchk11 (k x k) in place
+    // T holds Dchk = (Q^* D) Q (the W slot held Q^* D); Cholesky of Dchk11 (k x k) in place
     if (!wg_potrf(T, m, k, sh, &s_flag)) {
         if (tid == 0) atomicAdd(a.fail, 1);
         return;
@@ -540,7 +532,26 @@ static fio_status factor_impl(hss_s *h, hipStream_t s, hss_ulv_t *out) {
             fa.scratch = scr.as<double2>();
             fa.scoff = (const size_t *)(mb + o_sc);
             fa.fail = failb.as<int>();
-            k_ulv_node<<<nn, ulv_threads(mlev), 0, s>>>(fa);
+            k_ulv_node<0><<<nn, ulv_threads(mlev), 0, s>>>(fa);
+            FIO_HIP(hipGetLastError());
+            {
+                // Dchk = Q^* D Q for every node of the level: W slot <- Q^* D, T <- (Q^* D) Q
+                ZgemmBatch g1, g2;
+                double2 *sc = scr.as<double2>();
+                double2 *W = f->W.as<double2>();
+                for (int j = 0; j < nn; ++j) {
+                    const int m = f->m[l][j];
+                    double2 *Q = sc + scoff[j] + (size_t)m * m, *T = Q + (size_t)m * m;
+                    g1.add(Q, m, Din + din_off[j], m, W + f->woff[l][j], m, m, m, m);
+                    g2.add(W + f->woff[l][j], m, Q, m, T, m, m, m, m);
+                }
+                g1.upload(s);
+                g2.upload(s);
+                g1.run(true, zc(1.0, 0.0), zc(0.0, 0.0), s);
+                g2.run(false, zc(1.0, 0.0), zc(0.0, 0.0), s);
+                FIO_HIP(hipStreamSynchronize(s));   // the descriptor lists are released here
+            }
+            k_ulv_node<1><<<nn, ulv_threads(mlev), 0, s>>>(fa);
             FIO_HIP(hipGetLastError());
             // merge into level l-1
             const int np = h->nodes(l - 1);
