@@ -405,6 +405,7 @@ template <typename T, int Q> struct StructArgs {
     int nrhs;
     int cside;               // 1: C factors (P transposed, child index c_in)
     T P[2][Q][Q];            // P_c(i, t)
+    T PT[2][Q][Q];           // P_c(t, i): the transposes, so that every variant reads one pattern
 };
 
 template <typename T, int Q, int KL, bool ADJ, bool EPI_M, bool CS>
@@ -452,7 +453,14 @@ __global__ void __launch_bounds__((1 << KL) * 64, 4) k_struct_fused(StructArgs<T
             const int srcp = ADJ ? (o ? lout0 + Gl : lout0) : lin0 + o;
             const C *ta = tw + cout * 4 * Q + cin * Q;          // a(c_out, c_in, .)
             const C *tb = tw + cout * 4 * Q + (2 + cin) * Q;    // b(c_out, c_in, .)
-            const T *Pm = &a.P[0][0][0] + (CS ? cin : cout) * Q * Q;
+            // Double precision: element (r, t) of the quadrant matrix is read as Pm[t * Q + r] in
+            // every variant, and when both input children use the same matrix an opaque zero
+            // offset makes each child load it for itself (otherwise the compiler keeps all 2 q^2
+            // scalar registers of the matrix live across both and spills them into vector lanes).
+            constexpr bool D = sizeof(T) == 8;
+            int opaque0 = 0;
+            if constexpr (D) asm volatile("s_mov_b32 %0, 0" : "=s"(opaque0));
+            const T *Pm = (D && !TRANS ? &a.PT[0][0][0] : &a.P[0][0][0]) + (CS ? cin : cout) * Q * Q + opaque0;
             C w[Q];
 #pragma unroll
             for (int t = 0; t < Q; ++t) {
@@ -469,7 +477,7 @@ __global__ void __launch_bounds__((1 << KL) * 64, 4) k_struct_fused(StructArgs<T
                 C v = czero<C>();
 #pragma unroll
                 for (int t = 0; t < Q; ++t) {
-                    const T m = TRANS ? Pm[t * Q + r] : Pm[r * Q + t];
+                    const T m = (D || TRANS) ? Pm[t * Q + r] : Pm[r * Q + t];
                     v.x = fma(m, w[t].x, v.x);
                     v.y = fma(m, w[t].y, v.y);
                 }
@@ -714,7 +722,10 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
                 sa.cside = cside ? 1 : 0;
                 for (int c = 0; c < 2; ++c)
                     for (int i = 0; i < Q; ++i)
-                        for (int t = 0; t < Q; ++t) sa.P[c][i][t] = (T)bf->Pchild[(c * Q + i) * Q + t];
+                        for (int t = 0; t < Q; ++t) {
+                            sa.P[c][i][t] = (T)bf->Pchild[(c * Q + i) * Q + t];
+                            sa.PT[c][t][i] = sa.P[c][i][t];
+                        }
                 FIO_TIMED(f64 ? "bf_struct_f64" : "bf_struct_f32", s);
                 run_struct<T, Q>(sa, kl, a, epi, bf->N, s);
                 std::swap(cur, nxt);
