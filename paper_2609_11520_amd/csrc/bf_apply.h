@@ -408,8 +408,10 @@ template <typename T, int Q> struct StructArgs {
     T PT[2][Q][Q];           // P_c(t, i): the transposes, so that every variant reads one pattern
 };
 
+// Register budget: single precision keeps 8 waves per SIMD (four 37 KB workgroups per CU at
+// KL = 3, <= 64 VGPRs), double precision 4 (two 74 KB workgroups, LDS-bound anyway).
 template <typename T, int Q, int KL, bool ADJ, bool EPI_M, bool CS>
-__global__ void __launch_bounds__((1 << KL) * 64, 4) k_struct_fused(StructArgs<T, Q> a) {
+__global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 8 : 4) k_struct_fused(StructArgs<T, Q> a) {
     using C = cpx<T>;
     constexpr int P = 1 << KL;
     __shared__ C lds[P * Q * 64];
@@ -453,14 +455,16 @@ __global__ void __launch_bounds__((1 << KL) * 64, 4) k_struct_fused(StructArgs<T
             const int srcp = ADJ ? (o ? lout0 + Gl : lout0) : lin0 + o;
             const C *ta = tw + cout * 4 * Q + cin * Q;          // a(c_out, c_in, .)
             const C *tb = tw + cout * 4 * Q + (2 + cin) * Q;    // b(c_out, c_in, .)
-            // Double precision: element (r, t) of the quadrant matrix is read as Pm[t * Q + r] in
-            // every variant, and when both input children use the same matrix an opaque zero
-            // offset makes each child load it for itself (otherwise the compiler keeps all 2 q^2
-            // scalar registers of the matrix live across both and spills them into vector lanes).
+            // Element (r, t) of the quadrant matrix is read in one pattern per precision in every
+            // variant: Pm[t * Q + r] (double) or Pm[r * Q + t] (single), from P or its transpose
+            // as the variant needs.  In double precision, when both input children use the same
+            // matrix, an opaque zero offset makes each child load it for itself (otherwise the
+            // compiler keeps all 2 q^2 scalar registers of the matrix live across both and spills
+            // them into vector lanes).
             constexpr bool D = sizeof(T) == 8;
             int opaque0 = 0;
             if constexpr (D) asm volatile("s_mov_b32 %0, 0" : "=s"(opaque0));
-            const T *Pm = (D && !TRANS ? &a.PT[0][0][0] : &a.P[0][0][0]) + (CS ? cin : cout) * Q * Q + opaque0;
+            const T *Pm = ((D ? !TRANS : TRANS) ? &a.PT[0][0][0] : &a.P[0][0][0]) + (CS ? cin : cout) * Q * Q + opaque0;
             C w[Q];
 #pragma unroll
             for (int t = 0; t < Q; ++t) {
@@ -477,7 +481,7 @@ __global__ void __launch_bounds__((1 << KL) * 64, 4) k_struct_fused(StructArgs<T
                 C v = czero<C>();
 #pragma unroll
                 for (int t = 0; t < Q; ++t) {
-                    const T m = (D || TRANS) ? Pm[t * Q + r] : Pm[r * Q + t];
+                    const T m = D ? Pm[t * Q + r] : Pm[r * Q + t];
                     v.x = fma(m, w[t].x, v.x);
                     v.y = fma(m, w[t].y, v.y);
                 }
