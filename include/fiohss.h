@@ -165,6 +165,13 @@ fio_status fio_permute2d(long n, int to_internal, const void *X, long ldx, void 
  * thread-safe with respect to concurrent applies. */
 void fio_set_fused(int on);
 
+/* Selects how the HSS construction (hss_build_from_samples, fio_hss_build) runs the node
+ * algebra of a level: levels whose largest node has at least `rows` rows run every
+ * reflector and pivot step as its own launch spread over many workgroups; smaller levels
+ * run one workgroup per node.  Both give the same result up to rounding order.  rows <= 0
+ * restores the default (256).  Not thread-safe with respect to concurrent constructions. */
+void fio_hss_set_big_node(int rows);
+
 /* ---------------------------------------------------------------------------
  * Randomized black-box HSS construction of a Hermitian matrix (Section 3).
  * The tree is binary over rows 0..N-1, leaves of `leaf` rows (N = leaf 2^Lh);

@@ -361,6 +361,12 @@ def set_fused(on=True):
     lib().fio_set_fused(1 if on else 0)
 
 
+def set_hss_big_node(rows):
+    """HSS construction: levels whose largest node has >= rows rows use the multi-workgroup
+    reflector path (rows <= 0: default 256)."""
+    lib().fio_hss_set_big_node(int(rows))
+
+
 class Server:
     """Continuous-batching solve server (fio_server_* in the C ABI)."""
 

@@ -302,6 +302,221 @@ __global__ void __launch_bounds__(1024) k_node_finish(NodeArgs a) {
     for (int e = tid; e < m * r; e += nt) Uo[e] = U[e];
 }
 
+// ---------------------------------------------------------------------------
+// Large nodes (the upper levels of 2D trees, hundreds to thousands of rows, few nodes per
+// level): the same Section 3.1 steps as k_node_basis, one reflector or pivot step per
+// launch, each launch spread over many workgroups (grid.y = node, grid.x = column or row
+// chunk).  The reflector and pivot arithmetic is k_node_basis's; only the work split differs.
+struct BigArgs {
+    NodeArgs n;
+    double *tauA, *tauW;   // reflector scalars per node (kMaxM each)
+    double *nrm;           // column norms per node (ldn each)
+    int ldn;
+    int *done;             // 1 once the node's QRCP has stopped
+};
+
+constexpr int kBigChunk = 64;      // columns (or rows) per workgroup of the apply kernels
+
+__global__ void k_big_init(BigArgs b) {
+    const NodeArgs &a = b.n;
+    const int node = blockIdx.y, m = a.msz[node], s = a.s;
+    if (m == 0) return;
+    double2 *A = a.scratch + a.stride * node, *Z = A + (size_t)s * m;
+    const double2 *Om = a.Om + a.moff[node], *Yt = a.Y + a.moff[node];
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)s * m; e += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(e % s), j = (int)(e / s);
+        const double2 v = Om[j + (size_t)i * a.ldR];
+        A[e] = zc(v.x, -v.y);
+        const int zi = (int)(e % m), zj = (int)(e / m);
+        Z[e] = Yt[zi + (size_t)zj * a.ldR];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (!a.root) a.rank_out[node] = 0;
+        b.done[node] = 0;
+    }
+}
+
+// Householder vector of column j of A (rows j..s-1)
+__global__ void __launch_bounds__(1024) k_big_house_A(BigArgs b, int j) {
+    __shared__ double sh[16];
+    const NodeArgs &a = b.n;
+    const int node = blockIdx.y, m = a.msz[node], s = a.s;
+    if (j >= m) return;
+    double2 *A = a.scratch + a.stride * node;
+    const double tau = wg_house(A + j + (size_t)j * s, s - j, sh, nullptr);
+    if (threadIdx.x == 0) b.tauA[(size_t)node * kMaxM + j] = tau;
+}
+
+// H_j applied to columns j+1.. of A
+__global__ void __launch_bounds__(256) k_big_left_A(BigArgs b, int j) {
+    const NodeArgs &a = b.n;
+    const int node = blockIdx.y, m = a.msz[node], s = a.s;
+    const int c0 = j + 1 + blockIdx.x * kBigChunk;
+    if (j >= m || c0 >= m) return;
+    double2 *A = a.scratch + a.stride * node;
+    const int nc = m - c0 < kBigChunk ? m - c0 : kBigChunk;
+    wg_house_left(A + j + 1 + (size_t)j * s, s - j, b.tauA[(size_t)node * kMaxM + j], A + j + (size_t)c0 * s, s, nc);
+}
+
+// Z <- Z H_j on a chunk of Z's rows
+__global__ void __launch_bounds__(256) k_big_right_Z(BigArgs b, int j) {
+    const NodeArgs &a = b.n;
+    const int node = blockIdx.y, m = a.msz[node], s = a.s;
+    const int r0 = blockIdx.x * kBigChunk;
+    if (j >= m || r0 >= m) return;
+    double2 *A = a.scratch + a.stride * node, *Z = A + (size_t)s * m;
+    const int nr = m - r0 < kBigChunk ? m - r0 : kBigChunk;
+    wg_house_right(A + j + 1 + (size_t)j * s, s - j, b.tauA[(size_t)node * kMaxM + j], Z + r0 + (size_t)j * m, m, nr);
+}
+
+__device__ __forceinline__ int big_kmax(const NodeArgs &a, int m) {
+    const int nw = a.s - m;
+    int kmax = m < nw ? m : nw;
+    if (a.cap > 0 && a.cap < kmax) kmax = a.cap;
+    return kmax;
+}
+
+// QRCP step j: norms of the remaining columns of W (rows j..m-1), 4 lanes per column
+__global__ void __launch_bounds__(256) k_big_norms(BigArgs b, int j) {
+    const NodeArgs &a = b.n;
+    const int node = blockIdx.y, m = a.msz[node], s = a.s;
+    if (m == 0 || b.done[node] || j >= big_kmax(a, m)) return;
+    const int nw = s - m;
+    const double2 *W = a.scratch + a.stride * node + (size_t)s * m + (size_t)m * m;
+    const int sub = threadIdx.x & 3;
+    const int c = j + blockIdx.x * kBigChunk + (threadIdx.x >> 2);
+    double p = 0.0;
+    if (c < nw)
+        for (int i = j + sub; i < m; i += 4) {
+            const double2 v = W[i + (size_t)c * m];
+            p += v.x * v.x + v.y * v.y;
+        }
+    p += __shfl_xor(p, 1);
+    p += __shfl_xor(p, 2);
+    if (c < nw && sub == 0) b.nrm[(size_t)node * b.ldn + c] = sqrt(p);
+}
+
+// QRCP step j: pivot (largest norm, lowest index on ties), stop test, swap, reflector
+__global__ void __launch_bounds__(1024) k_big_pivot(BigArgs b, int j) {
+    __shared__ double sh[16];
+    __shared__ int s_piv;
+    __shared__ double s_max;
+    const NodeArgs &a = b.n;
+    const int node = blockIdx.y, m = a.msz[node], s = a.s;
+    if (m == 0 || b.done[node]) return;
+    if (j >= big_kmax(a, m)) {
+        if (threadIdx.x == 0) b.done[node] = 1;
+        return;
+    }
+    const int nw = s - m;
+    double2 *W = a.scratch + a.stride * node + (size_t)s * m + (size_t)m * m;
+    const double *nrm = b.nrm + (size_t)node * b.ldn;
+    if (threadIdx.x == 0) {
+        int best = j;
+        double bv = nrm[j];
+        for (int c = j + 1; c < nw; ++c)
+            if (nrm[c] > bv) {
+                bv = nrm[c];
+                best = c;
+            }
+        s_piv = best;
+        s_max = bv;
+    }
+    __syncthreads();
+    if (!(s_max > a.tol_abs)) {
+        if (threadIdx.x == 0) b.done[node] = 1;
+        return;
+    }
+    const int pc = s_piv;
+    if (pc != j) {
+        for (int i = threadIdx.x; i < m; i += blockDim.x) {
+            const double2 t = W[i + (size_t)j * m];
+            W[i + (size_t)j * m] = W[i + (size_t)pc * m];
+            W[i + (size_t)pc * m] = t;
+        }
+        __syncthreads();
+    }
+    const double tau = wg_house(W + j + (size_t)j * m, m - j, sh, nullptr);
+    if (threadIdx.x == 0) {
+        b.tauW[(size_t)node * kMaxM + j] = tau;
+        a.rank_out[node] = j + 1;
+    }
+}
+
+// QRCP step j: H_j applied to columns j+1.. of W
+__global__ void __launch_bounds__(256) k_big_left_W(BigArgs b, int j) {
+    const NodeArgs &a = b.n;
+    const int node = blockIdx.y, m = a.msz[node], s = a.s;
+    if (m == 0 || b.done[node]) return;
+    const int nw = s - m;
+    const int c0 = j + 1 + blockIdx.x * kBigChunk;
+    if (c0 >= nw) return;
+    double2 *W = a.scratch + a.stride * node + (size_t)s * m + (size_t)m * m;
+    const int nc = nw - c0 < kBigChunk ? nw - c0 : kBigChunk;
+    wg_house_left(W + j + 1 + (size_t)j * m, m - j, b.tauW[(size_t)node * kMaxM + j], W + j + (size_t)c0 * m, m, nc);
+}
+
+// U = [I_r; 0]
+__global__ void k_big_uinit(BigArgs b) {
+    const NodeArgs &a = b.n;
+    const int node = blockIdx.y, m = a.msz[node], s = a.s;
+    if (m == 0) return;
+    const int r = a.rank_out[node];
+    double2 *U = a.scratch + a.stride * node + (size_t)s * m + (size_t)m * s;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)m * r; e += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(e % m), jj = (int)(e / m);
+        U[e] = zc(i == jj ? 1.0 : 0.0, 0.0);
+    }
+}
+
+// U <- H_j U (rows j..m-1) on a chunk of U's r columns
+__global__ void __launch_bounds__(256) k_big_left_U(BigArgs b, int j) {
+    const NodeArgs &a = b.n;
+    const int node = blockIdx.y, m = a.msz[node], s = a.s;
+    if (m == 0) return;
+    const int r = a.rank_out[node];
+    const int c0 = blockIdx.x * kBigChunk;
+    if (j >= r || c0 >= r) return;
+    double2 *Z = a.scratch + a.stride * node + (size_t)s * m;
+    double2 *W = Z + (size_t)m * m, *U = Z + (size_t)m * s;
+    const int nc = r - c0 < kBigChunk ? r - c0 : kBigChunk;
+    wg_house_left(W + j + 1 + (size_t)j * m, m - j, b.tauW[(size_t)node * kMaxM + j], U + j + (size_t)c0 * m, m, nc);
+}
+
+// T = Z1 R^{-*} (R = upper m x m of A), one lane per row; at the root also H0 = (T + T^*)/2
+__global__ void __launch_bounds__(256) k_big_tsolve(BigArgs b) {
+    const NodeArgs &a = b.n;
+    const int node = blockIdx.y, m = a.msz[node], s = a.s;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m == 0 || i >= m) return;
+    const double2 *A = a.scratch + a.stride * node;
+    double2 *Z = const_cast<double2 *>(A) + (size_t)s * m;
+    for (int j = m - 1; j >= 0; --j) {
+        double2 acc = Z[i + (size_t)j * m];
+        for (int k = j + 1; k < m; ++k) {
+            const double2 rjk = A[j + (size_t)k * s];
+            const double2 t = Z[i + (size_t)k * m];
+            acc.x -= t.x * rjk.x + t.y * rjk.y;
+            acc.y -= t.y * rjk.x - t.x * rjk.y;
+        }
+        const double2 rjj = A[j + (size_t)j * s];
+        const double d = rjj.x * rjj.x + rjj.y * rjj.y;
+        Z[i + (size_t)j * m] = zc((acc.x * rjj.x - acc.y * rjj.y) / d, (acc.x * rjj.y + acc.y * rjj.x) / d);
+    }
+}
+
+__global__ void k_big_root_out(BigArgs b) {
+    const NodeArgs &a = b.n;
+    const int node = blockIdx.y, m = a.msz[node], s = a.s;
+    const double2 *Z = a.scratch + a.stride * node + (size_t)s * m;
+    double2 *out = a.Dres + a.doff[node];
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)m * m; e += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(e % m), j = (int)(e / m);
+        const double2 x = Z[i + (size_t)j * m], y = Z[j + (size_t)i * m];
+        out[e] = zc(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+    }
+}
+
 // P(a, c) = conj(Y(c, a)) for a < r, c < m, Y = X U in the X slot, P in the P slot of each node
 __global__ void k_node_conj_transpose(NodeArgs a) {
     const int node = blockIdx.y;
@@ -401,6 +616,71 @@ template <typename T> static DevBuf *upload(const std::vector<T> &v, hipStream_t
     DevBuf *b = new DevBuf(v.size() * sizeof(T) + 8);
     FIO_HIP(hipMemcpyAsync(b->p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
     return b;
+}
+
+// Section 3.1 on a level of large nodes, one reflector or pivot step per launch (see BigArgs).
+static int g_big_node = 256;       // levels whose largest node has at least this many rows take this path
+
+static unsigned cdiv(long a, long b) { return (unsigned)(a <= 0 ? 0 : (a + b - 1) / b); }
+
+static void basis_big(const NodeArgs &na, const std::vector<int> &ms, int nn, int mmax, int sl, bool root,
+                      hipStream_t s) {
+    DevBuf tauA((size_t)nn * kMaxM * sizeof(double)), tauW((size_t)nn * kMaxM * sizeof(double)),
+        nrm((size_t)nn * sl * sizeof(double)), done((size_t)nn * sizeof(int));
+    BigArgs b;
+    b.n = na;
+    b.tauA = tauA.as<double>();
+    b.tauW = tauW.as<double>();
+    b.nrm = nrm.as<double>();
+    b.ldn = sl;
+    b.done = done.as<int>();
+    const unsigned y = (unsigned)nn;
+    k_big_init<<<dim3(256, y), 256, 0, s>>>(b);
+    // full Householder QR of Omega_tau^* (s x m), then Z = Y_tau H_0 ... H_{m-1}
+    for (int j = 0; j < mmax; ++j) {
+        k_big_house_A<<<dim3(1, y), 1024, 0, s>>>(b, j);
+        if (mmax - 1 - j > 0) k_big_left_A<<<dim3(cdiv(mmax - 1 - j, kBigChunk), y), 256, 0, s>>>(b, j);
+    }
+    for (int j = 0; j < mmax; ++j) k_big_right_Z<<<dim3(cdiv(mmax, kBigChunk), y), 256, 0, s>>>(b, j);
+    FIO_HIP(hipGetLastError());
+    if (!root) {
+        // QRCP of W = Z[:, m:s]; every 32 steps the host stops once every node has stopped
+        int mmin = mmax, kcap = 0;
+        for (int v : ms)
+            if (v > 0) mmin = v < mmin ? v : mmin;
+        for (int v : ms) {
+            if (v == 0) continue;
+            int k = v < sl - v ? v : sl - v;
+            if (na.cap > 0 && na.cap < k) k = na.cap;
+            kcap = k > kcap ? k : kcap;
+        }
+        const int nwmax = sl - mmin;
+        std::vector<int> hd(nn);
+        for (int j = 0; j < kcap; ++j) {
+            k_big_norms<<<dim3(cdiv(nwmax - j, kBigChunk), y), 256, 0, s>>>(b, j);
+            k_big_pivot<<<dim3(1, y), 1024, 0, s>>>(b, j);
+            if (nwmax - j - 1 > 0) k_big_left_W<<<dim3(cdiv(nwmax - j - 1, kBigChunk), y), 256, 0, s>>>(b, j);
+            if ((j & 31) == 31) {
+                FIO_HIP(hipMemcpyAsync(hd.data(), done.p, nn * sizeof(int), hipMemcpyDeviceToHost, s));
+                FIO_HIP(hipStreamSynchronize(s));
+                bool all = true;
+                for (int k = 0; k < nn; ++k) all = all && (hd[k] || ms[k] == 0);
+                if (all) break;
+            }
+        }
+        std::vector<int> rk(nn);
+        FIO_HIP(hipMemcpyAsync(rk.data(), na.rank_out, nn * sizeof(int), hipMemcpyDeviceToHost, s));
+        FIO_HIP(hipStreamSynchronize(s));
+        int rmax = 0;
+        for (int v : rk) rmax = v > rmax ? v : rmax;
+        // U = H_0 ... H_{r-1} [I_r; 0]
+        k_big_uinit<<<dim3(64, y), 256, 0, s>>>(b);
+        for (int j = rmax - 1; j >= 0; --j) k_big_left_U<<<dim3(cdiv(rmax, kBigChunk), y), 256, 0, s>>>(b, j);
+    }
+    k_big_tsolve<<<dim3(cdiv(mmax, 256), y), 256, 0, s>>>(b);
+    if (root) k_big_root_out<<<dim3(64, y), 256, 0, s>>>(b);
+    FIO_HIP(hipGetLastError());
+    FIO_HIP(hipStreamSynchronize(s));    // the work arrays are released here
 }
 
 void hss_layout_level(hss_s *h, int l) {
@@ -553,7 +833,11 @@ static fio_status build_impl(long n, const hss_opts *o, const Sampler &sm, hipSt
             if (mmax > kMaxM) throw Err{FIO_ERR_UNSUPPORTED};
             const int rh = root ? 0 : (o->rhat > 0 ? o->rhat : mmax);
             const int sl = mmax + rh + o->p;
-            if (!root && sl - mmax > kMaxNW) throw Err{FIO_ERR_UNSUPPORTED};
+            // the one-workgroup node kernel keeps the norms of all s - m sample columns in LDS
+            int mmin = mmax;
+            for (int v : ms)
+                if (v > 0) mmin = v < mmin ? v : mmin;
+            if (!root && mmax < g_big_node && sl - mmin > kMaxNW) throw Err{FIO_ERR_UNSUPPORTED};
             h->samples[l] = sl;
             Om.ensure((size_t)R * sl * sizeof(double2));
             if (sm.omega(sm.octx, l, R, sl, Om.p, s) != 0) throw Err{FIO_ERR_CALLBACK};
@@ -595,8 +879,12 @@ static fio_status build_impl(long n, const hss_opts *o, const Sampler &sm, hipSt
             na.Dres = Dres[l]->as<double2>();
             na.doff = ddo->as<size_t>();
             na.root = root ? 1 : 0;
-            k_node_basis<<<nn, node_threads(mmax), 0, s>>>(na);
-            FIO_HIP(hipGetLastError());
+            if (mmax < g_big_node) {
+                k_node_basis<<<nn, node_threads(mmax), 0, s>>>(na);
+                FIO_HIP(hipGetLastError());
+            } else {
+                basis_big(na, ms, nn, mmax, sl, root, s);
+            }
             if (!root) {
                 h->rank[l].assign(nn, 0);
                 FIO_HIP(hipMemcpyAsync(h->rank[l].data(), rk.p, nn * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -945,3 +1233,5 @@ extern "C" fio_status hss_matvec(hss_t h, const void *X, long ldx, void *Y, long
 }
 
 extern "C" void hss_destroy(hss_t h) { delete h; }
+
+extern "C" void fio_hss_set_big_node(int rows) { fio::g_big_node = rows > 0 ? rows : 256; }

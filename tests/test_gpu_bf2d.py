@@ -200,3 +200,25 @@ def test_pcg_2d_matches_oracle():
     fh, info = F.approx_solve(B, U, dev(u), mode=F.FIO_SOLVE_PCG, rel_res_tol=1e-12, max_ir=50)
     assert info.ir_steps <= 10
     assert osolve.col_rel_err(host(fh), f) < 1e-10
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_hss_large_node_path_matches_oracle(n):
+    """The multi-workgroup node path (forced on every level with >= 64 rows) against the oracle."""
+    F = fiohss()
+    step("2D HSS large-node path n=%d" % n)
+    h, fac = oracle_hss2(n, 1e-3, 10, 1002)
+    B = gpu_bf2(F, n, 9, "aniso16", imported=True)
+    F.set_hss_big_node(64)
+    try:
+        H = F.HSS.from_bf(B, tol=1e-3, p=10, omega=F.omega_from(omega_np(1002)))
+    finally:
+        F.set_hss_big_node(0)
+    assert H.ranks() == {l: list(v) for l, v in h.rank.items()}
+    x = fi.complex_gaussian(6, fi.PURPOSE_PROBE, n * n, 3)
+    assert rel(host(H.matvec(dev(x))), ohss.matvec(h, x)) < 1e-12
+    ob = oracle_bf2(n, 9, "aniso16")
+    f = fi.rhs(0, n * n, 2)
+    u = ob.apply(f)
+    fh, _ = F.approx_solve(B, F.ULV(H), dev(u))
+    assert rel(host(fh), osolve.direct_solve2d(ob, fac, u)) < 1e-12
