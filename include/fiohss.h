@@ -172,6 +172,11 @@ void fio_set_fused(int on);
  * restores the default (256).  Not thread-safe with respect to concurrent constructions. */
 void fio_hss_set_big_node(int rows);
 
+/* The same choice for the basis elimination of hss_ulv_factor (QL of each node's basis and
+ * the explicit Q): levels whose largest node has at least `rows` rows apply every reflector
+ * in its own launch over many workgroups.  rows <= 0 restores the default (256). */
+void fio_ulv_set_big_node(int rows);
+
 /* ---------------------------------------------------------------------------
  * Randomized black-box HSS construction of a Hermitian matrix (Section 3).
  * The tree is binary over rows 0..N-1, leaves of `leaf` rows (N = leaf 2^Lh);

@@ -367,6 +367,12 @@ def set_hss_big_node(rows):
     lib().fio_hss_set_big_node(int(rows))
 
 
+def set_ulv_big_node(rows):
+    """ULV factorization: levels whose largest node has >= rows rows apply the basis reflectors
+    with the multi-workgroup path (rows <= 0: default 256)."""
+    lib().fio_ulv_set_big_node(int(rows))
+
+
 class Server:
     """Continuous-batching solve server (fio_server_* in the C ABI)."""
 

@@ -60,6 +60,7 @@ PROTOS = {
     "fio_bf_destroy": (None, [vp]),
     "fio_set_fused": (None, [i32]),
     "fio_hss_set_big_node": (None, [i32]),
+    "fio_ulv_set_big_node": (None, [i32]),
     "fio_permute2d": (i32, [lg, i32, vp, lg, vp, lg, i32, vp]),
     "hss_build_from_samples": (i32, [lg, C.POINTER(HssOpts), MATVEC_FN, vp, OMEGA_FN, vp, vp, C.POINTER(vp)]),
     "fio_hss_build": (i32, [vp, C.POINTER(HssOpts), OMEGA_FN, vp, vp, C.POINTER(vp)]),

@@ -255,6 +255,140 @@ __global__ void __launch_bounds__(1024) k_ulv_node(FactArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Large nodes (upper levels of 2D trees): phase 0 of k_ulv_node with one reflector per
+// launch spread over many workgroups (grid.y = node, grid.x = 64-column chunk).  Node j of
+// the level eliminates its columns jj = r-1 .. 0 at host steps t = r-1-jj, and builds Q
+// with jj = t.  Same reflector arithmetic as k_ulv_node; the dot products run over four
+// lanes per column.
+struct UlvBig {
+    FactArgs f;
+    double *tau;            // kUlvMaxM per node
+};
+
+constexpr int kUlvChunk = 64;
+
+__global__ void k_ubig_init(UlvBig b) {
+    const FactArgs &a = b.f;
+    const int node = blockIdx.y, m = a.msz[node], r = a.rsz[node];
+    if (m == 0) return;
+    double2 *Uw = a.scratch + a.scoff[node], *Q = Uw + (size_t)m * m;
+    const double2 *Uin = a.U + a.uoff[node];
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)m * m; e += (long)gridDim.x * blockDim.x) {
+        if (e < (long)m * r) Uw[e] = Uin[e];
+        Q[e] = zc((e % m) == (e / m) ? 1.0 : 0.0, 0.0);
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_ubig_house(UlvBig b, int t) {
+    __shared__ double sh[16];
+    const FactArgs &a = b.f;
+    const int node = blockIdx.y, m = a.msz[node], r = a.rsz[node], k = m - r;
+    const int jj = r - 1 - t;
+    if (m == 0 || jj < 0) return;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int p = k + jj, n = p + 1;
+    double2 *x = a.scratch + a.scoff[node] + (size_t)jj * m;
+    const double2 al = x[p];
+    double part = 0.0;
+    for (int i = tid; i < n; i += nt) part += x[i].x * x[i].x + x[i].y * x[i].y;
+    const double sigma = sqrt(wsum(part, sh));
+    double tau = 0.0;
+    if (sigma > 0.0) {
+        const double aa = sqrt(al.x * al.x + al.y * al.y);
+        const double2 ph = aa > 0.0 ? zc(al.x / aa, al.y / aa) : zc(1.0, 0.0);
+        const double2 beta = zc(-ph.x * sigma, -ph.y * sigma);
+        const double2 den = csub(al, beta);
+        const double dn = den.x * den.x + den.y * den.y;
+        const double2 inv = zc(den.x / dn, -den.y / dn);
+        for (int i = tid; i < p; i += nt) x[i] = cmul(x[i], inv);
+        __syncthreads();
+        if (tid == 0) x[p] = beta;
+        tau = 1.0 + aa / sigma;
+    }
+    if (tid == 0) b.tau[(size_t)node * kUlvMaxM + jj] = tau;
+}
+
+// columns [c0, c1) of A (lda) <- H A, H = I - tau v v^*, v = [x[0..p); 1] (rows 0..p)
+__device__ void ql_apply_cols(const double2 *x, int p, double tau, double2 *A, int lda, int c0, int c1) {
+    const int sub = threadIdx.x & 3;
+    for (int cb = c0; cb < c1; cb += (int)(blockDim.x >> 2)) {
+        const int c = cb + (int)(threadIdx.x >> 2);
+        double2 *col = A + (size_t)(c < c1 ? c : c0) * lda;
+        double2 w = zc(0.0, 0.0);
+        if (c < c1)
+            for (int i = sub; i < p; i += 4) cfmac(w, x[i], col[i]);
+        w.x += __shfl_xor(w.x, 1);
+        w.y += __shfl_xor(w.y, 1);
+        w.x += __shfl_xor(w.x, 2);
+        w.y += __shfl_xor(w.y, 2);
+        if (c < c1) {
+            w = cadd(w, col[p]);
+            const double2 tw = zc(tau * w.x, tau * w.y);
+            if (sub == 0) col[p] = csub(col[p], tw);
+            for (int i = sub; i < p; i += 4) col[i] = csub(col[i], cmul(x[i], tw));
+        }
+    }
+}
+
+// the current reflector applied to the node's remaining columns 0..jj-1
+__global__ void __launch_bounds__(256) k_ubig_left(UlvBig b, int t) {
+    const FactArgs &a = b.f;
+    const int node = blockIdx.y, m = a.msz[node], r = a.rsz[node], k = m - r;
+    const int jj = r - 1 - t;
+    const int c0 = blockIdx.x * kUlvChunk;
+    if (m == 0 || jj < 0 || c0 >= jj) return;
+    const double tau = b.tau[(size_t)node * kUlvMaxM + jj];
+    if (tau == 0.0) return;
+    double2 *Uw = a.scratch + a.scoff[node];
+    const int c1 = c0 + kUlvChunk < jj ? c0 + kUlvChunk : jj;
+    ql_apply_cols(Uw + (size_t)jj * m, k + jj, tau, Uw, m, c0, c1);
+}
+
+// Q <- H_jj Q, jj = t (Q = H_{r-1} ... H_0)
+__global__ void __launch_bounds__(256) k_ubig_q(UlvBig b, int t) {
+    const FactArgs &a = b.f;
+    const int node = blockIdx.y, m = a.msz[node], r = a.rsz[node], k = m - r;
+    const int c0 = blockIdx.x * kUlvChunk;
+    if (m == 0 || t >= r || c0 >= m) return;
+    const double tau = b.tau[(size_t)node * kUlvMaxM + t];
+    if (tau == 0.0) return;
+    double2 *Uw = a.scratch + a.scoff[node], *Q = Uw + (size_t)m * m;
+    const int c1 = c0 + kUlvChunk < m ? c0 + kUlvChunk : m;
+    ql_apply_cols(Uw + (size_t)t * m, k + t, tau, Q, m, c0, c1);
+}
+
+__global__ void k_ubig_u2(UlvBig b) {
+    const FactArgs &a = b.f;
+    const int node = blockIdx.y, m = a.msz[node], r = a.rsz[node], k = m - r;
+    if (m == 0) return;
+    const double2 *Uw = a.scratch + a.scoff[node];
+    double2 *U2 = a.U2 + a.soff[node];
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)r * r; e += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(e % r), c = (int)(e / r);
+        U2[e] = (c <= i) ? Uw[(k + i) + (size_t)c * m] : zc(0.0, 0.0);
+    }
+}
+
+static int g_ulv_big = 256;        // levels whose largest node has at least this many rows take this path
+
+static void ulv_phase0_big(const FactArgs &fa, int nn, int mlev, int rmax, hipStream_t s) {
+    DevBuf tau((size_t)nn * kUlvMaxM * sizeof(double));
+    UlvBig b{fa, tau.as<double>()};
+    const unsigned y = (unsigned)nn;
+    k_ubig_init<<<dim3(256, y), 256, 0, s>>>(b);
+    for (int t = 0; t < rmax; ++t) {
+        k_ubig_house<<<dim3(1, y), 1024, 0, s>>>(b, t);
+        const int ncol = rmax - 1 - t;     // an upper bound of every node's remaining columns
+        if (ncol > 0) k_ubig_left<<<dim3((unsigned)((ncol + kUlvChunk - 1) / kUlvChunk), y), 256, 0, s>>>(b, t);
+    }
+    for (int t = 0; t < rmax; ++t)
+        k_ubig_q<<<dim3((unsigned)((mlev + kUlvChunk - 1) / kUlvChunk), y), 256, 0, s>>>(b, t);
+    k_ubig_u2<<<dim3(64, y), 256, 0, s>>>(b);
+    FIO_HIP(hipGetLastError());
+    FIO_HIP(hipStreamSynchronize(s));   // the reflector scalars are released here
+}
+
 // Merge of eq. ulv_merge for every parent (one workgroup per parent):
 //   D+ = [[D22(a1), (U2(a2) B U2(a1)^*)^*], [U2(a2) B U2(a1)^*, D22(a2)]],
 //   U+ = diag(U2(a1), U2(a2)) U_parent  (skipped at the root).
@@ -532,8 +666,14 @@ static fio_status factor_impl(hss_s *h, hipStream_t s, hss_ulv_t *out) {
             fa.scratch = scr.as<double2>();
             fa.scoff = (const size_t *)(mb + o_sc);
             fa.fail = failb.as<int>();
-            k_ulv_node<0><<<nn, ulv_threads(mlev), 0, s>>>(fa);
-            FIO_HIP(hipGetLastError());
+            if (mlev < g_ulv_big) {
+                k_ulv_node<0><<<nn, ulv_threads(mlev), 0, s>>>(fa);
+                FIO_HIP(hipGetLastError());
+            } else {
+                int rmax = 0;
+                for (int v : f->r[l]) rmax = v > rmax ? v : rmax;
+                ulv_phase0_big(fa, nn, mlev, rmax, s);
+            }
             {
                 // Dchk = Q^* D Q for every node of the level: W slot <- Q^* D, T <- (Q^* D) Q
                 ZgemmBatch g1, g2;
@@ -759,3 +899,5 @@ extern "C" fio_status hss_ulv_solve(hss_ulv_t f, const void *Y, long ldy, void *
 }
 
 extern "C" void hss_ulv_destroy(hss_ulv_t f) { delete f; }
+
+extern "C" void fio_ulv_set_big_node(int rows) { fio::g_ulv_big = rows > 0 ? rows : 256; }

@@ -222,3 +222,11 @@ def test_hss_large_node_path_matches_oracle(n):
     u = ob.apply(f)
     fh, _ = F.approx_solve(B, F.ULV(H), dev(u))
     assert rel(host(fh), osolve.direct_solve2d(ob, fac, u)) < 1e-12
+    # the multi-workgroup basis elimination of the ULV factorization, forced on every level
+    F.set_ulv_big_node(64)
+    try:
+        U2 = F.ULV(H)
+    finally:
+        F.set_ulv_big_node(0)
+    fh2, _ = F.approx_solve(B, U2, dev(u))
+    assert rel(host(fh2), osolve.direct_solve2d(ob, fac, u)) < 1e-12
