@@ -24,6 +24,7 @@ struct hss_ulv_s {
     std::vector<std::vector<long>> yoff, roff;  // rows of a node in its level vector / parent vector
     std::vector<long> rows;                     // rows of the level-l vector (l = 0..Lh)
     fio::DevBuf W;                              // all W slots
+    fio::DevBuf WH;                             // W^* of every node (same offsets), for narrow solves
     fio::DevBuf Linv;                           // m0 x m0
     fio::DevBuf meta;                           // device copies of the per-level tables
     std::vector<size_t> meta_woff, meta_m, meta_k, meta_yoff, meta_roff;   // byte offsets into meta
@@ -576,6 +577,125 @@ __global__ void __launch_bounds__(256) k_ulv_level(LevelArgs a, const double2 *_
     }
 }
 
+// One level of the ULV solve for few right-hand sides on large nodes, in two launches:
+// k_ulv_narrow computes partial products over S slices of the inner dimension, one wave
+// per 64 output rows and slice, lanes on rows, so W (UP) or W^* (DOWN, the stored copy WH)
+// streams coalesced from HBM once; 64-entry pieces of the input vector are staged in LDS
+// and read back as broadcasts.  k_ulv_narrow_sum adds the S partials in a fixed order and
+// scatters the rows like k_ulv_level.  Partial (s, level row, column) at
+// P[(s * rows + row) * 8 + column] for one chunk of 8 columns.
+constexpr int kNarrowCols = 8;
+
+template <bool DOWN>
+__global__ void __launch_bounds__(64) k_ulv_narrow(LevelArgs a, const double2 *__restrict__ WH,
+                                                   const double2 *__restrict__ Yin, long ldin,
+                                                   const double2 *__restrict__ Bh, long ldb,
+                                                   const double2 *__restrict__ Ylo, long ldlo, int nrhs, int c0,
+                                                   int S, long rows, double2 *__restrict__ P) {
+    __shared__ double2 xs[64][kNarrowCols];
+    const int node = blockIdx.y, sl = blockIdx.z;
+    const int m = a.m[node], k = a.k[node];
+    const int r0 = blockIdx.x * 64;
+    if (r0 >= m) return;
+    const int r = r0 + threadIdx.x;
+    const int nc = nrhs - c0 < kNarrowCols ? nrhs - c0 : kNarrowCols;
+    const double2 *Wn = (DOWN ? WH : a.W) + a.woff[node];
+    const long yo = a.yoff[node], ro = a.roff[node];
+    const int len = (m + S - 1) / S;
+    const int l0 = sl * len, l1 = l0 + len < m ? l0 + len : m;
+    double2 acc[kNarrowCols];
+#pragma unroll
+    for (int c = 0; c < kNarrowCols; ++c) acc[c] = zc(0.0, 0.0);
+    for (int lb = l0; lb < l1; lb += 64) {
+        const int nl = l1 - lb < 64 ? l1 - lb : 64;
+        __syncthreads();
+        {
+            const int l = lb + threadIdx.x;
+            for (int c = 0; c < kNarrowCols; ++c) {
+                double2 v = zc(0.0, 0.0);
+                if (threadIdx.x < nl && c < nc) {
+                    if (DOWN)
+                        v = l < k ? Bh[(yo + l) + (size_t)(c0 + c) * ldb] : Ylo[(ro + l - k) + (size_t)(c0 + c) * ldlo];
+                    else
+                        v = Yin[(yo + l) + (size_t)(c0 + c) * ldin];
+                }
+                xs[threadIdx.x][c] = v;
+            }
+        }
+        __syncthreads();
+        if (r < m) {
+            for (int j = 0; j < nl; ++j) {
+                const double2 w = Wn[r + (size_t)(lb + j) * m];
+#pragma unroll
+                for (int c = 0; c < kNarrowCols; ++c) cfma(acc[c], w, xs[j][c]);
+            }
+        }
+    }
+    if (r < m) {
+        double2 *pp = P + ((size_t)sl * rows + yo + r) * kNarrowCols;
+#pragma unroll
+        for (int c = 0; c < kNarrowCols; ++c) pp[c] = acc[c];
+    }
+}
+
+template <bool DOWN>
+__global__ void k_ulv_narrow_sum(LevelArgs a, const double2 *__restrict__ P, int S, long rows, int nrhs, int c0,
+                                 double2 *__restrict__ Bh, long ldb, double2 *__restrict__ Ylo, long ldlo,
+                                 double2 *__restrict__ Yout, long ldout) {
+    const int node = blockIdx.y;
+    const int m = a.m[node], k = a.k[node];
+    const long yo = a.yoff[node], ro = a.roff[node];
+    const int nc = nrhs - c0 < kNarrowCols ? nrhs - c0 : kNarrowCols;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m * kNarrowCols; e += gridDim.x * blockDim.x) {
+        const int r = e / kNarrowCols, c = e % kNarrowCols;
+        if (c >= nc) continue;
+        double2 v = zc(0.0, 0.0);
+        for (int q = 0; q < S; ++q) v = cadd(v, P[((size_t)q * rows + yo + r) * kNarrowCols + c]);
+        if (DOWN)
+            Yout[(yo + r) + (size_t)(c0 + c) * ldout] = v;
+        else if (r < k)
+            Bh[(yo + r) + (size_t)(c0 + c) * ldb] = v;
+        else
+            Ylo[(ro + r - k) + (size_t)(c0 + c) * ldlo] = v;
+    }
+}
+
+// WH = W^* for every node of a level
+__global__ void k_ulv_wh(const double2 *W, double2 *WH, const size_t *woff, const int *msz) {
+    const int node = blockIdx.y, m = msz[node];
+    const double2 *Wn = W + woff[node];
+    double2 *Hn = WH + woff[node];
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)m * m; e += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(e % m), j = (int)(e / m);
+        const double2 v = Wn[j + (size_t)i * m];
+        Hn[e] = zc(v.x, -v.y);
+    }
+}
+
+// levels whose largest node has at least this many rows use k_ulv_narrow for <= 16 columns
+constexpr int kNarrowMinRows = 128, kNarrowMaxCols = 16;
+
+// inner-dimension slices of a level: about 2048 waves in flight, at least 64 entries per slice,
+// and at most 4 N partial rows
+static int narrow_slices(long rows, int mmax) {
+    const long waves = (rows + 63) / 64;
+    long S = (2048 + waves - 1) / waves;
+    if (S > mmax / 64) S = mmax / 64;
+    if (S > 32) S = 32;
+    return S < 1 ? 1 : (int)S;
+}
+
+static size_t narrow_part_rows(const hss_ulv_s *f) {
+    size_t mx = 0;
+    for (int l = 1; l <= f->Lh; ++l) {
+        int mm = 0;
+        for (int v : f->m[l]) mm = v > mm ? v : mm;
+        const size_t need = (size_t)narrow_slices(f->rows[l], mm) * f->rows[l];
+        mx = need > mx ? need : mx;
+    }
+    return mx;
+}
+
 template <typename T> static size_t put(std::vector<char> &blob, const std::vector<T> &v) {
     size_t off = (blob.size() + 255) & ~(size_t)255;
     blob.resize(off + v.size() * sizeof(T) + 8);
@@ -773,6 +893,24 @@ static fio_status factor_impl(hss_s *h, hipStream_t s, hss_ulv_t *out) {
         }
         f->meta.alloc(blob.size() + 16);
         FIO_HIP(hipMemcpy(f->meta.p, blob.data(), blob.size(), hipMemcpyHostToDevice));
+        // W^* copies for the levels that the narrow solve kernel serves
+        bool any = false;
+        for (int l = 1; l <= Lh; ++l)
+            for (int v : f->m[l]) any = any || v >= kNarrowMinRows;
+        if (any) {
+            f->WH.alloc(wtot * sizeof(double2) + 16);
+            const char *mb = f->meta.as<char>();
+            for (int l = 1; l <= Lh; ++l) {
+                int ml = 0;
+                for (int v : f->m[l]) ml = v > ml ? v : ml;
+                if (ml < kNarrowMinRows) continue;
+                k_ulv_wh<<<dim3(64, (unsigned)f->m[l].size()), 256, 0, s>>>(
+                    f->W.as<double2>(), f->WH.as<double2>(), (const size_t *)(mb + f->meta_woff[l]),
+                    (const int *)(mb + f->meta_m[l]));
+            }
+            FIO_HIP(hipGetLastError());
+            FIO_HIP(hipStreamSynchronize(s));
+        }
         return FIO_OK;
     });
     if (st != FIO_OK) {
@@ -789,7 +927,9 @@ static size_t ulv_ws_bytes(const hss_ulv_s *f, int nrhs) {
     for (int l = 0; l < f->Lh; ++l) rows += f->rows[l];
     for (int l = 1; l <= f->Lh; ++l) rows += f->rows[l];
     rows += f->m0;
-    return (rows + 8 * (size_t)(f->Lh + 2)) * (size_t)nrhs * sizeof(double2) + 4096;
+    size_t part = 0;
+    if (f->WH.p && nrhs <= kNarrowMaxCols) part = narrow_part_rows(f) * kNarrowCols;   // entries
+    return (rows + 8 * (size_t)(f->Lh + 2)) * (size_t)nrhs * sizeof(double2) + part * sizeof(double2) + 8192;
 }
 
 void ulv_solve_impl(hss_ulv_s *f, const double2 *Y, long ldy, double2 *C, long ldc, int nrhs, void *ws,
@@ -824,16 +964,37 @@ void ulv_solve_impl(hss_ulv_s *f, const double2 *Y, long ldy, double2 *C, long l
         for (int x : f->m[l]) v = x > v ? x : v;
         return v;
     };
+    // few right-hand sides on large nodes: rows on lanes, W streamed once per 8 columns
+    // (k_ulv_narrow), over S slices of the inner dimension so that about 2048 waves stream
+    auto narrow = [&](int l) { return nrhs <= kNarrowMaxCols && f->WH.p && mmax(l) >= kNarrowMinRows; };
+    auto slices = [&](int l) { return narrow_slices(f->rows[l], mmax(l)); };
+    double2 *part = nullptr;
+    if (f->WH.p && nrhs <= kNarrowMaxCols) {
+        part = base + off;
+        off += narrow_part_rows(f) * kNarrowCols;
+    }
     // bottom-up
     for (int l = Lh; l >= 1; --l) {
         const int tilesM = (mmax(l) + 31) / 32;
         if (tilesM == 0) continue;
         const double2 *yin = (l == Lh) ? Y : Yl[l];
         long ldin = (l == Lh) ? ldy : f->rows[l];
-        dim3 grid(tilesM * tilesN, f->m[l].size());
         FIO_TIMED("ulv_up", s);
-        k_ulv_level<false><<<grid, 256, 0, s>>>(args(l), yin, ldin, Bl[l], f->rows[l], Yl[l - 1], f->rows[l - 1],
-                                                nullptr, 0, nrhs, tilesN);
+        if (narrow(l)) {
+            const int S = slices(l);
+            for (int c0 = 0; c0 < nrhs; c0 += kNarrowCols) {
+                dim3 g((unsigned)((mmax(l) + 63) / 64), (unsigned)f->m[l].size(), (unsigned)S);
+                k_ulv_narrow<false><<<g, 64, 0, s>>>(args(l), nullptr, yin, ldin, nullptr, 0, nullptr, 0, nrhs, c0,
+                                                     S, f->rows[l], part);
+                dim3 g2((unsigned)((mmax(l) * kNarrowCols + 255) / 256), (unsigned)f->m[l].size());
+                k_ulv_narrow_sum<false><<<g2, 256, 0, s>>>(args(l), part, S, f->rows[l], nrhs, c0, Bl[l], f->rows[l],
+                                                           Yl[l - 1], f->rows[l - 1], nullptr, 0);
+            }
+        } else {
+            dim3 grid(tilesM * tilesN, f->m[l].size());
+            k_ulv_level<false><<<grid, 256, 0, s>>>(args(l), yin, ldin, Bl[l], f->rows[l], Yl[l - 1], f->rows[l - 1],
+                                                    nullptr, 0, nrhs, tilesN);
+        }
     }
     // root: Y0 <- Linv^* Linv Y0
     if (f->m0 > 0) {
@@ -849,10 +1010,22 @@ void ulv_solve_impl(hss_ulv_s *f, const double2 *Y, long ldy, double2 *C, long l
         if (tilesM == 0) continue;
         double2 *yout = (l == Lh) ? C : Yl[l];
         long ldout = (l == Lh) ? ldc : f->rows[l];
-        dim3 grid(tilesM * tilesN, f->m[l].size());
         FIO_TIMED("ulv_down", s);
-        k_ulv_level<true><<<grid, 256, 0, s>>>(args(l), nullptr, 0, Bl[l], f->rows[l], Yl[l - 1], f->rows[l - 1],
-                                               yout, ldout, nrhs, tilesN);
+        if (narrow(l)) {
+            const int S = slices(l);
+            for (int c0 = 0; c0 < nrhs; c0 += kNarrowCols) {
+                dim3 g((unsigned)((mmax(l) + 63) / 64), (unsigned)f->m[l].size(), (unsigned)S);
+                k_ulv_narrow<true><<<g, 64, 0, s>>>(args(l), f->WH.as<double2>(), nullptr, 0, Bl[l], f->rows[l],
+                                                    Yl[l - 1], f->rows[l - 1], nrhs, c0, S, f->rows[l], part);
+                dim3 g2((unsigned)((mmax(l) * kNarrowCols + 255) / 256), (unsigned)f->m[l].size());
+                k_ulv_narrow_sum<true><<<g2, 256, 0, s>>>(args(l), part, S, f->rows[l], nrhs, c0, nullptr, 0,
+                                                          nullptr, 0, yout, ldout);
+            }
+        } else {
+            dim3 grid(tilesM * tilesN, f->m[l].size());
+            k_ulv_level<true><<<grid, 256, 0, s>>>(args(l), nullptr, 0, Bl[l], f->rows[l], Yl[l - 1], f->rows[l - 1],
+                                                   yout, ldout, nrhs, tilesN);
+        }
     }
     FIO_HIP(hipGetLastError());
 }
