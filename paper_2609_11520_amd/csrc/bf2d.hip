@@ -266,6 +266,7 @@ template <typename T> struct K2Args {
     int nrhs, ldc;          // right-hand sides, coefficient row stride
     int nb, nsplit;         // blocks per output, splits of the block range
     int fint;               // frequency-side vectors in Morton order (no index map)
+    long nout;              // output blocks (workgroup rows) of the launch
 };
 
 template <typename C> __device__ __forceinline__ C to_c(double2 v);
@@ -288,9 +289,13 @@ __global__ void __launch_bounds__(128) k2_step(K2Args<T> a) {
     const G2 &g = a.g;
     const int R = rows_of<STEP>(g), CC = cols_of<STEP>(g);
     const int r = threadIdx.x;
-    const long o = blockIdx.x;
-    const int split = blockIdx.y;
-    const int c0 = blockIdx.z * KC;
+    // grid: x = column chunk (fastest, so the chunks of one output block run together and share
+    // its factor blocks through L2), y (+ z) = output block, z = split for the leaf-box sums
+    const bool splitk = STEP == UF || STEP == VA;
+    const long o = splitk ? (long)blockIdx.y : (long)blockIdx.y + (long)blockIdx.z * gridDim.y;
+    const int split = splitk ? (int)blockIdx.z : 0;
+    const int c0 = blockIdx.x * KC;
+    if (o >= a.nout) return;
     const int nc = min(KC, a.nrhs - c0);
     const bool act = r < R;
     C acc[KC];
@@ -339,7 +344,7 @@ __global__ void __launch_bounds__(128) k2_step(K2Args<T> a) {
     if (!act) return;
     if (STEP == UF || STEP == VA) {
         if (a.nsplit > 1) {
-            C *pp = a.part + (((size_t)split * gridDim.x + o) * R + r) * a.ldc + c0;
+            C *pp = a.part + (((size_t)split * a.nout + o) * R + r) * a.ldc + c0;
 #pragma unroll
             for (int c = 0; c < KC; ++c) pp[c] = acc[c];
         } else {
@@ -370,9 +375,11 @@ __global__ void __launch_bounds__(128) k2_leaf_in(K2Args<T> a) {
     const int R = g.q2, CC = g.b2;
     const int r = threadIdx.x;
     const long groups = g.T / G;
-    const long box = blockIdx.x / groups;
-    const long first = (blockIdx.x % groups) * G;
-    const int c0 = blockIdx.z * KC;
+    const long wg = (long)blockIdx.y + (long)blockIdx.z * gridDim.y;   // x = column chunk (fastest)
+    if (wg >= a.nout) return;
+    const long box = wg / groups;
+    const long first = (wg % groups) * G;
+    const int c0 = blockIdx.x * KC;
     const int nc = min(KC, a.nrhs - c0);
     const bool internal = STEP == VF && a.fint;
     for (int e = threadIdx.x; e < CC * KC; e += blockDim.x) {
@@ -429,31 +436,40 @@ __global__ void k_perm2(int n, int L, int to_int, const double2 *X, long ldx, do
         Y[l + c * ldy] = X[m + c * ldx];
 }
 
-constexpr int KC2 = 8;
 
 int nsplit_of(long nb) { return (int)(nb < 16 ? nb : 16); }
 
 // output pairs per workgroup of the leaf-input steps: 8 when the box has that many partners
-template <typename T, int STEP>
-void launch_leaf_in(const K2Args<T> &a, const G2 &g, unsigned chunks, unsigned blk, hipStream_t s) {
-    const unsigned nbox = (unsigned)g.S;
-    if (g.T >= 8)
-        k2_leaf_in<T, KC2, STEP, 8><<<dim3(nbox * (unsigned)(g.T / 8), 1, chunks), blk, 0, s>>>(a);
-    else
-        k2_leaf_in<T, KC2, STEP, 1><<<dim3(nbox * (unsigned)g.T, 1, chunks), blk, 0, s>>>(a);
+// grid for `n` workgroup rows with the column chunks fastest: (chunks, min(n, 32768), rest)
+dim3 grid_rows(unsigned chunks, long n) {
+    const long gy = n < 32768 ? n : 32768;
+    return dim3(chunks, (unsigned)gy, (unsigned)((n + gy - 1) / gy));
 }
 
-template <typename T>
-void apply2(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs, const cpx<T> *F,
-            const cpx<T> *Fa, void *ws, bool fint, hipStream_t s) {
+template <typename T, int KC, int STEP>
+void launch_leaf_in(const K2Args<T> &a_in, const G2 &g, unsigned chunks, unsigned blk, hipStream_t s) {
+    K2Args<T> a = a_in;
+    const long G = g.T >= 8 ? 8 : 1;
+    a.nout = g.S * (g.T / G);
+    if (G == 8)
+        k2_leaf_in<T, KC, STEP, 8><<<grid_rows(chunks, a.nout), blk, 0, s>>>(a);
+    else
+        k2_leaf_in<T, KC, STEP, 1><<<grid_rows(chunks, a.nout), blk, 0, s>>>(a);
+}
+
+// KC columns per workgroup: 8 for few right-hand sides, 16 for wide blocks (the HSS sample
+// blocks), which halves how often the factors stream while the FMAs per factor entry double
+template <typename T, int KC>
+void apply2k(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs, const cpx<T> *F,
+             const cpx<T> *Fa, void *ws, bool fint, hipStream_t s) {
     using C = cpx<T>;
     const G2 g = g2_of(bf);
-    const int ldc = (nrhs + KC2 - 1) / KC2 * KC2;
+    const int ldc = (nrhs + KC - 1) / KC * KC;
     const size_t ncoef = (size_t)bf->N * g.q2 * ldc;
     C *c1 = reinterpret_cast<C *>(ws);
     C *c2 = c1 + ncoef;
     C *part = c2 + ncoef;
-    const unsigned chunks = (unsigned)(ldc / KC2);
+    const unsigned chunks = (unsigned)(ldc / KC);
     const bool f64 = sizeof(T) == 8;
     const unsigned blkq = 64 * ((g.q2 + 63) / 64), blkb = 64 * ((g.b2 + 63) / 64);
     const long NP = bf->N;                            // pairs on either side
@@ -469,19 +485,21 @@ void apply2(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long
             FIO_TIMED(f64 ? "bf2_V_f64" : "bf2_V_f32", s);
             K2Args<T> v = a;
             v.A = V; v.X = X; v.ldx = ldx; v.cout = c1; v.nb = 1; v.nsplit = 1;
-            launch_leaf_in<T, VF>(v, g, chunks, blkq, s);
+            launch_leaf_in<T, KC, VF>(v, g, chunks, blkq, s);
         }
         {
             FIO_TIMED(f64 ? "bf2_M_f64" : "bf2_M_f32", s);
             K2Args<T> m = a;
             m.A = M; m.cin = c1; m.cout = c2; m.nb = (int)g.rr; m.nsplit = 1;
-            k2_step<T, KC2, MF><<<dim3((unsigned)NP, 1, chunks), blkq, 0, s>>>(m);
+            m.nout = NP;
+            k2_step<T, KC, MF><<<grid_rows(chunks, NP), blkq, 0, s>>>(m);
         }
         {
             FIO_TIMED(f64 ? "bf2_U_f64" : "bf2_U_f32", s);
             K2Args<T> u = a;
             u.A = U; u.cin = c2; u.Y = Y; u.ldy = ldy; u.part = part; u.nb = (int)g.T; u.nsplit = nsp;
-            k2_step<T, KC2, UF><<<dim3((unsigned)g.S, nsp, chunks), blkb, 0, s>>>(u);
+            u.nout = g.S;
+            k2_step<T, KC, UF><<<dim3(chunks, (unsigned)g.S, nsp), blkb, 0, s>>>(u);
             if (nsp > 1) {
                 const size_t tot = (size_t)g.S * g.b2 * nrhs;
                 k2_reduce<T><<<grid1d(tot, 256), 256, 0, s>>>(g, part, nsp, g.S, ldc, nrhs, 0, 0, Y, ldy);
@@ -493,19 +511,21 @@ void apply2(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long
             FIO_TIMED(f64 ? "bf2_U_f64" : "bf2_U_f32", s);
             K2Args<T> u = a;
             u.A = Ua; u.X = X; u.ldx = ldx; u.cout = c2; u.nb = 1; u.nsplit = 1;
-            launch_leaf_in<T, UA>(u, g, chunks, blkq, s);
+            launch_leaf_in<T, KC, UA>(u, g, chunks, blkq, s);
         }
         {
             FIO_TIMED(f64 ? "bf2_M_f64" : "bf2_M_f32", s);
             K2Args<T> m = a;
             m.A = Ma; m.cin = c2; m.cout = c1; m.nb = (int)g.rr; m.nsplit = 1;
-            k2_step<T, KC2, MA><<<dim3((unsigned)NP, 1, chunks), blkq, 0, s>>>(m);
+            m.nout = NP;
+            k2_step<T, KC, MA><<<grid_rows(chunks, NP), blkq, 0, s>>>(m);
         }
         {
             FIO_TIMED(f64 ? "bf2_V_f64" : "bf2_V_f32", s);
             K2Args<T> v = a;
             v.A = Va; v.cin = c1; v.Y = Y; v.ldy = ldy; v.part = part; v.nb = (int)g.T; v.nsplit = nsp;
-            k2_step<T, KC2, VA><<<dim3((unsigned)g.S, nsp, chunks), blkb, 0, s>>>(v);
+            v.nout = g.S;
+            k2_step<T, KC, VA><<<dim3(chunks, (unsigned)g.S, nsp), blkb, 0, s>>>(v);
             if (nsp > 1) {
                 const size_t tot = (size_t)g.S * g.b2 * nrhs;
                 k2_reduce<T><<<grid1d(tot, 256), 256, 0, s>>>(g, part, nsp, g.S, ldc, nrhs, 1, a.fint, Y, ldy);
@@ -513,6 +533,15 @@ void apply2(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long
         }
     }
     FIO_HIP(hipGetLastError());
+}
+
+template <typename T>
+void apply2(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs, const cpx<T> *F,
+            const cpx<T> *Fa, void *ws, bool fint, hipStream_t s) {
+    if (nrhs >= 16)
+        apply2k<T, 16>(bf, adj, X, ldx, Y, ldy, nrhs, F, Fa, ws, fint, s);
+    else
+        apply2k<T, 8>(bf, adj, X, ldx, Y, ldy, nrhs, F, Fa, ws, fint, s);
 }
 
 }  // namespace
@@ -527,6 +556,7 @@ fio_status bf2d_plan(const fio_bf_desc *d, fio_bf_s *bf) {
     if (L - d->level_offset > h) return FIO_ERR_UNSUPPORTED;   // transfer levels are not built in 2D
     const int b = (int)(d->n >> h);
     if (b * b > 128) return FIO_ERR_UNSUPPORTED;                // a leaf box must fit one workgroup
+    if (h > 7) return FIO_ERR_UNSUPPORTED;                      // 4^h leaf boxes on one grid axis
     if (d->q * d->q > 128) return FIO_ERR_UNSUPPORTED;
     bf->desc = *d;
     bf->dim = 2;
@@ -553,7 +583,7 @@ fio_status bf2d_plan(const fio_bf_desc *d, fio_bf_s *bf) {
 size_t bf2d_ws_bytes(const fio_bf_s *bf, int nrhs, fio_prec prec) {
     if (prec == FIO_PREC_SPLIT_FP16) return 0;
     const size_t es = prec == FIO_PREC_FP64 ? sizeof(double2) : sizeof(float2);
-    const size_t ldc = (size_t)(nrhs + KC2 - 1) / KC2 * KC2;
+    const size_t ldc = (size_t)(nrhs + 15) / 16 * 16;     // the larger of the two column chunkings
     const size_t T = 1UL << (2 * bf->lc);
     const size_t ns = (size_t)nsplit_of((long)T);
     return (2 * (size_t)bf->N * bf->q * bf->q * ldc + (ns > 1 ? ns * (size_t)bf->N * ldc : 0)) * es;
