@@ -533,10 +533,6 @@ __global__ void k_node_conj_transpose(NodeArgs a) {
     }
 }
 
-
-// Section 3.3 for the two children of every node of level l (one workgroup per child c):
-//   A = the child's diagonal block of D^[l]_parent; B_{a2,a1} = A_21 (written by the first child);
-//   D_c = D_res_c + U_c A U_c^*.
 struct PostArgs {
     const double2 *Dpar;   // parent diagonal blocks (m_par x m_par slots)
     const size_t *dpoff;
@@ -551,16 +547,20 @@ struct PostArgs {
     const size_t *dooff;
     double2 *Bout;         // B of the parents
     const size_t *boff;
-    double2 *tmp;          // scratch, m_ch x r_ch per child
+    double2 *tmp;          // scratch per child: T (m_ch x r_ch), then U_c^* (r_ch x m_ch)
     size_t tstride;
 };
 
-__global__ void __launch_bounds__(1024) k_post(PostArgs a) {
+// Section 3.3 for the two children of every node of level l (one workgroup per child c),
+// around two batched GEMMs over the level:
+//   k_post_prep: B_{a2,a1} = A_21 of the parent's block (written by the first child),
+//                D_c <- D_res_c, and the conjugate transpose U_c^* next to T in the scratch;
+//   GEMMs: T = U_c A (A = the child's diagonal block of D^[l]_parent), D_c += T U_c^*.
+__global__ void __launch_bounds__(1024) k_post_prep(PostArgs a) {
     const int c = blockIdx.x, par = c >> 1, tid = threadIdx.x, nt = blockDim.x;
     const int mp = a.mpar[par], mc = a.mch[c], r = a.rch[c];
     const int r1 = a.rch[par * 2];
     const double2 *Dp = a.Dpar + a.dpoff[par];
-    const int o = (c & 1) ? r1 : 0;                  // the child's block of the parent's D
     if ((c & 1) == 0) {
         const int r2 = a.rch[par * 2 + 1];
         double2 *Bo = a.Bout + a.boff[par];
@@ -570,23 +570,15 @@ __global__ void __launch_bounds__(1024) k_post(PostArgs a) {
         }
     }
     const double2 *Uc = a.Uslot + a.uoff[c];
-    double2 *T = a.tmp + a.tstride * c;
-    // T = U_c A   (mc x r)
-    for (int e = tid; e < mc * r; e += nt) {
-        int i = e % mc, j = e / mc;
-        double2 acc = zc(0.0, 0.0);
-        for (int k = 0; k < r; ++k) cfma(acc, Uc[i + (size_t)k * mc], Dp[(o + k) + (size_t)(o + j) * mp]);
-        T[e] = acc;
+    double2 *UcH = a.tmp + a.tstride * c + (size_t)mc * r;
+    for (int e = tid; e < r * mc; e += nt) {
+        int i = e % r, j = e / r;
+        const double2 u = Uc[j + (size_t)i * mc];
+        UcH[i + (size_t)j * r] = zc(u.x, -u.y);
     }
-    __syncthreads();
     const double2 *Dr = a.Dres + a.droff[c];
     double2 *Do = a.Dout + a.dooff[c];
-    for (int e = tid; e < mc * mc; e += nt) {
-        int i = e % mc, j = e / mc;
-        double2 acc = Dr[e];
-        for (int k = 0; k < r; ++k) cfmac(acc, Uc[j + (size_t)k * mc], T[i + (size_t)k * mc]);
-        Do[e] = acc;
-    }
+    for (int e = tid; e < mc * mc; e += nt) Do[e] = Dr[e];
 }
 
 __global__ void k_sumsq_partial(const double2 *x, size_t n, double *part) {
@@ -954,7 +946,7 @@ static fio_status build_impl(long n, const hss_opts *o, const Sampler &sm, hipSt
                 Dnext.alloc(tot * sizeof(double2) + 16);
                 dout = Dnext.as<double2>();
             }
-            tmp.ensure(tmax * nc * sizeof(double2) + 16);
+            tmp.ensure(2 * tmax * nc * sizeof(double2) + 16);
             std::vector<size_t> bo = h->boff[l];
             DevBuf *d1 = upload(dpoff, s), *d2 = upload(mpar, s), *d3 = upload(h->rank[l + 1], s),
                    *d4 = upload(doff[l + 1], s), *d5 = upload(h->m[l + 1], s), *d6 = upload(h->uoff[l + 1], s),
@@ -974,11 +966,25 @@ static fio_status build_impl(long n, const hss_opts *o, const Sampler &sm, hipSt
             pa.Bout = h->Bbuf.as<double2>();
             pa.boff = d8->as<size_t>();
             pa.tmp = tmp.as<double2>();
-            pa.tstride = tmax;
+            pa.tstride = 2 * tmax;
             int mcmax = 0;
             for (int c = 0; c < nc; ++c) mcmax = h->m[l + 1][c] > mcmax ? h->m[l + 1][c] : mcmax;
-            k_post<<<nc, node_threads(mcmax), 0, s>>>(pa);
+            k_post_prep<<<nc, node_threads(mcmax), 0, s>>>(pa);
             FIO_HIP(hipGetLastError());
+            ZgemmBatch g1, g2;
+            for (int c = 0; c < nc; ++c) {
+                const int par = c >> 1, mc = h->m[l + 1][c], r = h->rank[l + 1][c], mp = mpar[par];
+                if (mc == 0 || r == 0) continue;
+                const int o = (c & 1) ? h->rank[l + 1][par * 2] : 0;
+                double2 *T = tmp.as<double2>() + pa.tstride * c, *UcH = T + (size_t)mc * r;
+                const double2 *Uc = h->Ubuf[l + 1]->as<double2>() + h->uoff[l + 1][c];
+                g1.add(Uc, mc, dpar + dpoff[par] + o + (size_t)o * mp, mp, T, mc, mc, r, r);   // T = U_c A
+                g2.add(T, mc, UcH, r, dout + dooff[c], mc, mc, mc, r);                         // D_c += T U_c^*
+            }
+            g1.upload(s);
+            g2.upload(s);
+            g1.run(false, zc(1.0, 0.0), zc(0.0, 0.0), s);
+            g2.run(false, zc(1.0, 0.0), zc(1.0, 0.0), s);
             FIO_HIP(hipStreamSynchronize(s));
             for (DevBuf *d : {d1, d2, d3, d4, d5, d6, d7, d8}) delete d;
             Dcur.swap(Dnext);

@@ -125,9 +125,8 @@ __global__ void __launch_bounds__(1024) k_ulv_node(FactArgs a) {
     if (m == 0) return;
     double2 *Uw = a.scratch + a.scoff[node];        // m x r working copy, then reflectors
     double2 *Q = Uw + (size_t)m * m;                 // m x m explicit Q
-    double2 *T = Q + (size_t)m * m;                  // m x m: Q^* D, then Dchk
+    double2 *T = Q + (size_t)m * m;                  // m x m: Dchk = Q^* D Q (batched GEMMs)
     const double2 *Uin = a.U + a.uoff[node];
-    const double2 *Din = a.D + a.doff[node];
     double2 *Wm = a.W + a.woff[node];
     if constexpr (PHASE == 0) {
         for (int e = tid; e < m * r; e += nt) Uw[e] = Uin[e];
@@ -406,61 +405,43 @@ struct MergeArgs {
     const size_t *dooff;
     double2 *Uout;           // merged U (m x r_par per parent)
     const size_t *uooff;
-    double2 *tmp;            // r2 x r1 per parent
+    double2 *tmp;            // per parent: T (r2 x r1), then U2(a1)^* (r1 x r1)
     const size_t *toff;
 };
 
-__global__ void __launch_bounds__(1024) k_ulv_merge(MergeArgs a) {
+// Merge, around four batched GEMMs over the parents of the level:
+//   k_ulv_merge_prep: diagonal blocks D22(a1), D22(a2) into D+, and U2(a1)^* next to T;
+//   GEMMs: T = U2(a2) B, lower-left block of D+ = T U2(a1)^*, U+ = diag(U2(a1), U2(a2)) U_parent;
+//   k_ulv_merge_fill: upper-right block of D+ = conj transpose of the lower-left block.
+__global__ void __launch_bounds__(1024) k_ulv_merge_prep(MergeArgs a) {
     const int par = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
     const int c1 = 2 * par, c2 = 2 * par + 1;
     const int r1 = a.rch[c1], r2 = a.rch[c2], m = r1 + r2;
     if (m == 0) return;
     const double2 *Da = a.D22 + a.soff[c1], *Db = a.D22 + a.soff[c2];
-    const double2 *Ua = a.U2 + a.soff[c1], *Ub = a.U2 + a.soff[c2];
-    const double2 *B = a.B + a.boff[par];
-    double2 *T = a.tmp + a.toff[par];
-    // T = U2(a2) B  (r2 x r1); B is r2 x r1
-    for (int e = tid; e < r2 * r1; e += nt) {
-        int i = e % r2, j = e / r2;
-        double2 acc = zc(0.0, 0.0);
-        for (int l = 0; l < r2; ++l) cfma(acc, Ub[i + (size_t)l * r2], B[l + (size_t)j * r2]);
-        T[e] = acc;
-    }
-    __syncthreads();
+    const double2 *Ua = a.U2 + a.soff[c1];
+    double2 *UaH = a.tmp + a.toff[par] + (size_t)r1 * r2;
     double2 *D = a.Dout + a.dooff[par];
-    for (int e = tid; e < m * m; e += nt) {
-        int i = e % m, j = e / m;
-        double2 v;
-        if (i < r1 && j < r1) {
-            v = Da[i + (size_t)j * r1];
-        } else if (i >= r1 && j >= r1) {
-            v = Db[(i - r1) + (size_t)(j - r1) * r2];
-        } else if (i >= r1) {        // lower-left: (T U2(a1)^*)(i - r1, j)
-            double2 acc = zc(0.0, 0.0);
-            for (int l = 0; l < r1; ++l) cfmac(acc, Ua[j + (size_t)l * r1], T[(i - r1) + (size_t)l * r2]);
-            v = acc;
-        } else {                     // upper-right: conj of lower-left (j - r1, i)
-            double2 acc = zc(0.0, 0.0);
-            for (int l = 0; l < r1; ++l) cfmac(acc, Ua[i + (size_t)l * r1], T[(j - r1) + (size_t)l * r2]);
-            v = zc(acc.x, -acc.y);
-        }
-        D[e] = v;
+    for (int e = tid; e < r1 * r1; e += nt) {
+        const int i = e % r1, j = e / r1;
+        D[i + (size_t)j * m] = Da[e];
+        const double2 u = Ua[j + (size_t)i * r1];
+        UaH[e] = zc(u.x, -u.y);
     }
-    if (a.Upar) {
-        const int rp = a.rpar[par];
-        const double2 *Up = a.Upar + a.upoff[par];
-        double2 *Uo = a.Uout + a.uooff[par];
-        for (int e = tid; e < m * rp; e += nt) {
-            int i = e % m, j = e / m;
-            double2 acc = zc(0.0, 0.0);
-            if (i < r1) {
-                for (int l = 0; l <= i; ++l) cfma(acc, Ua[i + (size_t)l * r1], Up[l + (size_t)j * m]);
-            } else {
-                int ii = i - r1;
-                for (int l = 0; l <= ii; ++l) cfma(acc, Ub[ii + (size_t)l * r2], Up[(r1 + l) + (size_t)j * m]);
-            }
-            Uo[e] = acc;
-        }
+    for (int e = tid; e < r2 * r2; e += nt) {
+        const int i = e % r2, j = e / r2;
+        D[(r1 + i) + (size_t)(r1 + j) * m] = Db[e];
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_ulv_merge_fill(MergeArgs a) {
+    const int par = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const int r1 = a.rch[2 * par], r2 = a.rch[2 * par + 1], m = r1 + r2;
+    double2 *D = a.Dout + a.dooff[par];
+    for (int e = tid; e < r1 * r2; e += nt) {
+        const int i = e % r1, j = e / r1;          // upper-right (i, r1 + j) = conj(lower-left (r1 + j, i))
+        const double2 v = D[(r1 + j) + (size_t)i * m];
+        D[i + (size_t)(r1 + j) * m] = zc(v.x, -v.y);
     }
 }
 
@@ -613,7 +594,7 @@ __global__ void __launch_bounds__(64) k_ulv_narrow(LevelArgs a, const double2 *_
             const int l = lb + threadIdx.x;
             for (int c = 0; c < kNarrowCols; ++c) {
                 double2 v = zc(0.0, 0.0);
-                if (threadIdx.x < nl && c < nc) {
+                if ((int)threadIdx.x < nl && c < nc) {
                     if (DOWN)
                         v = l < k ? Bh[(yo + l) + (size_t)(c0 + c) * ldb] : Ylo[(ro + l - k) + (size_t)(c0 + c) * ldlo];
                     else
@@ -823,7 +804,7 @@ static fio_status factor_impl(hss_s *h, hipStream_t s, hss_ulv_t *out) {
                 dooff[j] = dt;
                 dt += (size_t)m * m;
                 toff[j] = tt;
-                tt += (size_t)r1 * r2;
+                tt += (size_t)r1 * r2 + (size_t)r1 * r1;      // T, then U2(a1)^*
                 if (l - 1 >= 1) {
                     rpar[j] = h->rank[l - 1][j];
                     upoff[j] = h->uoff[l - 1][j];
@@ -856,9 +837,32 @@ static fio_status factor_impl(hss_s *h, hipStream_t s, hss_ulv_t *out) {
             ma.uooff = (const size_t *)(m2 + q_uo);
             ma.tmp = tmp.as<double2>();
             ma.toff = (const size_t *)(m2 + q_t);
-            k_ulv_merge<<<np, ulv_threads(mlev), 0, s>>>(ma);
+            k_ulv_merge_prep<<<np, ulv_threads(mlev), 0, s>>>(ma);
             FIO_HIP(hipGetLastError());
-            FIO_HIP(hipStreamSynchronize(s));
+            {
+                ZgemmBatch g1, g2, g3, g4;
+                const double2 *U2b = U2.as<double2>();
+                for (int j = 0; j < np; ++j) {
+                    const int r1 = f->r[l][2 * j], r2 = f->r[l][2 * j + 1], m = r1 + r2, rp = rpar[j];
+                    if (m == 0) continue;
+                    const double2 *Ua = U2b + soff[2 * j], *Ub = U2b + soff[2 * j + 1];
+                    double2 *T = tmp.as<double2>() + toff[j], *UaH = T + (size_t)r1 * r2;
+                    double2 *Dp = Dn.as<double2>() + dooff[j];
+                    g1.add(Ub, r2, h->Bbuf.as<double2>() + boff[j], r2, T, r2, r2, r1, r2);   // T = U2(a2) B
+                    g2.add(T, r2, UaH, r1, Dp + r1, m, r2, r1, r1);                          // lower-left
+                    if (l - 1 >= 1) {
+                        const double2 *Up = h->Ubuf[l - 1]->as<double2>() + upoff[j];
+                        double2 *Uo = Un.as<double2>() + uooff[j];
+                        g3.add(Ua, r1, Up, m, Uo, m, r1, rp, r1);                            // rows of a1
+                        g4.add(Ub, r2, Up + r1, m, Uo + r1, m, r2, rp, r2);                  // rows of a2
+                    }
+                }
+                for (ZgemmBatch *g : {&g1, &g2, &g3, &g4}) g->upload(s);
+                for (ZgemmBatch *g : {&g1, &g2, &g3, &g4}) g->run(false, zc(1.0, 0.0), zc(0.0, 0.0), s);
+                k_ulv_merge_fill<<<np, ulv_threads(mlev), 0, s>>>(ma);
+                FIO_HIP(hipGetLastError());
+                FIO_HIP(hipStreamSynchronize(s));   // the descriptor lists are released here
+            }
             int fail = 0;
             FIO_HIP(hipMemcpy(&fail, failb.p, sizeof(int), hipMemcpyDeviceToHost));
             if (fail) throw Err{FIO_ERR_NOT_HPD};
