@@ -445,26 +445,89 @@ __global__ void __launch_bounds__(1024) k_ulv_merge_fill(MergeArgs a) {
     }
 }
 
-// Root: Cholesky of D+ and the explicit inverse Linv of the lower factor.
-__global__ void __launch_bounds__(1024) k_ulv_root(double2 *D, int m, double2 *Linv, int *fail) {
+// Root: Cholesky of D+ and the explicit inverse Linv of the lower factor, blocked by
+// kRootBlock columns: the diagonal blocks and the triangular solves run in small kernels,
+// the trailing updates of the Cholesky and of the inverse as GEMMs over the whole GPU.
+constexpr int kRootBlock = 64;
+
+__global__ void __launch_bounds__(256) k_root_diag(double2 *D, int m, int k0, int kb, int *fail) {
     __shared__ double sh[16];
     __shared__ int s_flag;
-    if (!wg_potrf(D, m, m, sh, &s_flag)) {
+    if (!wg_potrf(D + k0 + (size_t)k0 * m, m, kb, sh, &s_flag))
         if (threadIdx.x == 0) atomicAdd(fail, 1);
-        return;
-    }
-    // Linv column c: solve L x = e_c by forward substitution
-    for (int c = threadIdx.x; c < m; c += blockDim.x) {
-        for (int i = 0; i < m; ++i) {
-            double2 acc = zc(i == c ? 1.0 : 0.0, 0.0);
-            for (int l = c; l < i; ++l) {
-                double2 t = cmul(D[i + (size_t)l * m], Linv[l + (size_t)c * m]);
-                acc = csub(acc, t);
-            }
-            double d = D[i + (size_t)i * m].x;
-            Linv[i + (size_t)c * m] = i < c ? zc(0.0, 0.0) : zc(acc.x / d, acc.y / d);
+}
+
+// rows i >= k0 + kb of the block column: x L_kk^* = a (forward over the kb columns)
+__global__ void k_root_panel(double2 *D, int m, int k0, int kb) {
+    const int i = k0 + kb + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    for (int j = 0; j < kb; ++j) {
+        double2 acc = D[i + (size_t)(k0 + j) * m];
+        for (int l = 0; l < j; ++l) {
+            const double2 x = D[i + (size_t)(k0 + l) * m], Ljl = D[(k0 + j) + (size_t)(k0 + l) * m];
+            acc.x -= x.x * Ljl.x + x.y * Ljl.y;       // acc -= x conj(Ljl)
+            acc.y -= x.y * Ljl.x - x.x * Ljl.y;
         }
+        const double d = D[(k0 + j) + (size_t)(k0 + j) * m].x;
+        D[i + (size_t)(k0 + j) * m] = zc(acc.x / d, acc.y / d);
     }
+}
+
+// PH (kb x rest) = panel^* of D rows k0+kb.., columns k0..k0+kb
+__global__ void k_root_ct(const double2 *D, int m, int k0, int kb, double2 *PH) {
+    const int rest = m - k0 - kb;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)rest * kb; e += (long)gridDim.x * blockDim.x) {
+        const int j = (int)(e % kb), i = (int)(e / kb);
+        const double2 v = D[(k0 + kb + i) + (size_t)(k0 + j) * m];
+        PH[j + (size_t)i * kb] = zc(v.x, -v.y);
+    }
+}
+
+__global__ void k_root_clear_upper_and_eye(double2 *D, double2 *X, int m) {
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)m * m; e += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(e % m), j = (int)(e / m);
+        if (j > i) D[e] = zc(0.0, 0.0);
+        X[e] = zc(i == j ? 1.0 : 0.0, 0.0);
+    }
+}
+
+// rows k0..k0+kb of X <- L_kk^{-1} rows k0..k0+kb of X, one lane per column
+__global__ void k_root_fwd(const double2 *D, double2 *X, int m, int k0, int kb) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= m) return;
+    for (int j = 0; j < kb; ++j) {
+        double2 acc = X[(k0 + j) + (size_t)c * m];
+        for (int l = 0; l < j; ++l) acc = csub(acc, cmul(D[(k0 + j) + (size_t)(k0 + l) * m], X[(k0 + l) + (size_t)c * m]));
+        const double d = D[(k0 + j) + (size_t)(k0 + j) * m].x;
+        X[(k0 + j) + (size_t)c * m] = zc(acc.x / d, acc.y / d);
+    }
+}
+
+static void ulv_root_factor(double2 *D, int m, double2 *Linv, int *fail, hipStream_t s) {
+    const int nb = kRootBlock;
+    DevBuf ph((size_t)nb * m * sizeof(double2) + 16);
+    for (int k0 = 0; k0 < m; k0 += nb) {
+        const int kb = m - k0 < nb ? m - k0 : nb, rest = m - k0 - kb;
+        k_root_diag<<<1, 256, 0, s>>>(D, m, k0, kb, fail);
+        if (rest == 0) break;
+        k_root_panel<<<(rest + 255) / 256, 256, 0, s>>>(D, m, k0, kb);
+        k_root_ct<<<64, 256, 0, s>>>(D, m, k0, kb, ph.as<double2>());
+        // trailing update D22 -= P P^* (the whole square; only the lower triangle is used)
+        ZgemmDesc d{D + (k0 + kb) + (size_t)k0 * m, ph.as<double2>(), D + (k0 + kb) + (size_t)(k0 + kb) * m,
+                    rest, rest, kb, m, kb, m};
+        zgemm_one(d, false, zc(-1.0, 0.0), zc(1.0, 0.0), s);
+    }
+    k_root_clear_upper_and_eye<<<256, 256, 0, s>>>(D, Linv, m);
+    // Linv: blocked forward substitution of L X = I
+    for (int k0 = 0; k0 < m; k0 += nb) {
+        const int kb = m - k0 < nb ? m - k0 : nb, rest = m - k0 - kb;
+        k_root_fwd<<<(m + 255) / 256, 256, 0, s>>>(D, Linv, m, k0, kb);
+        if (rest == 0) break;
+        ZgemmDesc d{D + (k0 + kb) + (size_t)k0 * m, Linv + k0, Linv + (k0 + kb), rest, m, kb, m, m, m};
+        zgemm_one(d, false, zc(-1.0, 0.0), zc(1.0, 0.0), s);
+    }
+    FIO_HIP(hipGetLastError());
+    FIO_HIP(hipStreamSynchronize(s));     // the panel buffer is released here
 }
 
 // One level of the ULV solve.  UP: z = W y_tau, rows < k to Bh, rows >= k to the parent's
@@ -874,9 +937,7 @@ static fio_status factor_impl(hss_s *h, hipStream_t s, hss_ulv_t *out) {
             uin_off = uooff;
         }
         if (f->m0 > 0) {
-            k_ulv_root<<<1, ulv_threads(f->m0), 0, s>>>(Dcur.as<double2>(), f->m0, f->Linv.as<double2>(), failb.as<int>());
-            FIO_HIP(hipGetLastError());
-            FIO_HIP(hipStreamSynchronize(s));
+            ulv_root_factor(Dcur.as<double2>(), f->m0, f->Linv.as<double2>(), failb.as<int>(), s);
             int fail = 0;
             FIO_HIP(hipMemcpy(&fail, failb.p, sizeof(int), hipMemcpyDeviceToHost));
             if (fail) throw Err{FIO_ERR_NOT_HPD};
