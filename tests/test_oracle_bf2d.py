@@ -139,3 +139,30 @@ def test_paper_ecbf_2d_64():
     y = B.apply(f)[rows]
     e = np.linalg.norm(y - Kr @ f) / np.linalg.norm(Kr @ f)
     assert paper / 4 < e < paper * 4
+
+
+def test_morton_frequency_wrapper_and_2d_solve():
+    """The 2D solve composition: K~ with Morton-ordered frequencies, HSS of K~^*K~ in that order,
+    f^ mapped back to user order; refinement and PCG converge to f (Sec. 4.1, Sec. 5.3)."""
+    import fio_inputs as fi
+    from oracle import solve as osolve, ulv as oulv
+    n = 16
+    B = bf2d.BF2D(n, 9, f2.PHASE2_ANISO16)
+    mf = osolve.MortonFrequencies(B)
+    rng = np.random.default_rng(7)
+    x = cgauss(rng, n * n, 2)
+    assert np.array_equal(mf.apply(f2.to_internal(x, n)), B.apply(x))
+    assert np.array_equal(f2.to_user(mf.apply_adj(x), n), B.apply_adj(x))
+    h = osolve.build_hss_for_bf2d(B, lambda l, r, c: fi.omega(1002, l, r, c), 1e-3, p=10)
+    fac = oulv.factor(h)
+    f = fi.rhs(0, n * n, 2)
+    u = B.apply(f)
+    fd = osolve.direct_solve2d(B, fac, u)
+    assert 1e-7 < osolve.rel_err(fd, f) < 5e-2
+    fr, hist = osolve.refine(mf, fac, u, 4)
+    assert hist[-1] < 1e-12
+    assert osolve.col_rel_err(f2.to_user(fr, n), f) < 1e-10
+    fp, it = osolve.pcg(mf, fac, u[:, 0], tol=1e-12)
+    # the paper's preconditioned iteration counts in 2D are 5-6 (Sec. 5.3, iterative table)
+    assert it <= 8
+    assert osolve.rel_err(f2.to_user(fp, n), f[:, 0]) < 1e-10
