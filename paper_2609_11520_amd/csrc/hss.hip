@@ -315,7 +315,9 @@ struct BigArgs {
     int *done;             // 1 once the node's QRCP has stopped
 };
 
-constexpr int kBigChunk = 64;      // columns (or rows) per workgroup of the apply kernels
+// columns (or rows) per workgroup of the apply kernels, four lanes each: small workgroups, so
+// that the few large nodes of a level still spread over most of the GPU
+constexpr int kBigChunk = 16, kBigThreads = 4 * kBigChunk;
 
 __global__ void k_big_init(BigArgs b) {
     const NodeArgs &a = b.n;
@@ -631,9 +633,9 @@ static void basis_big(const NodeArgs &na, const std::vector<int> &ms, int nn, in
     // full Householder QR of Omega_tau^* (s x m), then Z = Y_tau H_0 ... H_{m-1}
     for (int j = 0; j < mmax; ++j) {
         k_big_house_A<<<dim3(1, y), 1024, 0, s>>>(b, j);
-        if (mmax - 1 - j > 0) k_big_left_A<<<dim3(cdiv(mmax - 1 - j, kBigChunk), y), 256, 0, s>>>(b, j);
+        if (mmax - 1 - j > 0) k_big_left_A<<<dim3(cdiv(mmax - 1 - j, kBigChunk), y), kBigThreads, 0, s>>>(b, j);
     }
-    for (int j = 0; j < mmax; ++j) k_big_right_Z<<<dim3(cdiv(mmax, kBigChunk), y), 256, 0, s>>>(b, j);
+    for (int j = 0; j < mmax; ++j) k_big_right_Z<<<dim3(cdiv(mmax, kBigChunk), y), kBigThreads, 0, s>>>(b, j);
     FIO_HIP(hipGetLastError());
     if (!root) {
         // QRCP of W = Z[:, m:s]; every 32 steps the host stops once every node has stopped
@@ -649,9 +651,9 @@ static void basis_big(const NodeArgs &na, const std::vector<int> &ms, int nn, in
         const int nwmax = sl - mmin;
         std::vector<int> hd(nn);
         for (int j = 0; j < kcap; ++j) {
-            k_big_norms<<<dim3(cdiv(nwmax - j, kBigChunk), y), 256, 0, s>>>(b, j);
+            k_big_norms<<<dim3(cdiv(nwmax - j, kBigChunk), y), kBigThreads, 0, s>>>(b, j);
             k_big_pivot<<<dim3(1, y), 1024, 0, s>>>(b, j);
-            if (nwmax - j - 1 > 0) k_big_left_W<<<dim3(cdiv(nwmax - j - 1, kBigChunk), y), 256, 0, s>>>(b, j);
+            if (nwmax - j - 1 > 0) k_big_left_W<<<dim3(cdiv(nwmax - j - 1, kBigChunk), y), kBigThreads, 0, s>>>(b, j);
             if ((j & 31) == 31) {
                 FIO_HIP(hipMemcpyAsync(hd.data(), done.p, nn * sizeof(int), hipMemcpyDeviceToHost, s));
                 FIO_HIP(hipStreamSynchronize(s));
@@ -667,7 +669,7 @@ static void basis_big(const NodeArgs &na, const std::vector<int> &ms, int nn, in
         for (int v : rk) rmax = v > rmax ? v : rmax;
         // U = H_0 ... H_{r-1} [I_r; 0]
         k_big_uinit<<<dim3(64, y), 256, 0, s>>>(b);
-        for (int j = rmax - 1; j >= 0; --j) k_big_left_U<<<dim3(cdiv(rmax, kBigChunk), y), 256, 0, s>>>(b, j);
+        for (int j = rmax - 1; j >= 0; --j) k_big_left_U<<<dim3(cdiv(rmax, kBigChunk), y), kBigThreads, 0, s>>>(b, j);
     }
     k_big_tsolve<<<dim3(cdiv(mmax, 256), y), 256, 0, s>>>(b);
     if (root) k_big_root_out<<<dim3(64, y), 256, 0, s>>>(b);

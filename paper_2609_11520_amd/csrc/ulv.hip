@@ -266,7 +266,7 @@ struct UlvBig {
     double *tau;            // kUlvMaxM per node
 };
 
-constexpr int kUlvChunk = 64;
+constexpr int kUlvChunk = 16, kUlvThreads = 4 * kUlvChunk;   // columns per workgroup, four lanes each
 
 __global__ void k_ubig_init(UlvBig b) {
     const FactArgs &a = b.f;
@@ -380,10 +380,10 @@ static void ulv_phase0_big(const FactArgs &fa, int nn, int mlev, int rmax, hipSt
     for (int t = 0; t < rmax; ++t) {
         k_ubig_house<<<dim3(1, y), 1024, 0, s>>>(b, t);
         const int ncol = rmax - 1 - t;     // an upper bound of every node's remaining columns
-        if (ncol > 0) k_ubig_left<<<dim3((unsigned)((ncol + kUlvChunk - 1) / kUlvChunk), y), 256, 0, s>>>(b, t);
+        if (ncol > 0) k_ubig_left<<<dim3((unsigned)((ncol + kUlvChunk - 1) / kUlvChunk), y), kUlvThreads, 0, s>>>(b, t);
     }
     for (int t = 0; t < rmax; ++t)
-        k_ubig_q<<<dim3((unsigned)((mlev + kUlvChunk - 1) / kUlvChunk), y), 256, 0, s>>>(b, t);
+        k_ubig_q<<<dim3((unsigned)((mlev + kUlvChunk - 1) / kUlvChunk), y), kUlvThreads, 0, s>>>(b, t);
     k_ubig_u2<<<dim3(64, y), 256, 0, s>>>(b);
     FIO_HIP(hipGetLastError());
     FIO_HIP(hipStreamSynchronize(s));   // the reflector scalars are released here
