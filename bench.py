@@ -11,9 +11,11 @@ the relative error of every column of f^ against f is checked after the timed
 region and must be below 1e-8:
   fp64  : K~^* and K~ applied in FP64;
   mixed : K~^* applied in FP32 (FP32 factors and coefficients), residual K~ f and
-          the ULV solve in FP64.
-`value` is the mixed path's RHS/s (64 / seconds per step); the FP64 path is
-reported beside it.  Offline work (BF, HSS and ULV construction) happens before
+          the ULV solve in FP64;
+  split16: as mixed, with the transfer factors of K~^* applied on the matrix cores
+          in split FP16 (hi + lo halves, FP32 accumulation).
+`value` is the faster mixed path's RHS/s (64 / seconds per step; `config.mixed_variant`
+names it); the FP64 path and the other mixed path are reported beside it.  Offline work (BF, HSS and ULV construction) happens before
 the timed region; inputs are resident in HBM when it starts.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
@@ -30,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP16_MFMA_PEAK_TFLOPS = 2500.0 # MI355X dense FP16 matrix (no sparsity)
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector
 # FP32 vector without packed-FP32 instructions (which every kernel here is compiled without):
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz; the 157.3 TFLOP/s datasheet figure
@@ -103,6 +106,16 @@ def kernel_model(name, n, q, k):
     M); per group and column 4 quadrants of q complex scalings, a real q x q product and q complex
     multiply-adds (6q + 4q^2 + 8q flops each), plus 8 q^2 flops per pair for M."""
     es = 16 if name.endswith("f64") else 8
+    if name == "bf_split16":
+        # one split pass: FP32 coefficients read and written once, the hi/lo block planes of
+        # every group of each level (2880 bytes), the FP32 middle blocks on the pass that applies
+        # M; per group and column three real 36 x 36 products (the complex 18 x 18 block)
+        plan = pass_plan(n)
+        byts = flops = 0.0
+        for kl, epi in plan:
+            byts += 2 * n * q * k * 8 + kl * (n // 2) * 2880 + (n * q * q * 8 if epi else 0)
+            flops += kl * (n // 2) * k * 3 * 2 * (4 * q) ** 2
+        return byts / len(plan), flops / len(plan)
     if name.startswith("bf_struct"):
         plan = pass_plan(n)
         byts = flops = 0.0
@@ -379,7 +392,7 @@ def main():
         print(json.dumps({"workload_2d": w2d}), flush=True)
         return
     t = time.perf_counter()
-    B = F.BF(n, q, 2.0 / 16, 1.0 / 16, precs=(F.FIO_PREC_FP64, F.FIO_PREC_FP32))
+    B = F.BF(n, q, 2.0 / 16, 1.0 / 16, precs=(F.FIO_PREC_FP64, F.FIO_PREC_FP32, F.FIO_PREC_SPLIT_FP16))
     sync()
     t_bf = time.perf_counter() - t
     t = time.perf_counter()
@@ -402,7 +415,8 @@ def main():
     results = {}
     kernel_stats = {}
     checked = {}
-    for name, prec in (("fp64", F.FIO_PREC_FP64), ("mixed", F.FIO_PREC_FP32)):
+    for name, prec in (("fp64", F.FIO_PREC_FP64), ("mixed", F.FIO_PREC_FP32),
+                       ("split16", F.FIO_PREC_SPLIT_FP16)):
         out = F.empty(n, k)
         ws = torch.empty(F.solve_workspace_size(B, U, k, F.FIO_SOLVE_IR, prec, a.rel_res, 6), dtype=torch.uint8,
                          device=dev)
@@ -487,8 +501,10 @@ def main():
                       "rel_res": info.rel_res, "max_col_rel_err": e}
     log("pcg", json.dumps(pcg))
 
-    # roofline of the dominant kernel of the headline (mixed) path
-    ks = kernel_stats["mixed"]
+    # the headline mixed path: the faster of the two low-precision variants
+    head = "split16" if results["split16"]["value"] > results["mixed"]["value"] else "mixed"
+    # roofline of the dominant kernel of the headline path
+    ks = kernel_stats[head]
     dom = max(ks, key=lambda kn: ks[kn][1])
     cnt, tot = ks[dom]
     avg_ms = tot / cnt
@@ -497,6 +513,8 @@ def main():
     if model:
         byts, flops = model
         peak_f = FP64_PEAK_TFLOPS if dom.endswith("f64") else FP32_PEAK_TFLOPS
+        if dom == "bf_split16":
+            peak_f = FP16_MFMA_PEAK_TFLOPS
         t_mem = byts / (HBM_PEAK_GBS * 1e9)
         t_alu = flops / (peak_f * 1e12)
         if t_mem >= t_alu:
@@ -505,7 +523,8 @@ def main():
                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": stored_traffic(dom)}
         else:
             ach = flops / (avg_ms * 1e-3) / 1e12
-            roof = {"bound": "alu", "achieved": round(ach, 2), "peak": peak_f, "unit": "TFLOP/s",
+            roof = {"bound": "mfma" if dom == "bf_split16" else "alu", "achieved": round(ach, 2), "peak": peak_f,
+                    "unit": "TFLOP/s",
                     "frac": round(ach / peak_f, 4), "traffic": stored_traffic(dom)}
         roof.update({"kernel": dom, "avg_launch_ms": round(avg_ms, 4), "launches": cnt,
                      "algorithmic_bytes_per_launch": int(byts), "algorithmic_flops_per_launch": float(flops)})
@@ -529,20 +548,21 @@ def main():
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(n, q, k, results["fp64"]["ir_steps"])
 
-    mixed = results["mixed"]
+    mixed = results[head]
     for nm, r in results.items():
         if r["max_col_rel_err"] > 1e-8:
             log("ERROR: %s path missed rel err 1e-8: %g" % (nm, r["max_col_rel_err"]))
     line = {
         "metric": METRIC, "value": round(mixed["value"], 2), "unit": "RHS/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(mixed["ms_per_step"], 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "fp32+fp64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp16x2+fp32+fp64" if head == "split16" else "fp32+fp64",
+        "data": "synthetic",
         "config": {"workload": "1D FIO N=2^%d, c(x)=(2+sin 2pi x)/16, q=%d, HSS tol %g, p=10, %d RHS, "
                                "refinement steps calibrated to rel residual %g" % (int(np.log2(n)), q, a.hss_tol, k,
                                                                                     a.rel_res),
-                   "n": n, "nrhs": k, "q": q, "hss_tol": a.hss_tol,
+                   "n": n, "nrhs": k, "q": q, "hss_tol": a.hss_tol, "mixed_variant": head,
                    "hss_max_rank_per_level": {str(l): int(max(v)) for l, v in ranks.items()}},
-        "mixed": mixed, "fp64": results["fp64"],
+        "mixed": results["mixed"], "split16": results["split16"], "fp64": results["fp64"],
         "direct_fp64": {"ms_per_step": round(ms_direct, 3), "value": k / (ms_direct / 1e3),
                         "max_col_rel_err": err_d},
         "pcg_fp64": pcg,

@@ -47,7 +47,8 @@ typedef enum {
 typedef enum {
     FIO_PREC_FP64 = 0,           /* complex128 factors and coefficients */
     FIO_PREC_FP32 = 1,           /* complex64 factors and coefficients, complex128 input/output */
-    FIO_PREC_SPLIT_FP16 = 2      /* factors split into two fp16 halves, MFMA with fp32 accumulation */
+    FIO_PREC_SPLIT_FP16 = 2      /* transfer blocks and coefficients split into hi + lo fp16 halves,
+                                    MFMA with fp32 accumulation (see fio_bf_apply) */
 } fio_prec;
 
 typedef struct fio_bf_s *fio_bf_t;
@@ -83,7 +84,9 @@ typedef struct {
     double c0, c1;           /* phase parameters, see above */
     int q;                   /* Chebyshev points per box and dimension, 2 <= q <= 16 */
     int level_offset;        /* L' = max(L - level_offset, h); 3 gives leaf boxes of 8 points per dimension */
-    unsigned prec_mask;      /* bit p set: keep a copy of the factors in fio_prec p resident */
+    unsigned prec_mask;      /* bit p set: keep a copy of the factors in fio_prec p resident;
+                                FIO_PREC_SPLIT_FP16 (dim 1, q = 9 only, else FIO_ERR_UNSUPPORTED
+                                at build/import) also keeps the FP32 copy */
 } fio_bf_desc;
 
 /* Number of complex entries of the explicit factors of `desc`, in the layout
@@ -137,7 +140,17 @@ fio_status fio_bf_workspace_size(fio_bf_t bf, int nrhs, fio_prec prec, size_t *b
  * input and output are complex128 in every precision.  `ws` is device memory
  * of at least fio_bf_workspace_size bytes, or NULL to use a workspace owned
  * by the handle (then calls on the handle must not overlap).  X and Y must
- * not overlap. */
+ * not overlap.
+ * FIO_PREC_SPLIT_FP16 (the growth direction of the refinement's low-precision
+ * K~^*): every transfer block a and its input coefficients x are split into
+ * half-precision parts a_hi + a_lo, x_hi + x_lo, and a x is formed on the matrix
+ * cores as a_hi x_hi + a_hi x_lo + a_lo x_hi with FP32 accumulation; each
+ * column is scaled by a power of two per pass so that its entries sit well
+ * inside half range (any FP32-representable input scale works).  The middle
+ * factor is folded into the neighbouring transfer level (FP64 products before
+ * the split); leaf factors and the coefficient buffers between passes are
+ * FP32.  Accuracy is that of FP32 (about 1e-6 relative per apply).  A
+ * FIO_ERR_ARG is returned when the handle holds no such copy. */
 fio_status fio_bf_apply(fio_bf_t bf, const void *X, long ldx, void *Y, long ldy, int nrhs,
                         fio_prec prec, void *ws, size_t ws_bytes, void *stream);
 

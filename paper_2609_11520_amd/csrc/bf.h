@@ -14,7 +14,8 @@ struct fio_bf_s {
     std::vector<size_t> offC, offB;   // offC[lev] = C^[h+1+lev], offB[lev] = B^[h+1+lev]
     fio::DevBuf f64;                   // complex128 factors, import/export layout
     fio::DevBuf f32;                   // complex64 copy (FIO_PREC_FP32)
-    fio::DevBuf f16;                   // split-fp16 copy: hi and lo planes (FIO_PREC_SPLIT_FP16)
+    fio::DevBuf f16;                   // split-fp16 transfer blocks: hi and lo planes (FIO_PREC_SPLIT_FP16)
+    bool split16 = false;              // FIO_PREC_SPLIT_FP16 copies built (1D, q = 9)
     // structured transfer factors (built on the GPU only): twiddles of every B and C level and
     // the two shared Lagrange matrices P_c(i, t) (host copy, passed as kernel arguments)
     bool structured = false;

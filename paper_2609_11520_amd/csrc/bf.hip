@@ -343,8 +343,11 @@ static void bf_generate(fio_bf_s *bf, hipStream_t s) {
 void bf_make_lowprec(fio_bf_s *bf, hipStream_t s);   // bf_lowprec.hip
 
 static void bf_make_copies(fio_bf_s *bf, hipStream_t s) {
+    const bool want16 = (bf->desc.prec_mask & (1u << FIO_PREC_SPLIT_FP16)) != 0;
+    if (want16 && (bf->dim != 1 || bf->q != 9)) throw Err{FIO_ERR_UNSUPPORTED};
     if (bf->dim == 2) return bf2d_finish(bf, s);
-    if (bf->desc.prec_mask & (1u << FIO_PREC_FP32)) {
+    // the split-FP16 apply keeps leaf and middle factors in FP32
+    if (bf->desc.prec_mask & ((1u << FIO_PREC_FP32) | (1u << FIO_PREC_SPLIT_FP16))) {
         bf->f32.alloc(bf->total * sizeof(float2));
         cvt_f64_f32<<<grid1d(bf->total, 256), 256, 0, s>>>(bf->f64.as<double2>(), bf->f32.as<float2>(),
                                                          bf->total);
@@ -355,13 +358,13 @@ static void bf_make_copies(fio_bf_s *bf, hipStream_t s) {
         }
         FIO_HIP(hipGetLastError());
     }
-    if (bf->desc.prec_mask & (1u << FIO_PREC_SPLIT_FP16)) bf_make_lowprec(bf, s);
+    if (want16) bf_make_lowprec(bf, s);
 }
 
 void bf_apply_f64(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs,
                  const double2 *F, void *ws, hipStream_t s);
 void bf_apply_f32(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs,
-                 const float2 *F, void *ws, hipStream_t s);
+                 const float2 *F, void *ws, hipStream_t s, bool split);
 
 void bf_apply_split16(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs,
                       void *ws, hipStream_t s);   // bf_lowprec.hip
@@ -391,10 +394,10 @@ void bf_apply_impl(fio_bf_s *bf, bool adjoint, const double2 *X, long ldx, doubl
             break;
         case FIO_PREC_FP32:
             if (!bf->f32.p) throw Err{FIO_ERR_ARG};
-            bf_apply_f32(bf, adjoint, X, ldx, Y, ldy, nrhs, bf->f32.as<float2>(), ws, s);
+            bf_apply_f32(bf, adjoint, X, ldx, Y, ldy, nrhs, bf->f32.as<float2>(), ws, s, false);
             break;
         case FIO_PREC_SPLIT_FP16:
-            if (!bf->f16.p) throw Err{FIO_ERR_ARG};
+            if (!bf->split16) throw Err{FIO_ERR_ARG};
             bf_apply_split16(bf, adjoint, X, ldx, Y, ldy, nrhs, ws, s);
             break;
     }
@@ -493,7 +496,7 @@ static fio_status bf_apply_api(fio_bf_t bf, bool adj, const void *X, long ldx, v
     FIO_CHECK_ARG(X && Y && ldx >= bf->N && ldy >= bf->N);
     FIO_CHECK_ARG(prec >= FIO_PREC_FP64 && prec <= FIO_PREC_SPLIT_FP16);
     if (prec == FIO_PREC_FP32 && !bf->f32.p) return FIO_ERR_ARG;
-    if (prec == FIO_PREC_SPLIT_FP16 && !bf->f16.p) return FIO_ERR_ARG;
+    if (prec == FIO_PREC_SPLIT_FP16 && !bf->split16) return FIO_ERR_ARG;
     size_t need = bf_ws_bytes(bf, nrhs, prec);
     return guarded([&] {
         hipStream_t s = as_stream(stream);

@@ -1,6 +1,8 @@
 // Apply kernels of the butterfly factorization (Section 2.2, eq. bf), shared by the
 // per-precision translation units bf_apply_f64.hip and bf_apply_f32.hip.
 #pragma once
+#include <type_traits>
+
 #include "bf.h"
 #include "timing.h"
 
@@ -8,6 +10,19 @@ namespace fio {
 
 constexpr int kLeafPts = 8;
 bool fused_disabled();
+
+// Split-FP16 transfer passes on the matrix cores (bf_lowprec.hip): KL <= 3 transfer factors of
+// one side per launch, FP32 coefficient buffers in and out, as the structured passes; the
+// middle factor is folded into the blocks of the level next to it.
+struct SplitPass {
+    const void *A[3];        // split blocks of forward step j (forward or adjoint copy)
+    long G0;
+    const float2 *in;
+    float2 *out;
+    int nrhs;
+};
+void split_pass(const SplitPass &sp, int kl, bool adj, long N, hipStream_t s);
+const void *split_blocks(const fio_bf_s *bf, bool cside, int lev, bool adj);
 
 // ---------------------------------------------------------------------------
 // geometry passed to the kernels by value
@@ -676,7 +691,7 @@ __global__ void __launch_bounds__(256) k_leaf_io(Geo g, const cpx<T> *__restrict
 
 template <typename T, int Q>
 static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs,
-                    const cpx<T> *F, cpx<T> *c0, cpx<T> *c1, hipStream_t s) {
+                    const cpx<T> *F, cpx<T> *c0, cpx<T> *c1, hipStream_t s, bool split) {
     Geo g = geo_of(bf);
     const unsigned TB = 256;
     const bool uni = (nrhs % 64) == 0;
@@ -705,12 +720,29 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
     bool fused = false;
     int kmax = 1;
     if constexpr (fused_q<Q>()) {
-        fused = bf->nl > 0 && !fused_disabled();
+        fused = bf->nl > 0 && (split || !fused_disabled());
         kmax = fused_max_kl<T, Q>();
     }
     auto pass = [&](bool a, bool cside, int lo, int hi, bool epi) {
         if constexpr (fused_q<Q>()) {
             const int kl = hi - lo;
+            if constexpr (std::is_same<T, float>::value && Q == 9) {
+                if (split) {
+                    SplitPass sp;
+                    for (int jj = 0; jj < 3; ++jj) sp.A[jj] = nullptr;
+                    for (int jj = 0; jj < kl; ++jj)
+                        sp.A[jj] = split_blocks(bf, cside, cside ? hi - 1 - jj : lo + jj, a);
+                    sp.G0 = cside ? (1L << (bf->h + hi - 1)) : (1L << (bf->L - (bf->h + lo) - 1));
+                    sp.in = cur;
+                    sp.out = nxt;
+                    sp.nrhs = nrhs;
+                    FIO_TIMED("bf_split16", s);
+                    // the middle factor is folded into the split blocks next to it
+                    split_pass(sp, kl, a, bf->N, s);
+                    std::swap(cur, nxt);
+                    return;
+                }
+            }
             if (bf->structured) {
                 StructArgs<T, Q> sa;
                 const cpx<T> *TWb = f64 ? reinterpret_cast<const cpx<T> *>(bf->tw64.p)
@@ -841,12 +873,12 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
 
 template <typename T>
 void apply_t(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs,
-                    const cpx<T> *F, void *ws, hipStream_t s) {
+                    const cpx<T> *F, void *ws, hipStream_t s, bool split = false) {
     cpx<T> *c0 = reinterpret_cast<cpx<T> *>(ws);
     cpx<T> *c1 = c0 + bf_coef_elems(bf, nrhs);
     switch (bf->q) {
 #define FIO_Q(QQ) \
-    case QQ: apply_q<T, QQ>(bf, adj, X, ldx, Y, ldy, nrhs, F, c0, c1, s); break;
+    case QQ: apply_q<T, QQ>(bf, adj, X, ldx, Y, ldy, nrhs, F, c0, c1, s, split); break;
         FIO_Q(2) FIO_Q(3) FIO_Q(4) FIO_Q(5) FIO_Q(6) FIO_Q(7) FIO_Q(8) FIO_Q(9)
         FIO_Q(10) FIO_Q(11) FIO_Q(12) FIO_Q(13) FIO_Q(14) FIO_Q(15) FIO_Q(16)
 #undef FIO_Q

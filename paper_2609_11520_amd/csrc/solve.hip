@@ -320,7 +320,7 @@ extern "C" fio_status fio_approx_solve(fio_bf_t bf, hss_ulv_t f, const void *U, 
     FIO_CHECK_ARG(opts->prec >= FIO_PREC_FP64 && opts->prec <= FIO_PREC_SPLIT_FP16);
     FIO_CHECK_ARG(opts->max_ir >= 0);
     if (opts->prec == FIO_PREC_FP32 && !bf->f32.p) return FIO_ERR_ARG;
-    if (opts->prec == FIO_PREC_SPLIT_FP16 && !bf->f16.p) return FIO_ERR_ARG;
+    if (opts->prec == FIO_PREC_SPLIT_FP16 && !bf->split16) return FIO_ERR_ARG;
     size_t need = solve_ws_bytes(bf, f, nrhs, opts);
     FIO_CHECK_ARG(ws && ws_bytes >= need);
     return guarded([&] {

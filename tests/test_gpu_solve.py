@@ -11,7 +11,8 @@ pytestmark = pytest.mark.gpu
 
 def setup_imported(F, n=1024, tol=1e-3):
     h, fac = oracle_hss(n, 9, "sin16", tol, 10, 1000)
-    B = gpu_bf(F, n, 9, "sin16", imported=True, precs=(F.FIO_PREC_FP64, F.FIO_PREC_FP32))
+    B = gpu_bf(F, n, 9, "sin16", imported=True,
+               precs=(F.FIO_PREC_FP64, F.FIO_PREC_FP32, F.FIO_PREC_SPLIT_FP16))
     ranks, gen = hss_generators(h)
     U = F.ULV(F.HSS.from_generators(n, 64, ranks, gen))
     return B, U, oracle_bf(n, 9, "sin16"), fac
@@ -30,7 +31,7 @@ def test_direct_solve_matches_oracle(k):
     assert 1e-6 < rel(ref, f) < 5e-4
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_refinement_reaches_1e8(prec):
     F = fiohss()
     step("IR prec=%d" % prec)
