@@ -130,6 +130,13 @@ template <int KL, bool ADJ> __device__ __forceinline__ int split_slot(int j, int
     return 2 * ((hi >> 1) * Gl + p % Gl) + (hi & 1);
 }
 
+// LDS planes: group g's two input pairs occupy 20 rows (slot 2g + c, coefficient i at row
+// 20 g + 9 c + i; rows 18, 19 stay zero), each row holds 64 columns with bits 4-5 of the column
+// index XORed with bits 2-3 of the row, so that the four quarter-waves of an operand read (rows
+// 4 apart) and of an output write (rows 2 apart) mostly fall into different bank ranges
+__device__ __forceinline__ int prow(int slot, int i) { return 20 * (slot >> 1) + kQ * (slot & 1) + i; }
+__device__ __forceinline__ int pidx(int row, int n) { return row * 64 + (n ^ (((row >> 2) & 3) << 4)); }
+
 __device__ __forceinline__ u4 odd_form(u4 w) {
     // odd rows read (Im a, Re a): swap the halves of the stored (Re a, -Im a), negate the low one
     w.x = __builtin_amdgcn_alignbit(w.x, w.x, 16) ^ 0x8000u;
@@ -142,14 +149,18 @@ __device__ __forceinline__ u4 odd_form(u4 w) {
 template <int KL, bool ADJ>
 __global__ void __launch_bounds__((1 << KL) * 64, 4) k_split_fused(SplitArgsK a) {
     using C = float2;
-    constexpr int Q = kQ, P = 1 << KL, PW = P * Q * 64, NG = P / 2, NT = P * 64;
+    constexpr int Q = kQ, P = 1 << KL, NG = P / 2, PW = NG * 20 * 64, NT = P * 64;
     constexpr int BLK4 = kGroupWords / 4;      // uint4 per group block
     constexpr int NSTG = (NG * BLK4 + NT - 1) / NT;
     constexpr int ZERO = 2 * PW;
-    __shared__ uint32_t sm[2 * PW + 256];      // hi plane, lo plane, 256 zero words
-    __shared__ u4 sA[2][NG][BLK4];             // [even / odd-row form][group][block]
+    __shared__ uint32_t sm[2 * PW + 256];      // hi plane, lo plane (swizzled, see pidx), 256 zero words
+    // [even / odd-row form][group][block]; the odd form starts 8 words (mod 64) after the even
+    // one, so lanes 2r and 2r + 1, which read the same row in the two forms, use different banks
+    constexpr int SAF = NG * BLK4 + 2;
+    __shared__ u4 sA[2 * SAF];
     __shared__ float cmax[P][64];
-    C *ftile = reinterpret_cast<C *>(sm);      // [P][Q][64] FP32 results of the last factor
+    C *ftile = reinterpret_cast<C *>(sm);      // [P Q rows][64] FP32 results of the last factor (pidx)
+    static_assert(P * Q * 64 * 2 <= 2 * PW, "the FP32 tile aliases the planes");
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -191,12 +202,17 @@ __global__ void __launch_bounds__((1 << KL) * 64, 4) k_split_fused(SplitArgsK a)
         }
         cmax[lp][lane] = m;
         for (int e = tid; e < 256; e += NT) sm[ZERO + e] = 0u;
+        // the two padding rows of every group, both planes
+        for (int e = tid; e < NG * 2 * 64 * 2; e += NT) {
+            const int pl = e / (NG * 128), r = (e / 64) % (NG * 2);
+            sm[pl * PW + (20 * (r >> 1) + kQ2 + (r & 1)) * 64 + (e & 63)] = 0u;
+        }
 #pragma unroll
         for (int r = 0; r < NSTG; ++r) {
             const int e = tid + r * NT;
             if (e < NG * BLK4) {
-                (&sA[0][0][0])[e] = pf[r];
-                (&sA[1][0][0])[e] = odd_form(pf[r]);
+                sA[e] = pf[r];
+                sA[SAF + e] = odd_form(pf[r]);
             }
         }
         __syncthreads();
@@ -213,28 +229,30 @@ __global__ void __launch_bounds__((1 << KL) * 64, 4) k_split_fused(SplitArgsK a)
         for (int i = 0; i < Q; ++i) {
             uint32_t hi, lo;
             split2(v[i].x * sc, v[i].y * sc, hi, lo);
-            sm[(slot * Q + i) * 64 + lane] = hi;
-            sm[PW + (slot * Q + i) * 64 + lane] = lo;
+            sm[pidx(prow(slot, i), lane)] = hi;
+            sm[PW + pidx(prow(slot, i), lane)] = lo;
         }
     }
     __syncthreads();
 
     const int grp = wave >> 1, nh = wave & 1;
     const int r16 = lane & 15, qd = lane >> 4;
-    // per-lane constant operand offsets: B words of K-tile kt (plus 64 e4 + 16 nt), A uint4s of
-    // (row tile mt, K-tile kt) inside the group's staged block
+    // per-lane constant operand offsets: B word of K-tile kt, input t0 of the first 16-column
+    // tile (input t0 + e4 is 64 e4 further, since rows 20 g + t0 .. + 3 share their swizzle; the
+    // second tile's word differs in column bit 4: offset ^ 16), A uint4s of (row tile mt, K-tile
+    // kt) inside the group's staged block
     int boff[4], aoff[3][4];
 #pragma unroll
     for (int kt = 0; kt < 4; ++kt) {
         const int sl = 4 * kt + qd, reg = sl / 5, t0 = 4 * (sl % 5);
-        boff[kt] = reg == 3 ? ZERO + r16 : (reg == 1 ? PW : 0) + (2 * grp * Q + t0) * 64 + nh * 32 + r16;
+        boff[kt] = reg == 3 ? ZERO + r16 : (reg == 1 ? PW : 0) + pidx(20 * grp + t0, nh * 32 + r16);
 #pragma unroll
         for (int mt = 0; mt < 3; ++mt) {
             const int ir = (16 * mt + r16) >> 1, i = ir < kQ2 ? ir : kQ2 - 1;
             aoff[mt][kt] = ((reg == 2 ? 1 : 0) * kQ2 + i) * (kCols / 4) + (reg < 3 ? t0 / 4 : 0);
         }
     }
-    const u4 *blkA = &sA[lane & 1][grp][0];
+    const u4 *blkA = sA + (lane & 1) * SAF + grp * BLK4;
 #pragma unroll
     for (int st = 0; st < KL; ++st) {
         const int j = ADJ ? KL - 1 - st : st;
@@ -255,7 +273,7 @@ __global__ void __launch_bounds__((1 << KL) * 64, 4) k_split_fused(SplitArgsK a)
         for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
             for (int kt = 0; kt < 4; ++kt) {
-                const uint32_t *bp = sm + boff[kt] + nt * 16;
+                const uint32_t *bp = sm + (boff[kt] ^ (nt * 16));
                 Bop[nt][kt] = u4{bp[0], bp[64], bp[128], bp[192]};
             }
         f4 acc[2][3];
@@ -289,11 +307,11 @@ __global__ void __launch_bounds__((1 << KL) * 64, 4) k_split_fused(SplitArgsK a)
                     const int i = 8 * mt + 2 * qd + u;
                     if (i < kQ2) {
                         const int c = i >= Q, jj = i - Q * c;
-                        const int w = ((c ? e1 : e0) * Q + jj) * 64 + n;
+                        const int w = pidx(prow(c ? e1 : e0, jj), n);
                         const float re = u ? acc[nt][mt].z : acc[nt][mt].x;
                         const float im = u ? acc[nt][mt].w : acc[nt][mt].y;
                         if (st == KL - 1) {
-                            ftile[w] = make_float2(re, im);
+                            ftile[pidx((c ? e1 : e0) * Q + jj, n)] = make_float2(re, im);
                         } else {
                             uint32_t hi, lo;
                             split2(re, im, hi, lo);
@@ -309,8 +327,8 @@ __global__ void __launch_bounds__((1 << KL) * 64, 4) k_split_fused(SplitArgsK a)
             for (int r = 0; r < NSTG; ++r) {
                 const int e = tid + r * NT;
                 if (e < NG * BLK4) {
-                    (&sA[0][0][0])[e] = pf[r];
-                    (&sA[1][0][0])[e] = odd_form(pf[r]);
+                    sA[e] = pf[r];
+                    sA[SAF + e] = odd_form(pf[r]);
                 }
             }
         }
@@ -322,7 +340,7 @@ __global__ void __launch_bounds__((1 << KL) * 64, 4) k_split_fused(SplitArgsK a)
         C *dstp = a.out + (size_t)gp * Q * ld + col;
 #pragma unroll
         for (int i = 0; i < Q; ++i)
-            if (act) dstp[i * ld] = cscale(ftile[(lp * Q + i) * 64 + lane], inv);
+            if (act) dstp[i * ld] = cscale(ftile[pidx(lp * Q + i, lane)], inv);
     }
 }
 
