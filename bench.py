@@ -49,7 +49,7 @@ def kernel_source_hash():
     """Hash of the butterfly apply kernels' source; stored counter traffic is valid only for it."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("bf_apply.h", "bf_apply_f64.hip", "bf_apply_f32.hip"):
+    for f in ("bf_apply.h", "bf_apply_f64.hip", "bf_apply_f32.hip", "bf_lowprec.hip"):
         with open(os.path.join(ROOT, "paper_2609_11520_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
