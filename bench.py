@@ -178,23 +178,23 @@ def synthetic_hss(n, leaf, r):
 def serving(F, torch, fi, duration, rate, seed=4, rel_res=5e-9):
     """Serving workload: three resident operators N = 2^14, 2^16, 2^18 (same phase, q = 9, HSS
     tolerance 1e-3), Poisson arrivals at `rate` requests/s for `duration` s, each request 1..32
-    right-hand sides (uniform) for an operator drawn uniformly; the mixed-precision refinement
-    with the step count calibrated per operator; batches of up to 64 columns on 2 streams,
+    right-hand sides (uniform) for an operator drawn uniformly; the refinement with the split-FP16
+    K~^* and the step count calibrated per operator; batches of up to 64 columns on 2 streams,
     replayed from captured hipGraphs.  Latency = completion - submission (host clock)."""
     dev = torch.device("cuda")
     ops = []
     for e in (14, 16, 18):
         n = 1 << e
-        B = F.BF(n, 9, 2.0 / 16, 1.0 / 16, precs=(F.FIO_PREC_FP64, F.FIO_PREC_FP32))
+        B = F.BF(n, 9, 2.0 / 16, 1.0 / 16, precs=(F.FIO_PREC_FP64, F.FIO_PREC_SPLIT_FP16))
         U = F.ULV(F.HSS.from_bf(B, tol=1e-3, p=10, seed=1003))
         fpool = fi.rhs(seed + e, n, 32)
         fd = torch.from_numpy(np.ascontiguousarray(fpool.T)).to(dev).t()
         upool = B.apply(fd)
-        _, info = F.approx_solve(B, U, upool, mode=F.FIO_SOLVE_IR, prec=F.FIO_PREC_FP32, rel_res_tol=rel_res,
-                                 max_ir=6)
+        _, info = F.approx_solve(B, U, upool, mode=F.FIO_SOLVE_IR, prec=F.FIO_PREC_SPLIT_FP16,
+                                 rel_res_tol=rel_res, max_ir=6)
         ops.append({"n": n, "B": B, "U": U, "u": upool, "f": fpool, "nir": max(1, info.ir_steps)})
     srv = F.Server(max_batch_rhs=64, streams=2, use_graphs=True, width_bucket=16)
-    ids = [srv.add_operator(o["B"], o["U"], mode=F.FIO_SOLVE_IR, prec=F.FIO_PREC_FP32, max_ir=o["nir"])
+    ids = [srv.add_operator(o["B"], o["U"], mode=F.FIO_SOLVE_IR, prec=F.FIO_PREC_SPLIT_FP16, max_ir=o["nir"])
            for o in ops]
     arr = fi.poisson_arrivals(seed, rate, duration)
     ks = fi.integers(seed, fi.PURPOSE_DATA, 1, 32, len(arr))
@@ -229,7 +229,7 @@ def serving(F, torch, fi, duration, rate, seed=4, rel_res=5e-9):
     srv.close()
     lat = np.array(lat)
     return {"workload": "3 resident 1D FIOs N=2^14,2^16,2^18; Poisson %g req/s for %g s (seed %d); "
-                        "1-32 RHS per request; mixed refinement; 64-column batches, 2 streams, hipGraphs"
+                        "1-32 RHS per request; split-FP16 refinement; 64-column batches, 2 streams, hipGraphs"
                         % (rate, duration, seed),
             "requests": len(rids), "rhs": int(np.sum(ks)), "rhs_per_s": float(np.sum(ks) / (last - first)),
             "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),

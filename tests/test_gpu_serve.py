@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 def operators(F, sizes=(4096, 1 << 14)):
     ops = []
     for n in sizes:
-        B = F.BF(n, 9, 2.0 / 16, 1.0 / 16, precs=(F.FIO_PREC_FP64, F.FIO_PREC_FP32))
+        B = F.BF(n, 9, 2.0 / 16, 1.0 / 16, precs=(F.FIO_PREC_FP64, F.FIO_PREC_FP32, F.FIO_PREC_SPLIT_FP16))
         U = F.ULV(F.HSS.from_bf(B, tol=1e-3, p=10, seed=5))
         ops.append((n, B, U))
     return ops
@@ -47,13 +47,15 @@ def run(F, srv_kw, ops, reqs, alone, solve_kw):
     return [host(f) for f in outs], st, infos
 
 
-@pytest.mark.parametrize("graphs", [False, True])
-def test_alone_equals_mixed_bitwise(graphs):
+@pytest.mark.parametrize("graphs,prec", [(False, 1), (True, 1), (True, 2)])
+def test_alone_equals_mixed_bitwise(graphs, prec):
+    # prec 1: FP32 low-precision K~^*; 2: split FP16 (per-column scaling keeps every column's
+    # arithmetic independent of the other columns of its batch)
     F = fiohss()
-    step("serve alone vs mixed graphs=%s" % graphs)
+    step("serve alone vs mixed graphs=%s prec=%d" % (graphs, prec))
     ops = operators(F)
     reqs = requests(ops, 14, 40)
-    kw = dict(mode=F.FIO_SOLVE_IR, prec=F.FIO_PREC_FP32, max_ir=1)
+    kw = dict(mode=F.FIO_SOLVE_IR, prec=prec, max_ir=1)
     a, sa, _ = run(F, dict(max_batch_rhs=64, streams=2, use_graphs=graphs), ops, reqs, True, kw)
     m, sm, infos = run(F, dict(max_batch_rhs=64, streams=2, use_graphs=graphs), ops, reqs, False, kw)
     assert sa["batches"] == len(reqs) and sm["completed"] == len(reqs)
@@ -64,7 +66,7 @@ def test_alone_equals_mixed_bitwise(graphs):
     # and the same as a direct library solve of each request on its own
     for (o, u), y in zip(reqs, a):
         n, B, U = ops[o]
-        fh, _ = F.approx_solve(B, U, u, mode=F.FIO_SOLVE_IR, prec=F.FIO_PREC_FP32, max_ir=1)
+        fh, _ = F.approx_solve(B, U, u, mode=F.FIO_SOLVE_IR, prec=prec, max_ir=1)
         assert np.array_equal(host(fh), y)
 
 
