@@ -83,3 +83,34 @@ def test_pcg_matches_oracle_and_converges():
     assert osolve.col_rel_err(host(fh), f) < 1e-10
     with pytest.raises(F.FioError):
         F.approx_solve(B, U, dev(u), mode=F.FIO_SOLVE_PCG, prec=1, rel_res_tol=1e-12, max_ir=5)
+
+
+@pytest.mark.parametrize("phase", ["sin16", "dft"])
+def test_n2e16_sixteen_rhs_and_dft_sanity(phase):
+    """N = 2^16, 16 right-hand sides (seed 1), HSS from s = r + 10 sample columns (p = 10) at the
+    paper's tolerance 1e-3.  sin16: the refinement reaches 1e-8 and PCG 1e-10.  DFT (c = 0):
+    K*K = N I exactly, so the HSS of K~^*K~ has rank 0 on every node at 1e-3 and the direct solve
+    is K~^* u / N up to the BF error (~3e-7)."""
+    F = fiohss()
+    n, k = 1 << 16, 16
+    step("N=2^16 %s" % phase)
+    c0, c1 = (2.0 / 16, 1.0 / 16) if phase == "sin16" else (0.0, 0.0)
+    B = F.BF(n, 9, c0, c1, precs=(F.FIO_PREC_FP64, F.FIO_PREC_FP32))
+    H = F.HSS.from_bf(B, tol=1e-3, p=10, seed=11)
+    U = F.ULV(H)
+    f = fi.rhs(1, n, k)
+    u = B.apply(dev(f))
+    fd, _ = F.approx_solve(B, U, u)
+    e_direct = osolve.col_rel_err(host(fd), f)
+    if phase == "dft":
+        assert max(max(v) for v in H.ranks().values()) == 0
+        assert e_direct < 1e-5
+        ka = host(B.apply_adj(u)) / n
+        assert rel(host(fd), ka) < 1e-5
+    else:
+        assert 1e-6 < e_direct < 5e-3
+        fr, info = F.approx_solve(B, U, u, mode=F.FIO_SOLVE_IR, prec=F.FIO_PREC_FP32, rel_res_tol=1e-10,
+                                  max_ir=8)
+        assert info.rel_res <= 1e-10 and osolve.col_rel_err(host(fr), f) < 1e-8
+        fp, info = F.approx_solve(B, U, u, mode=F.FIO_SOLVE_PCG, rel_res_tol=1e-12, max_ir=30)
+        assert info.ir_steps <= 8 and osolve.col_rel_err(host(fp), f) < 1e-10

@@ -132,3 +132,20 @@ def test_full_size_dft_closed_form():
     assert rel(host(B.apply_adj(dev(f))), refa) < 1e-6
     assert rel(host(B.apply(dev(f), prec=SPLIT)), ref) < 1e-6 + TOL16
     assert rel(host(B.apply_adj(dev(f), prec=SPLIT)), refa) < 1e-6 + TOL16
+
+
+def test_full_size_refinement_all_precisions(full_size):
+    """The benchmark's solve at N = 2^18, 64 right-hand sides: the refinement with a K~^* in FP64,
+    FP32 or split FP16 (residual and ULV in FP64) reaches a relative error of 1e-8 on every column."""
+    F, n, B = full_size
+    step("full size HSS + ULV")
+    H = F.HSS.from_bf(B, tol=1e-3, p=10, seed=1003)
+    U = F.ULV(H)
+    f = fi.rhs(1, n, 64)
+    u = B.apply(dev(f))
+    for p in (F.FIO_PREC_FP64, F.FIO_PREC_FP32, SPLIT):
+        step("full size refinement prec=%d" % p)
+        fr, info = F.approx_solve(B, U, u, mode=F.FIO_SOLVE_IR, prec=p, rel_res_tol=5e-9, max_ir=6)
+        assert info.rel_res <= 5e-9
+        err = np.linalg.norm(host(fr) - f, axis=0) / np.linalg.norm(f, axis=0)
+        assert err.max() < 1e-8
