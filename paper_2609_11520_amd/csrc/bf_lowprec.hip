@@ -44,12 +44,20 @@ __device__ __forceinline__ uint32_t pack_h2(_Float16 lo, _Float16 hi) {
     return (uint32_t)__builtin_bit_cast(uint16_t, lo) | ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
 }
 
-// x = hi + lo: hi truncated to half precision (so that x - hi is exact in FP32), lo rounded.
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+
+// x = hi + lo: hi truncated to half precision (so that x - hi is exact in FP32), lo rounded to
+// nearest.  The remainder x - hi is one v_fma_mix_f32 per component (the half operand is widened
+// inside the instruction; the exact result is representable, so the FMA does not round).
 __device__ __forceinline__ void split2(float re, float im, uint32_t &hi, uint32_t &lo) {
-    auto h = __builtin_amdgcn_cvt_pkrtz(re, im);
-    const float rr = re - (float)h[0], ri = im - (float)h[1];
-    hi = __builtin_bit_cast(uint32_t, h);
-    lo = pack_h2((_Float16)rr, (_Float16)ri);
+    hi = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(re, im));
+    float rr, ri;
+    asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]" : "=v"(rr) : "v"(hi), "v"(re));
+    asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(ri) : "v"(hi), "v"(im));
+    h2 l;
+    l[0] = (_Float16)rr;
+    l[1] = (_Float16)ri;
+    lo = __builtin_bit_cast(uint32_t, l);
 }
 
 // ---------------------------------------------------------------------------
