@@ -621,6 +621,97 @@ __global__ void __launch_bounds__(256) k_ulv_level(LevelArgs a, const double2 *_
     }
 }
 
+// The same level product for nodes of at most 64 rows (the leaf level): one workgroup per
+// node and 64 right-hand sides, 4 x 4 outputs per thread, so W and the vector block are read
+// once and every LDS operand read feeds four multiply-adds.  Accumulation runs over k in the
+// order of k_ulv_level, so both kernels give identical results.
+template <bool DOWN>
+__global__ void __launch_bounds__(256) k_ulv_level64(LevelArgs a, const double2 *__restrict__ Yin, long ldin,
+                                                     double2 *__restrict__ Bh, long ldb, double2 *__restrict__ Ylo,
+                                                     long ldlo, double2 *__restrict__ Yout, long ldout, int nrhs) {
+    const int node = blockIdx.y;
+    const int m = a.m[node], k = a.k[node];
+    const int n0 = blockIdx.x * 64;
+    if (m == 0 || n0 >= nrhs) return;
+    const double2 *W = a.W + a.woff[node];
+    const long yo = a.yoff[node], ro = a.roff[node];
+    __shared__ double2 As[16][65];
+    __shared__ double2 Bs[16][65];
+    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+    double2 acc[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = zc(0.0, 0.0);
+    for (int k0 = 0; k0 < m; k0 += 16) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int e = tid + 256 * r;
+            int mm, kk;
+            double2 v = zc(0.0, 0.0);
+            if (DOWN) {      // op(A) = W^*: element (row, kk) = conj(W(kk, row))
+                kk = e % 16;
+                mm = e / 16;
+                const int gm = mm, gk = k0 + kk;
+                if (gm < m && gk < m) {
+                    const double2 t = W[gk + (size_t)gm * m];
+                    v = zc(t.x, -t.y);
+                }
+            } else {
+                mm = e % 64;
+                kk = e / 64;
+                const int gm = mm, gk = k0 + kk;
+                if (gm < m && gk < m) v = W[gm + (size_t)gk * m];
+            }
+            As[kk][mm] = v;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int e = tid + 256 * r;
+            const int kk = e % 16, nn = e / 16;
+            const int gk = k0 + kk, gn = n0 + nn;
+            double2 v = zc(0.0, 0.0);
+            if (gk < m && gn < nrhs) {
+                if (DOWN)
+                    v = gk < k ? Bh[(yo + gk) + (size_t)gn * ldb] : Ylo[(ro + gk - k) + (size_t)gn * ldlo];
+                else
+                    v = Yin[(yo + gk) + (size_t)gn * ldin];
+            }
+            Bs[kk][nn] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            double2 av[4], bv[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) av[x] = As[kk][tx + 16 * x];
+#pragma unroll
+            for (int y = 0; y < 4; ++y) bv[y] = Bs[kk][ty + 16 * y];
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) cfma(acc[x][y], av[x], bv[y]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+        const int gm = tx + 16 * x;
+        if (gm >= m) continue;
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+            const int gn = n0 + ty + 16 * y;
+            if (gn >= nrhs) continue;
+            if (DOWN)
+                Yout[(yo + gm) + (size_t)gn * ldout] = acc[x][y];
+            else if (gm < k)
+                Bh[(yo + gm) + (size_t)gn * ldb] = acc[x][y];
+            else
+                Ylo[(ro + gm - k) + (size_t)gn * ldlo] = acc[x][y];
+        }
+    }
+}
+
 // One level of the ULV solve for few right-hand sides on large nodes, in two launches:
 // k_ulv_narrow computes partial products over S slices of the inner dimension, one wave
 // per 64 output rows and slice, lanes on rows, so W (UP) or W^* (DOWN, the stored copy WH)
@@ -1055,6 +1146,10 @@ void ulv_solve_impl(hss_ulv_s *f, const double2 *Y, long ldy, double2 *C, long l
                 k_ulv_narrow_sum<false><<<g2, 256, 0, s>>>(args(l), part, S, f->rows[l], nrhs, c0, Bl[l], f->rows[l],
                                                            Yl[l - 1], f->rows[l - 1], nullptr, 0);
             }
+        } else if (mmax(l) > 32 && mmax(l) <= 64) {
+            dim3 grid((unsigned)((nrhs + 63) / 64), f->m[l].size());
+            k_ulv_level64<false><<<grid, 256, 0, s>>>(args(l), yin, ldin, Bl[l], f->rows[l], Yl[l - 1],
+                                                      f->rows[l - 1], nullptr, 0, nrhs);
         } else {
             dim3 grid(tilesM * tilesN, f->m[l].size());
             k_ulv_level<false><<<grid, 256, 0, s>>>(args(l), yin, ldin, Bl[l], f->rows[l], Yl[l - 1], f->rows[l - 1],
@@ -1086,6 +1181,10 @@ void ulv_solve_impl(hss_ulv_s *f, const double2 *Y, long ldy, double2 *C, long l
                 k_ulv_narrow_sum<true><<<g2, 256, 0, s>>>(args(l), part, S, f->rows[l], nrhs, c0, nullptr, 0,
                                                           nullptr, 0, yout, ldout);
             }
+        } else if (mmax(l) > 32 && mmax(l) <= 64) {
+            dim3 grid((unsigned)((nrhs + 63) / 64), f->m[l].size());
+            k_ulv_level64<true><<<grid, 256, 0, s>>>(args(l), nullptr, 0, Bl[l], f->rows[l], Yl[l - 1],
+                                                     f->rows[l - 1], yout, ldout, nrhs);
         } else {
             dim3 grid(tilesM * tilesN, f->m[l].size());
             k_ulv_level<true><<<grid, 256, 0, s>>>(args(l), nullptr, 0, Bl[l], f->rows[l], Yl[l - 1], f->rows[l - 1],
