@@ -159,6 +159,31 @@ fio_status fio_bf_apply(fio_bf_t bf, const void *X, long ldx, void *Y, long ldy,
 fio_status fio_bf_apply_adj(fio_bf_t bf, const void *X, long ldx, void *Y, long ldy, int nrhs,
                             fio_prec prec, void *ws, size_t ws_bytes, void *stream);
 
+/* Tile autotuner of the applies.  For `nrhs` columns in precision `prec`, times every candidate
+ * tile configuration of fio_bf_apply and of fio_bf_apply_adj on the caller's X (one warm-up
+ * and `reps` timed applies each, HIP events on `stream`) and keeps the fastest per direction
+ * in the handle; later applies whose column count falls in the same bucket (the next power of
+ * two of nrhs, all counts >= 64 in one bucket) and precision use it.  Candidates: for dim = 2
+ * the column chunk of the workgroups (8 or 16) times the reduction split of the U and V^*
+ * steps (4, 8, 16 dividing the partner count); for dim = 1 (q = 9) the number of transfer
+ * levels per fused pass (1, 2, 3); the built-in default is always a candidate.  Every
+ * candidate applies the same operator (results differ at most by rounding order).  Y (ldy >= N)
+ * receives the last apply; `ws` as for fio_bf_apply (NULL: the handle's workspace).  When
+ * `report` is not NULL, a NUL-terminated summary of the timings and the choices is written to
+ * it (at most report_len bytes).  Synchronous.  Must not run concurrently with applies on the
+ * same handle (the candidates are installed in turn).  Errors as fio_bf_apply; FIO_ERR_ARG
+ * also for nrhs < 1 or reps < 1. */
+fio_status fio_bf_autotune(fio_bf_t bf, const void *X, long ldx, void *Y, long ldy, int nrhs, fio_prec prec,
+                           int reps, void *ws, size_t ws_bytes, void *stream, char *report, size_t report_len);
+
+/* Pins the tile configuration of one direction (adj != 0: fio_bf_apply_adj), precision and
+ * column bucket (as fio_bf_autotune), e.g. to reproduce a tuned choice: kc in {0, 8, 16},
+ * nsplit 0 or a power of two dividing the 2D partner count (at most 16), kmax in 0..3 (1D
+ * levels per pass); 0 keeps the built-in default.  Values a descriptor does not use are
+ * ignored.  FIO_ERR_ARG for other values.  Host-side only; must not run concurrently with
+ * applies on the same handle. */
+fio_status fio_bf_set_tile(fio_bf_t bf, int adj, fio_prec prec, int nrhs, int kc, int nsplit, int kmax);
+
 void fio_bf_destroy(fio_bf_t bf);
 
 /* Index map of the 2D grids: reorders the rows of X (n^2 x nrhs, device) into Y

@@ -121,6 +121,24 @@ class BF:
         """K~^* X."""
         return self._apply(lib().fio_bf_apply_adj, X, prec, out, ws)
 
+    def autotune(self, X, prec=FIO_PREC_FP64, reps=5, ws=None):
+        """Times the tile candidates of both applies on X (its column count selects the bucket) and
+        keeps the fastest in the handle (fio_bf_autotune).  Returns the library's report string."""
+        X, ldx = colmajor(X)
+        k = X.shape[1]
+        Y, ldy = colmajor(empty(self.n, k))
+        if ws is None:
+            ws = _workspace(self.workspace_size(k, prec))
+        rep = C.create_string_buffer(4096)
+        st = lib().fio_bf_autotune(self.h, _ptr(X), ldx, _ptr(Y), ldy, k, prec, reps, _ptr(ws), ws.numel(),
+                                   _stream(), rep, len(rep))
+        _lib.check(st, "fio_bf_autotune")
+        return rep.value.decode()
+
+    def set_tile(self, nrhs, prec=FIO_PREC_FP64, adj=False, kc=0, nsplit=0, kmax=0):
+        """Pins the tile configuration of one direction / precision / column bucket (fio_bf_set_tile)."""
+        _lib.check(lib().fio_bf_set_tile(self.h, int(adj), prec, nrhs, kc, nsplit, kmax), "fio_bf_set_tile")
+
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None and _lib._lib is not None:
             _lib._lib.fio_bf_destroy(self.h)

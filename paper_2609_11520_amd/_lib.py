@@ -57,6 +57,8 @@ PROTOS = {
     "fio_bf_workspace_size": (i32, [vp, i32, i32, C.POINTER(sz)]),
     "fio_bf_apply": (i32, [vp, vp, lg, vp, lg, i32, i32, vp, sz, vp]),
     "fio_bf_apply_adj": (i32, [vp, vp, lg, vp, lg, i32, i32, vp, sz, vp]),
+    "fio_bf_autotune": (i32, [vp, vp, lg, vp, lg, i32, i32, i32, vp, sz, vp, C.c_char_p, sz]),
+    "fio_bf_set_tile": (i32, [vp, i32, i32, i32, i32, i32, i32]),
     "fio_bf_destroy": (None, [vp]),
     "fio_set_fused": (None, [i32]),
     "fio_hss_set_big_node": (None, [i32]),

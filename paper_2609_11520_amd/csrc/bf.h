@@ -1,6 +1,17 @@
 // Butterfly factorization handle (Section 2.2) shared by the BF, HSS and solve units.
 #pragma once
+#include <map>
+
 #include "common.h"
+
+namespace fio {
+// Tile configuration of the applies for one (direction, precision, column bucket); 0 = the
+// built-in default.  kc: 2D column chunk (8 or 16); nsplit: 2D reduction split of the U / V^*
+// steps; kmax: 1D levels per fused pass.
+struct TileCfg {
+    int kc = 0, nsplit = 0, kmax = 0;
+};
+}  // namespace fio
 
 struct fio_bf_s {
     fio_bf_desc desc;
@@ -24,6 +35,8 @@ struct fio_bf_s {
     fio::DevBuf adj64, adj32;          // 2D: conjugate-transposed factor copies read by the adjoint
     fio::DevBuf ws;                    // handle-owned workspace (ws == NULL in the applies)
     std::mutex ws_mu;
+    std::map<int, fio::TileCfg> tuned; // fio_bf_autotune results, key tile_key(adj, prec, nrhs)
+    mutable std::mutex tune_mu;
 };
 
 namespace fio {
@@ -45,5 +58,9 @@ void bf2d_apply(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, 
 // permutation between user order and Morton order of a 2D grid (bf2d.hip)
 void permute2d(int n, bool to_internal, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs, hipStream_t s);
 size_t bf_ws_bytes(const fio_bf_s *bf, int nrhs, fio_prec prec);
+// column bucket of the tuned configurations: the next power of two of nrhs, capped at 64
+int tile_key(bool adj, fio_prec prec, int nrhs);
+// the tuned configuration for an apply (all zero when none was tuned)
+TileCfg bf_tile(const fio_bf_s *bf, bool adj, fio_prec prec, int nrhs);
 size_t bf_tw_off(const fio_bf_s *bf, bool cside, int lev);   // element offset of a level's twiddles
 }  // namespace fio

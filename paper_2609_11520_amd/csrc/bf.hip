@@ -12,6 +12,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <string>
 
 namespace fio {
 
@@ -381,6 +382,35 @@ size_t bf_ws_bytes(const fio_bf_s *bf, int nrhs, fio_prec prec) {
     return 0;
 }
 
+int tile_key(bool adj, fio_prec prec, int nrhs) {
+    int b = 0;
+    while (b < 6 && (1 << b) < nrhs) ++b;
+    return (adj ? 1 : 0) | ((int)prec << 1) | (b << 3);
+}
+
+TileCfg bf_tile(const fio_bf_s *bf, bool adj, fio_prec prec, int nrhs) {
+    std::lock_guard<std::mutex> lk(bf->tune_mu);
+    auto it = bf->tuned.find(tile_key(adj, prec, nrhs));
+    return it == bf->tuned.end() ? TileCfg{} : it->second;
+}
+
+// candidate tile configurations of an apply (the first is the built-in default)
+static std::vector<TileCfg> tile_candidates(const fio_bf_s *bf, fio_prec prec) {
+    std::vector<TileCfg> c;
+    c.push_back(TileCfg{});
+    if (bf->dim == 2) {
+        const long T = 1L << (2 * bf->lc);
+        const int nmax = (int)(T < 16 ? T : 16);
+        for (int kc : {8, 16})
+            for (int ns : {4, 8, 16})
+                if (ns <= nmax && T % ns == 0) c.push_back(TileCfg{kc, ns, 0});
+    } else if (bf->nl > 0 && bf->q == 9) {
+        for (int km : {1, 2, 3}) c.push_back(TileCfg{0, 0, km});
+    }
+    (void)prec;
+    return c;
+}
+
 void bf_apply_impl(fio_bf_s *bf, bool adjoint, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs,
                    fio_prec prec, void *ws, hipStream_t s, bool freq_internal) {
     if (nrhs <= 0) return;
@@ -523,6 +553,89 @@ extern "C" fio_status fio_bf_apply(fio_bf_t bf, const void *X, long ldx, void *Y
 extern "C" fio_status fio_bf_apply_adj(fio_bf_t bf, const void *X, long ldx, void *Y, long ldy, int nrhs,
                                        fio_prec prec, void *ws, size_t ws_bytes, void *stream) {
     return bf_apply_api(bf, true, X, ldx, Y, ldy, nrhs, prec, ws, ws_bytes, stream);
+}
+
+extern "C" fio_status fio_bf_set_tile(fio_bf_t bf, int adj, fio_prec prec, int nrhs, int kc, int nsplit, int kmax) {
+    FIO_CHECK_ARG(bf && nrhs > 0 && prec >= FIO_PREC_FP64 && prec <= FIO_PREC_SPLIT_FP16);
+    FIO_CHECK_ARG(kc == 0 || kc == 8 || kc == 16);
+    FIO_CHECK_ARG(kmax >= 0 && kmax <= 3 && nsplit >= 0);
+    if (bf->dim == 2 && nsplit > 0) {
+        const long T = 1L << (2 * bf->lc);
+        FIO_CHECK_ARG(nsplit <= (T < 16 ? T : 16) && T % nsplit == 0);
+    }
+    std::lock_guard<std::mutex> lk(bf->tune_mu);
+    bf->tuned[tile_key(adj != 0, prec, nrhs)] = TileCfg{kc, nsplit, kmax};
+    return FIO_OK;
+}
+
+extern "C" fio_status fio_bf_autotune(fio_bf_t bf, const void *X, long ldx, void *Y, long ldy, int nrhs,
+                                     fio_prec prec, int reps, void *ws, size_t ws_bytes, void *stream, char *report,
+                                     size_t report_len) {
+    FIO_CHECK_ARG(bf && nrhs > 0 && reps > 0 && X && Y && ldx >= bf->N && ldy >= bf->N);
+    FIO_CHECK_ARG(prec >= FIO_PREC_FP64 && prec <= FIO_PREC_SPLIT_FP16);
+    if (prec == FIO_PREC_FP32 && !bf->f32.p) return FIO_ERR_ARG;
+    if (prec == FIO_PREC_SPLIT_FP16 && !bf->split16) return FIO_ERR_ARG;
+    if (bf->dim == 2 && prec == FIO_PREC_SPLIT_FP16) return FIO_ERR_ARG;
+    const size_t need = bf_ws_bytes(bf, nrhs, prec);
+    if (ws && ws_bytes < need) return FIO_ERR_ARG;
+    return guarded([&] {
+        hipStream_t s = as_stream(stream);
+        if (!ws) {
+            std::lock_guard<std::mutex> lk(bf->ws_mu);
+            if (bf->ws.bytes < need) {
+                FIO_HIP(hipStreamSynchronize(s));
+                bf->ws.alloc(need);
+            }
+            ws = bf->ws.p;
+        }
+        hipEvent_t e0, e1;
+        FIO_HIP(hipEventCreate(&e0));
+        FIO_HIP(hipEventCreate(&e1));
+        std::string rep;
+        const std::vector<TileCfg> cand = tile_candidates(bf, prec);
+        for (int adj = 0; adj < 2; ++adj) {
+            const int key = tile_key(adj != 0, prec, nrhs);
+            float best = -1.f;
+            TileCfg bc{};
+            for (const TileCfg &c : cand) {
+                {
+                    std::lock_guard<std::mutex> lk(bf->tune_mu);
+                    bf->tuned[key] = c;
+                }
+                bf_apply_impl(bf, adj != 0, (const double2 *)X, ldx, (double2 *)Y, ldy, nrhs, prec, ws, s);
+                FIO_HIP(hipEventRecord(e0, s));
+                for (int r = 0; r < reps; ++r)
+                    bf_apply_impl(bf, adj != 0, (const double2 *)X, ldx, (double2 *)Y, ldy, nrhs, prec, ws, s);
+                FIO_HIP(hipEventRecord(e1, s));
+                FIO_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                FIO_HIP(hipEventElapsedTime(&ms, e0, e1));
+                ms /= (float)reps;
+                char buf[128];
+                snprintf(buf, sizeof buf, "%s kc=%d nsplit=%d kmax=%d %.4f ms; ", adj ? "adj" : "fwd", c.kc, c.nsplit,
+                         c.kmax, ms);
+                rep += buf;
+                if (best < 0.f || ms < best) {
+                    best = ms;
+                    bc = c;
+                }
+            }
+            std::lock_guard<std::mutex> lk(bf->tune_mu);
+            bf->tuned[key] = bc;
+            char buf[128];
+            snprintf(buf, sizeof buf, "chosen %s kc=%d nsplit=%d kmax=%d; ", adj ? "adj" : "fwd", bc.kc, bc.nsplit,
+                     bc.kmax);
+            rep += buf;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (report && report_len) {
+            const size_t n = rep.size() < report_len - 1 ? rep.size() : report_len - 1;
+            memcpy(report, rep.data(), n);
+            report[n] = 0;
+        }
+        return FIO_OK;
+    });
 }
 
 extern "C" void fio_bf_destroy(fio_bf_t bf) { delete bf; }

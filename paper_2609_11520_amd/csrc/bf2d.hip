@@ -461,7 +461,7 @@ void launch_leaf_in(const K2Args<T> &a_in, const G2 &g, unsigned chunks, unsigne
 // blocks), which halves how often the factors stream while the FMAs per factor entry double
 template <typename T, int KC>
 void apply2k(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs, const cpx<T> *F,
-             const cpx<T> *Fa, void *ws, bool fint, hipStream_t s) {
+             const cpx<T> *Fa, void *ws, bool fint, int nsplit, hipStream_t s) {
     using C = cpx<T>;
     const G2 g = g2_of(bf);
     const int ldc = (nrhs + KC - 1) / KC * KC;
@@ -473,7 +473,10 @@ void apply2k(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, lon
     const bool f64 = sizeof(T) == 8;
     const unsigned blkq = 64 * ((g.q2 + 63) / 64), blkb = 64 * ((g.b2 + 63) / 64);
     const long NP = bf->N;                            // pairs on either side
-    const int nsp = nsplit_of(g.T);
+    // reduction split of the U / V^* steps: a power of two dividing the T partner blocks, at most
+    // nsplit_of(T) (the workspace holds that many partial sums)
+    int nsp = nsplit_of(g.T);
+    if (nsplit > 0 && nsplit < nsp && g.T % nsplit == 0) nsp = nsplit;
     K2Args<T> a{};
     a.g = g;
     a.nrhs = nrhs;
@@ -538,10 +541,13 @@ void apply2k(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, lon
 template <typename T>
 void apply2(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs, const cpx<T> *F,
             const cpx<T> *Fa, void *ws, bool fint, hipStream_t s) {
-    if (nrhs >= 16)
-        apply2k<T, 16>(bf, adj, X, ldx, Y, ldy, nrhs, F, Fa, ws, fint, s);
+    // column chunk and reduction split: tuned (fio_bf_autotune) or 16 columns for wide blocks
+    const TileCfg c = bf_tile(bf, adj, sizeof(T) == 8 ? FIO_PREC_FP64 : FIO_PREC_FP32, nrhs);
+    const int kc = c.kc ? c.kc : (nrhs >= 16 ? 16 : 8);
+    if (kc == 16)
+        apply2k<T, 16>(bf, adj, X, ldx, Y, ldy, nrhs, F, Fa, ws, fint, c.nsplit, s);
     else
-        apply2k<T, 8>(bf, adj, X, ldx, Y, ldy, nrhs, F, Fa, ws, fint, s);
+        apply2k<T, 8>(bf, adj, X, ldx, Y, ldy, nrhs, F, Fa, ws, fint, c.nsplit, s);
 }
 
 }  // namespace

@@ -722,6 +722,10 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
     if constexpr (fused_q<Q>()) {
         fused = bf->nl > 0 && (split || !fused_disabled());
         kmax = fused_max_kl<T, Q>();
+        // levels per pass: tuned (fio_bf_autotune) or the most the LDS tile holds
+        const fio_prec pr = f64 ? FIO_PREC_FP64 : (split ? FIO_PREC_SPLIT_FP16 : FIO_PREC_FP32);
+        const int tk = bf_tile(bf, adj, pr, nrhs).kmax;
+        if (tk > 0 && tk < kmax) kmax = tk;
     }
     auto pass = [&](bool a, bool cside, int lo, int hi, bool epi) {
         if constexpr (fused_q<Q>()) {

@@ -1,0 +1,67 @@
+"""The tile autotuner of the applies (fio_bf_autotune, fio_bf_set_tile): every candidate
+configuration applies the same operator, so each is checked against the oracle, and the tuned
+handle still matches it."""
+import numpy as np
+import pytest
+
+import fio_inputs as fi
+from oracle import bf2d as obf2, fio2d as of2
+from gpu_common import fiohss, dev, host, rel, step, oracle_bf, gpu_bf
+
+pytestmark = pytest.mark.gpu
+
+
+def test_autotune_2d_candidates_match_oracle():
+    F = fiohss()
+    n, k = 32, 8                       # 16 partner blocks per leaf box: splits 4, 8, 16
+    step("autotune 2D n=%d" % n)
+    a0, a1 = of2.PHASE2_ANISO16
+    ob = obf2.BF2D(n, 9, of2.PHASE2_ANISO16)
+    B = F.BF(n, 9, a0, a1, precs=(F.FIO_PREC_FP64, F.FIO_PREC_FP32), dim=2, factors=ob.export_factors())
+    x = fi.complex_gaussian(31, fi.PURPOSE_PROBE, n * n, k)
+    rf, ra = ob.apply(x), ob.apply_adj(x)
+    for kc in (8, 16):
+        for ns in (4, 8, 16):
+            for adj in (False, True):
+                B.set_tile(k, adj=adj, kc=kc, nsplit=ns)
+            assert rel(host(B.apply(dev(x))), rf) < 1e-12
+            assert rel(host(B.apply_adj(dev(x))), ra) < 1e-12
+    with pytest.raises(F.FioError):
+        B.set_tile(k, nsplit=32)       # more than the partner count / the workspace holds
+    with pytest.raises(F.FioError):
+        B.set_tile(k, kc=12)
+    for prec in (F.FIO_PREC_FP64, F.FIO_PREC_FP32):
+        rep = B.autotune(dev(x), prec=prec, reps=3)
+        assert "chosen fwd" in rep and "chosen adj" in rep
+        step(rep)
+        tol = 1e-12 if prec == F.FIO_PREC_FP64 else 1e-5
+        assert rel(host(B.apply(dev(x), prec=prec)), rf) < tol
+        assert rel(host(B.apply_adj(dev(x), prec=prec)), ra) < tol
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_autotune_1d_levels_per_pass(prec):
+    F = fiohss()
+    n, k = 4096, 64                    # 3 transfer levels per side: passes of 1, 2 or 3 levels
+    step("autotune 1D prec=%d" % prec)
+    B = gpu_bf(F, n, 9, "sin16", imported=True, precs=(0, 1, 2))
+    ob = oracle_bf(n, 9, "sin16")
+    x = fi.complex_gaussian(32, fi.PURPOSE_PROBE, n, k)
+    rf, ra = ob.apply(x), ob.apply_adj(x)
+    tol = {0: 1e-12, 1: 1e-5, 2: 2e-5}[prec]
+    outs = []
+    for km in (1, 2, 3):
+        for adj in (False, True):
+            B.set_tile(k, prec=prec, adj=adj, kmax=km)
+        y, ya = host(B.apply(dev(x), prec=prec)), host(B.apply_adj(dev(x), prec=prec))
+        assert rel(y, rf) < tol and rel(ya, ra) < tol
+        outs.append((y, ya))
+    if prec != 2:
+        # FP64 / FP32 coefficients cross HBM unrounded between passes: identical results
+        for y, ya in outs[1:]:
+            assert np.array_equal(y, outs[0][0]) and np.array_equal(ya, outs[0][1])
+    rep = B.autotune(dev(x), prec=prec, reps=3)
+    step(rep)
+    assert "chosen fwd" in rep and "chosen adj" in rep
+    assert rel(host(B.apply(dev(x), prec=prec)), rf) < tol
+    assert rel(host(B.apply_adj(dev(x), prec=prec)), ra) < tol
