@@ -238,6 +238,11 @@ def serving(F, torch, fi, duration, rate, seed=4, rel_res=5e-9):
             "max_col_rel_err": err, "ir_steps": [o["nir"] for o in ops]}
 
 
+def chosen(report):
+    """The choices of a fio_bf_autotune report."""
+    return [x.strip()[len("chosen "):] for x in report.split(";") if x.strip().startswith("chosen")]
+
+
 def workload_2d(F, torch, fi, steps, warmup, rel_res=5e-9, solve=True):
     """2D workload (Section 5.3 phase, a = 1): n = 128 per dimension (N = 16384, odd L), q = 9
     (r = 81), 8 right-hand sides.  Times the BF applies (FP64 and FP32, forward and adjoint) with
@@ -254,6 +259,14 @@ def workload_2d(F, torch, fi, steps, warmup, rel_res=5e-9, solve=True):
     f = torch.from_numpy(np.ascontiguousarray(f_host.T)).to(dev).t()
     out = F.empty(N, k)
     ws = torch.empty(B.workspace_size(k, F.FIO_PREC_FP64), dtype=torch.uint8, device=dev)
+    # tile autotuner: the 8-column applies in both precisions, and the wide blocks (64+ columns)
+    # of the HSS sampling in FP64
+    tuned = {}
+    for prec, pn in ((F.FIO_PREC_FP64, "fp64_k8"), (F.FIO_PREC_FP32, "fp32_k8")):
+        tuned[pn] = chosen(B.autotune(f, prec=prec, reps=5, ws=ws))
+    wide = torch.randn((64, N), dtype=torch.complex128, device=dev).t()
+    tuned["fp64_k64"] = chosen(B.autotune(wide, prec=F.FIO_PREC_FP64, reps=2))
+    del wide
     applies, kstats = {}, {}
     for prec, pn in ((F.FIO_PREC_FP64, "fp64"), (F.FIO_PREC_FP32, "fp32")):
         for adj in (False, True):
@@ -289,7 +302,7 @@ def workload_2d(F, torch, fi, steps, warmup, rel_res=5e-9, solve=True):
             "algorithmic_flops_per_launch": flops}
     res = {"workload": "2D FIO n=128 (N=16384), Phi = x.xi + sqrt(c1^2 xi1^2 + c2^2 xi2^2) of Section 5.3, "
                        "q=9, 8 RHS (seed 1)",
-           "bf_build_s": round(t_bf, 3), "apply": applies, "roofline_middle": roof,
+           "bf_build_s": round(t_bf, 3), "autotuned_tiles": tuned, "apply": applies, "roofline_middle": roof,
            "kernels_ms": {kk: {kn: [c, round(m, 3)] for kn, (c, m) in v.items()} for kk, v in kstats.items()}}
     if solve:
         t = time.perf_counter()
@@ -411,6 +424,11 @@ def main():
     f = torch.from_numpy(np.ascontiguousarray(f_host.T)).to(dev).t()
     u = B.apply(f)
     sync()
+    # tile autotuner: levels per fused pass for the 64-column applies of each precision
+    tuned = {}
+    for prec, pn in ((F.FIO_PREC_FP64, "fp64"), (F.FIO_PREC_FP32, "fp32"), (F.FIO_PREC_SPLIT_FP16, "split16")):
+        tuned[pn] = chosen(B.autotune(u, prec=prec, reps=3))
+    log("autotuned tiles", json.dumps(tuned))
 
     results = {}
     kernel_stats = {}
@@ -560,7 +578,7 @@ def main():
         "config": {"workload": "1D FIO N=2^%d, c(x)=(2+sin 2pi x)/16, q=%d, HSS tol %g, p=10, %d RHS, "
                                "refinement steps calibrated to rel residual %g" % (int(np.log2(n)), q, a.hss_tol, k,
                                                                                     a.rel_res),
-                   "n": n, "nrhs": k, "q": q, "hss_tol": a.hss_tol, "mixed_variant": head,
+                   "n": n, "nrhs": k, "q": q, "hss_tol": a.hss_tol, "mixed_variant": head, "autotuned_tiles": tuned,
                    "hss_max_rank_per_level": {str(l): int(max(v)) for l, v in ranks.items()}},
         "mixed": results["mixed"], "split16": results["split16"], "fp64": results["fp64"],
         "direct_fp64": {"ms_per_step": round(ms_direct, 3), "value": k / (ms_direct / 1e3),
