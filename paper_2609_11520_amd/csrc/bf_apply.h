@@ -428,8 +428,14 @@ template <typename T, int Q> struct StructArgs {
 template <typename T, int Q, int KL, bool ADJ, bool EPI_M, bool CS>
 __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 8 : 4) k_struct_fused(StructArgs<T, Q> a) {
     using C = cpx<T>;
-    constexpr int P = 1 << KL;
+    constexpr int P = 1 << KL, NG = P / 2;
+    // double precision: the twiddles of the current factor's NG groups, fetched into registers
+    // during the previous factor (vector loads) and read back from LDS as broadcasts; single
+    // precision reads them through the scalar cache (its register budget has no room)
+    constexpr bool TWL = sizeof(T) == 8;
+    constexpr int NTW = TWL ? NG * 8 * Q : 1;
     __shared__ C lds[P * Q * 64];
+    __shared__ C stw[NTW];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -439,6 +445,16 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 8 : 4) k_stru
     const long A = blockIdx.x / nS, S = blockIdx.x % nS;
     const long Glast = a.G0 >> (KL - 1);
     const size_t ld = (size_t)a.nrhs;
+    static_assert(NTW <= P * 64, "one twiddle per thread");
+    // twiddle e (local group e / 8q, entry e % 8q) of forward step j
+    auto tw_src = [&](int j, int e) {
+        const int b = e / (8 * Q), o = e % (8 * Q);
+        const int Gl = P >> (j + 1);
+        const long g = (A * (1L << j) + b / Gl) * (a.G0 >> j) + S * Gl + b % Gl;
+        return a.TW[j][(size_t)g * 8 * Q + o];
+    };
+    C twn = czero<C>();
+    if (TWL && tid < NTW) stw[tid] = tw_src(ADJ ? KL - 1 : 0, tid);
     {
         const int lp = wave;
         const long gp = ADJ ? (A * P + lp) * Glast + S : A * 2 * a.G0 + S * P + lp;
@@ -459,7 +475,8 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 8 : 4) k_stru
         const int aj = grp / Gl, sj = grp % Gl;
         const long g = (A * (1L << j) + aj) * Gj + (S * Gl + sj);
         const int lin0 = aj * 2 * Gl + 2 * sj, lout0 = 2 * aj * Gl + sj;
-        const C *tw = a.TW[j] + (size_t)g * 8 * Q;
+        if (TWL && st + 1 < KL && tid < NTW) twn = tw_src(ADJ ? j - 1 : j + 1, tid);
+        const C *tw = TWL ? stw + grp * 8 * Q : a.TW[j] + (size_t)g * 8 * Q;
         C acc[Q];
 #pragma unroll
         for (int r = 0; r < Q; ++r) acc[r] = czero<C>();
@@ -510,6 +527,7 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 8 : 4) k_stru
         const int dst = ADJ ? lin0 + h : (h ? lout0 + Gl : lout0);
 #pragma unroll
         for (int r = 0; r < Q; ++r) lds[(dst * Q + r) * 64 + lane] = acc[r];
+        if (TWL && st + 1 < KL && tid < NTW) stw[tid] = twn;
         __syncthreads();
     }
     {
