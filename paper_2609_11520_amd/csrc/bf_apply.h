@@ -426,13 +426,13 @@ template <typename T, int Q> struct StructArgs {
 // Register budget: single precision keeps 8 waves per SIMD (four 37 KB workgroups per CU at
 // KL = 3, <= 64 VGPRs), double precision 4 (two 74 KB workgroups, LDS-bound anyway).
 template <typename T, int Q, int KL, bool ADJ, bool EPI_M, bool CS>
-__global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 8 : 4) k_struct_fused(StructArgs<T, Q> a) {
+__global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_struct_fused(StructArgs<T, Q> a) {
     using C = cpx<T>;
     constexpr int P = 1 << KL, NG = P / 2;
     // double precision: the twiddles of the current factor's NG groups, fetched into registers
     // during the previous factor (vector loads) and read back from LDS as broadcasts; single
     // precision reads them through the scalar cache (its register budget has no room)
-    constexpr bool TWL = sizeof(T) == 8;
+    constexpr bool TWL = true;
     constexpr int NTW = TWL ? NG * 8 * Q : 1;
     __shared__ C lds[P * Q * 64];
     __shared__ C stw[NTW];
