@@ -609,14 +609,21 @@ static void run_struct(const StructArgs<T, Q> &sa, int kl, bool adj, bool epi, l
 //   IN  = false: the vector from the coefficients (U forward, V^* adjoint).
 // Coarse partner c of leaf box b has pair index b nsl + c (U side) or c 2^L' + b (V side).
 template <typename T, int Q, bool IN, bool VSIDE>
-__global__ void __launch_bounds__(256) k_leaf_io(Geo g, const cpx<T> *__restrict__ Fblk,
+__global__ void __launch_bounds__(256, 4) k_leaf_io(Geo g, const cpx<T> *__restrict__ Fblk,
                                                  const double2 *__restrict__ Xin, long ldx,
                                                  const cpx<T> *__restrict__ cin, cpx<T> *__restrict__ cout,
                                                  double2 *__restrict__ Yout, long ldy, int nrhs) {
     using C = cpx<T>;
     constexpr int NB = 4;                           // leaf boxes per workgroup
     constexpr int R = NB * kLeafPts;                // rows per workgroup
+    constexpr int BLK = Q * kLeafPts;               // complex entries of one factor block
+    constexpr int NCH = BLK * (int)sizeof(C) / 16;  // its 16-byte chunks
+    constexpr int NPF = (NCH + 63) / 64;
     __shared__ C tile[64][R + 1];                   // [column][row]
+    // IN: one factor block per wave; the block of the wave's next unit is fetched into
+    // registers (vector loads) while the current one is applied, then written here and read
+    // back as broadcasts
+    __shared__ __attribute__((aligned(16))) C wblk[IN ? 4 : 1][IN ? BLK : 1];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const long box0 = (long)blockIdx.x * NB;        // first leaf box of the workgroup
@@ -625,7 +632,26 @@ __global__ void __launch_bounds__(256) k_leaf_io(Geo g, const cpx<T> *__restrict
     const int col = c0 + lane;
     const bool act = lane < ncol;
     const long Lp2 = 1L << g.Lp;
+    // V[sigma = box][tau = c] and U[tau = box][sigma = c] both sit at (box nsl + c) BLK
+    uint4 pf[NPF];
+    auto fetch = [&](long box, int c) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(Fblk + ((size_t)box * g.nsl + c) * BLK);
+#pragma unroll
+        for (int k = 0; k < NPF; ++k)
+            if (lane + 64 * k < NCH) pf[k] = src[lane + 64 * k];
+    };
+    auto stage = [&]() {
+        uint4 *dst = reinterpret_cast<uint4 *>(&wblk[IN ? wave : 0][0]);
+#pragma unroll
+        for (int k = 0; k < NPF; ++k)
+            if (lane + 64 * k < NCH) dst[lane + 64 * k] = pf[k];
+    };
     if (IN) {
+        const C *blk = &wblk[wave][0];
+        if (wave < NB * g.nsl) {
+            fetch(box0 + wave / g.nsl, wave % g.nsl);
+            stage();
+        }
         for (int e = tid; e < R * 64; e += 256) {
             const int r = e % R, cc = e / R;
             double2 v = cc < ncol ? Xin[(box0 * kLeafPts + r) + (size_t)(c0 + cc) * ldx] : zc(0.0, 0.0);
@@ -636,18 +662,13 @@ __global__ void __launch_bounds__(256) k_leaf_io(Geo g, const cpx<T> *__restrict
         for (int u = wave; u < NB * g.nsl; u += 4) {
             const int b = u / g.nsl, c = u % g.nsl;
             const long box = box0 + b;
+            const int un = u + 4;
+            if (un < NB * g.nsl) fetch(box0 + un / g.nsl, un % g.nsl);
             C x[kLeafPts];
 #pragma unroll
             for (int s = 0; s < kLeafPts; ++s) x[s] = tile[lane][b * kLeafPts + s];
-            size_t p;
-            const C *blk;
-            if (VSIDE) {    // V: block V[sigma = box][tau = c] (q x 8), pair c 2^L' + box
-                p = (size_t)c * Lp2 + box;
-                blk = Fblk + ((size_t)box * g.nsl + c) * Q * kLeafPts;
-            } else {        // U^*: block U[tau = box][sigma = c] (8 x q), pair box nsl + c
-                p = (size_t)box * g.nsl + c;
-                blk = Fblk + p * (size_t)kLeafPts * Q;
-            }
+            // V: block (q x 8) for pair c 2^L' + box; U^*: block (8 x q) for pair box nsl + c
+            const size_t p = VSIDE ? (size_t)c * Lp2 + box : (size_t)box * g.nsl + c;
             C *op = cout + p * Q * (size_t)nrhs + col;
 #pragma unroll
             for (int j = 0; j < Q; ++j) {
@@ -661,6 +682,10 @@ __global__ void __launch_bounds__(256) k_leaf_io(Geo g, const cpx<T> *__restrict
                 }
                 if (act) op[(size_t)j * nrhs] = acc;
             }
+            // the wave's reads of this block precede the overwrite (LDS runs a wave's accesses in order)
+            __builtin_amdgcn_wave_barrier();
+            if (un < NB * g.nsl) stage();
+            __builtin_amdgcn_wave_barrier();
         }
     } else {
         // each wave produces one box's rows for its lane's column
@@ -670,15 +695,11 @@ __global__ void __launch_bounds__(256) k_leaf_io(Geo g, const cpx<T> *__restrict
 #pragma unroll
             for (int s = 0; s < kLeafPts; ++s) acc[s] = czero<C>();
             for (int c = 0; c < g.nsl; ++c) {
-                size_t p;
-                const C *blk;
-                if (VSIDE) {    // V^*: block V[sigma = box][tau = c], pair c 2^L' + box
-                    p = (size_t)c * Lp2 + box;
-                    blk = Fblk + ((size_t)box * g.nsl + c) * Q * kLeafPts;
-                } else {        // U: block U[tau = box][sigma = c], pair box nsl + c
-                    p = (size_t)box * g.nsl + c;
-                    blk = Fblk + p * (size_t)kLeafPts * Q;
-                }
+                // V^*: block V[sigma = box][tau = c], pair c 2^L' + box; U: block U[tau = box][sigma = c],
+                // pair box nsl + c.  The block is read through the scalar cache here (as LDS values
+                // the compiler would hold all of it in vector registers).
+                const size_t p = VSIDE ? (size_t)c * Lp2 + box : (size_t)box * g.nsl + c;
+                const C *blk = Fblk + ((size_t)box * g.nsl + c) * BLK;
                 C d[Q];
                 const C *ip = cin + p * Q * (size_t)nrhs + col;
 #pragma unroll
