@@ -454,6 +454,8 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_stru
         return a.TW[j][(size_t)g * 8 * Q + o];
     };
     C twn = czero<C>();
+    constexpr int NMP = (Q * Q + 63) / 64;
+    C mpf[NMP];
     if (TWL && tid < NTW) stw[tid] = tw_src(ADJ ? KL - 1 : 0, tid);
     {
         const int lp = wave;
@@ -476,6 +478,14 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_stru
         const long g = (A * (1L << j) + aj) * Gj + (S * Gl + sj);
         const int lin0 = aj * 2 * Gl + 2 * sj, lout0 = 2 * aj * Gl + sj;
         if (TWL && st + 1 < KL && tid < NTW) twn = tw_src(ADJ ? j - 1 : j + 1, tid);
+        if (EPI_M && st == KL - 1) {
+            // the middle block of this wave's output pair, for the store phase
+            const long gpo = ADJ ? A * 2 * a.G0 + S * P + wave : (A * P + wave) * Glast + S;
+            const C *msrc = a.M + (size_t)gpo * Q * Q;
+#pragma unroll
+            for (int k2 = 0; k2 < NMP; ++k2)
+                if (lane + 64 * k2 < Q * Q) mpf[k2] = msrc[lane + 64 * k2];
+        }
         const C *tw = TWL ? stw + grp * 8 * Q : a.TW[j] + (size_t)g * 8 * Q;
         C acc[Q];
 #pragma unroll
@@ -538,7 +548,15 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_stru
             C x[Q];
 #pragma unroll
             for (int i = 0; i < Q; ++i) x[i] = lds[(lp * Q + i) * 64 + lane];
-            const C *m = a.M + (size_t)gp * Q * Q;
+            // the pair's rows of the tile are this wave's alone now: the prefetched middle block
+            // goes there and is read back as broadcasts
+            __builtin_amdgcn_wave_barrier();
+            C *mst = lds + (size_t)lp * Q * 64;
+#pragma unroll
+            for (int k2 = 0; k2 < NMP; ++k2)
+                if (lane + 64 * k2 < Q * Q) mst[lane + 64 * k2] = mpf[k2];
+            __builtin_amdgcn_wave_barrier();
+            const C *m = mst;
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 C acc = czero<C>();
