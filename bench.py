@@ -108,12 +108,12 @@ def kernel_model(name, n, q, k):
     es = 16 if name.endswith("f64") else 8
     if name == "bf_split16":
         # one split pass: FP32 coefficients read and written once, the hi/lo block planes of
-        # every group of each level (2880 bytes), the FP32 middle blocks on the pass that applies
-        # M; per group and column three real 36 x 36 products (the complex 18 x 18 block)
+        # every group of each level (2880 bytes; the middle factor is folded into them); per
+        # group and column three real 36 x 36 products (the complex 18 x 18 block)
         plan = pass_plan(n)
         byts = flops = 0.0
         for kl, epi in plan:
-            byts += 2 * n * q * k * 8 + kl * (n // 2) * 2880 + (n * q * q * 8 if epi else 0)
+            byts += 2 * n * q * k * 8 + kl * (n // 2) * 2880
             flops += kl * (n // 2) * k * 3 * 2 * (4 * q) ** 2
         return byts / len(plan), flops / len(plan)
     if name.startswith("bf_struct"):
