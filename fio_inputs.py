@@ -14,6 +14,7 @@ PURPOSE_RHS = 1       # solution vectors f (u is formed from them)
 PURPOSE_OMEGA = 2     # HSS test matrices Omega^[l]
 PURPOSE_PROBE = 3     # auxiliary probe vectors used by tests
 PURPOSE_DATA = 4      # arbitrary test data (synthetic generators, etc.)
+PURPOSE_AMP = 5       # centers of the Gaussian-sum amplitude (Section 5.1)
 
 
 def _gen(seed, purpose, level=0):
@@ -57,3 +58,11 @@ def poisson_arrivals(seed, rate, duration):
 def integers(seed, purpose, lo, hi, size, level=0):
     g = _gen(seed, purpose, level)
     return g.integers(lo, hi, size=size, endpoint=True)
+
+
+def amplitude_centers(seed, n, m=10):
+    """Centers (x_k, xi_k) of Section 5.1's amplitude, uniform in [0, 1] x [-n/2, n/2]
+    (m = 10 in the paper; it does not give the draws)."""
+    g = _gen(seed, PURPOSE_AMP)
+    u = g.random((2, m))
+    return u[0].copy(), (u[1] - 0.5) * n

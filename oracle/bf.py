@@ -49,13 +49,16 @@ from .fio import phase, kernel, spatial_grid, frequency_grid
 
 
 class BF1D:
-    """Explicit BF factors of the 1D FIO with phase parameters ``params``."""
+    """Explicit BF factors of the 1D FIO with phase parameters ``params`` and amplitude ``amp``
+    (a callable a(x, xi), None for a = 1).  The interpolation factors U, B, C, V carry only the
+    phase (Section 2.2 interpolates the residual phase factor); the amplitude enters through
+    the kernel values of the middle factor, M = k(Z, Gamma) (eq. bf_kernel_func_low_rank)."""
 
-    def __init__(self, n, q, params, level_offset=3):
+    def __init__(self, n, q, params, level_offset=3, amp=None):
         L = int(round(np.log2(n)))
         if 2 ** L != n or L % 2 != 0 or L < 2:
             raise ValueError("N must be 2^L with L even")
-        self.N, self.L, self.q, self.params = n, L, q, params
+        self.N, self.L, self.q, self.params, self.amp = n, L, q, params, amp
         self.h = L // 2
         self.Lp = max(L - level_offset, self.h)
         self.b = n >> self.Lp                     # points per leaf box
@@ -146,7 +149,7 @@ class BF1D:
         # M at the middle level h
         z = self._s_cheb_all(h)                                   # (tau, i)
         g = self._f_cheb_all(h)                                   # (sigma, j)
-        self.M = kernel(z[:, None, :, None], g[None, :, None, :], P).reshape(N, q, q)
+        self.M = kernel(z[:, None, :, None], g[None, :, None, :], P, self.amp).reshape(N, q, q)
 
         # B^[l+1], l = h..L'-1
         self.B = []
@@ -253,5 +256,5 @@ def sampled_rel_error(bf, f, rows):
     """Section 5's e_cBF estimator restricted to the given output rows."""
     from .fio import dense_K_rows
     u = bf.apply(f)
-    ku = dense_K_rows(bf.N, rows, bf.params) @ f
+    ku = dense_K_rows(bf.N, rows, bf.params, bf.amp) @ f
     return np.linalg.norm(u[rows] - ku) / np.linalg.norm(ku)

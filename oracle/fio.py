@@ -2,7 +2,8 @@
 
 Oracle (test infrastructure only).  Follows Section 1, eq. (fio) and
 (fio_mat): X = {i/n}, Xi = {-n/2, ..., n/2-1}, K_ij = a(x_i, xi_j) exp(2 pi i
-Phi(x_i, xi_j)) with a = 1 for every workload built here.
+Phi(x_i, xi_j)).  The amplitude is 1 unless a callable ``amp(x, xi)`` is given;
+``gaussian_amplitude`` builds Section 5.1's variable amplitude.
 
 Vector ordering (a reading; the paper defines only the sets): entry i of a
 spatial vector is x = i/N, entry j of a frequency vector is xi = j - N/2,
@@ -40,23 +41,42 @@ def phase(x, xi, params):
     return x * xi + c_of_x(x, params) * np.abs(xi)
 
 
-def kernel(x, xi, params):
-    """k(x, xi) = exp(2 pi i Phi(x, xi)) (amplitude 1)."""
-    return np.exp(2j * np.pi * phase(x, xi, params))
+def gaussian_amplitude(n, centers_x, centers_xi, sigma2):
+    """Section 5.1's amplitude: a(x, xi) = sum_k exp(-((x - x_k)^2 + ((xi - xi_k) / N)^2) / sigma^2),
+    with centers (x_k, xi_k) given (the paper draws them at random in [0, 1] x [-N/2, N/2])."""
+    cx = np.asarray(centers_x, dtype=np.float64)
+    cxi = np.asarray(centers_xi, dtype=np.float64)
+
+    def amp(x, xi):
+        x = np.asarray(x, dtype=np.float64)[..., None]
+        xi = np.asarray(xi, dtype=np.float64)[..., None]
+        return np.exp(-((x - cx) ** 2 + ((xi - cxi) / n) ** 2) / sigma2).sum(axis=-1)
+
+    return amp
 
 
-def dense_K(n, params):
+def kernel(x, xi, params, amp=None):
+    """k(x, xi) = a(x, xi) exp(2 pi i Phi(x, xi)) (a = 1 when amp is None)."""
+    k = np.exp(2j * np.pi * phase(x, xi, params))
+    if amp is not None:
+        x = np.asarray(x, dtype=np.float64)
+        xi = np.asarray(xi, dtype=np.float64)
+        k = k * amp(*np.broadcast_arrays(x, xi))
+    return k
+
+
+def dense_K(n, params, amp=None):
     """The N x N matrix K of eq. (fio_mat)."""
     x = spatial_grid(n)[:, None]
     xi = frequency_grid(n)[None, :]
-    return kernel(x, xi, params)
+    return kernel(x, xi, params, amp)
 
 
-def dense_K_rows(n, rows, params):
+def dense_K_rows(n, rows, params, amp=None):
     """Selected rows of K (for sampled checks at large N)."""
     x = spatial_grid(n)[np.asarray(rows)][:, None]
     xi = frequency_grid(n)[None, :]
-    return kernel(x, xi, params)
+    return kernel(x, xi, params, amp)
 
 
 def dft_apply(f):
