@@ -87,6 +87,17 @@ typedef struct {
     unsigned prec_mask;      /* bit p set: keep a copy of the factors in fio_prec p resident;
                                 FIO_PREC_SPLIT_FP16 (dim 1, q = 9 only, else FIO_ERR_UNSUPPORTED
                                 at build/import) also keeps the FP32 copy */
+    /* Amplitude (dim 1 only; dim 2 with amp_terms > 0 returns FIO_ERR_UNSUPPORTED):
+     * amp_terms = 0 gives a = 1; 1 <= amp_terms <= 16 gives Section 5.1's variable amplitude
+     *   a(x, xi) = sum_k exp(-((x - x_k)^2 + ((xi - xi_k) / N)^2) / amp_sigma2),
+     * with the centers in HOST memory at amp_centers (x_1 .. x_m, then xi_1 .. xi_m), copied
+     * when the descriptor is planned (build, import, factor count).  The interpolation factors
+     * U, B, C, V do not depend on a; it enters the middle factor, M = k(Z, Gamma) with
+     * k = a exp(2 pi i Phi) (eq. bf_kernel_func_low_rank).  FIO_ERR_ARG for amp_terms outside
+     * 0..16, amp_sigma2 <= 0 or a NULL amp_centers with amp_terms > 0. */
+    int amp_terms;
+    double amp_sigma2;
+    const double *amp_centers;
 } fio_bf_desc;
 
 /* Number of complex entries of the explicit factors of `desc`, in the layout

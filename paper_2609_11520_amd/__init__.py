@@ -70,12 +70,20 @@ class BF:
            c2 = c0 + c1 cos cos (Section 5.3), n points per dimension, N = n^2."""
 
     def __init__(self, n, q=9, c0=2.0 / 16, c1=1.0 / 16, level_offset=3, precs=(FIO_PREC_FP64,), factors=None,
-                 dim=1):
+                 dim=1, amp=None):
+        """amp: None (a = 1) or (centers_x, centers_xi, sigma2) for Section 5.1's Gaussian-sum amplitude."""
         L = lib()
         mask = 0
         for p in precs:
             mask |= 1 << p
-        self.desc = _lib.BfDesc(dim, n, c0, c1, q, level_offset, mask)
+        if amp is None:
+            self._amp = None
+            self.desc = _lib.BfDesc(dim, n, c0, c1, q, level_offset, mask, 0, 0.0, None)
+        else:
+            cx, cxi, s2 = amp
+            self._amp = np.ascontiguousarray(np.concatenate([np.asarray(cx, float), np.asarray(cxi, float)]))
+            self.desc = _lib.BfDesc(dim, n, c0, c1, q, level_offset, mask, len(cx), float(s2),
+                                    self._amp.ctypes.data_as(C.c_void_p))
         self.dim, self.q = dim, q
         self.n = n if dim == 1 else n * n          # vector length
         h = C.c_void_p()

@@ -22,7 +22,8 @@ class FioError(RuntimeError):
 
 class BfDesc(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_long), ("c0", C.c_double), ("c1", C.c_double), ("q", C.c_int),
-                ("level_offset", C.c_int), ("prec_mask", C.c_uint)]
+                ("level_offset", C.c_int), ("prec_mask", C.c_uint), ("amp_terms", C.c_int),
+                ("amp_sigma2", C.c_double), ("amp_centers", C.c_void_p)]
 
 
 class HssOpts(C.Structure):

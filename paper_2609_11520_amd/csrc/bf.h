@@ -11,6 +11,13 @@ namespace fio {
 struct TileCfg {
     int kc = 0, nsplit = 0, kmax = 0;
 };
+// Section 5.1's Gaussian-sum amplitude (m = 0: a = 1), passed to the factor generation by value
+constexpr int kMaxAmpTerms = 16;
+struct Amp {
+    int m = 0;
+    double s2 = 1.0;
+    double x[kMaxAmpTerms] = {}, xi[kMaxAmpTerms] = {};
+};
 }  // namespace fio
 
 struct fio_bf_s {
@@ -33,6 +40,7 @@ struct fio_bf_s {
     fio::DevBuf tw64, tw32;
     double Pchild[2 * 16 * 16] = {};
     fio::DevBuf adj64, adj32;          // 2D: conjugate-transposed factor copies read by the adjoint
+    fio::Amp amp;                      // amplitude of the kernel (copied from the descriptor)
     fio::DevBuf ws;                    // handle-owned workspace (ws == NULL in the applies)
     std::mutex ws_mu;
     std::map<int, fio::TileCfg> tuned; // fio_bf_autotune results, key tile_key(adj, prec, nrhs)

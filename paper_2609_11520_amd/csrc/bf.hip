@@ -26,7 +26,16 @@ fio_status bf_plan(const fio_bf_desc *d, fio_bf_s *bf) {
     while ((1L << L) < d->n) ++L;
     if (L % 2) return FIO_ERR_UNSUPPORTED;
     if (d->q < 2 || d->q > 16 || d->level_offset < 1) return FIO_ERR_ARG;
+    if (d->amp_terms < 0 || d->amp_terms > kMaxAmpTerms) return FIO_ERR_ARG;
+    if (d->amp_terms > 0 && (!(d->amp_sigma2 > 0.0) || !d->amp_centers)) return FIO_ERR_ARG;
     bf->desc = *d;
+    bf->desc.amp_centers = nullptr;          // the handle keeps its own copy
+    bf->amp.m = d->amp_terms;
+    bf->amp.s2 = d->amp_terms > 0 ? d->amp_sigma2 : 1.0;
+    for (int k = 0; k < d->amp_terms; ++k) {
+        bf->amp.x[k] = d->amp_centers[k];
+        bf->amp.xi[k] = d->amp_centers[d->amp_terms + k];
+    }
     bf->N = d->n;
     bf->n1 = d->n;
     bf->L = L;
@@ -145,7 +154,18 @@ __global__ void gen_C(Geo g, int l, double2 *out) {
 }
 
 // M[p][i][j] = k(z_tau,i, gamma_sigma,j), p = tau 2^h + sigma
-__global__ void gen_M(Geo g, double2 *out) {
+// a(z, gamma) of Section 5.1 (1 when the amplitude has no terms)
+__device__ double amp_at(const Amp &a, double z, double gam, double N) {
+    if (a.m == 0) return 1.0;
+    double s = 0.0;
+    for (int k = 0; k < a.m; ++k) {
+        const double dx = z - a.x[k], dxi = (gam - a.xi[k]) / N;
+        s += exp(-(dx * dx + dxi * dxi) / a.s2);
+    }
+    return s;
+}
+
+__global__ void gen_M(Geo g, Amp am, double2 *out) {
     const int q = g.q;
     size_t n = (size_t)g.N * q * q;
     size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -176,7 +196,9 @@ __global__ void gen_M(Geo g, double2 *out) {
     double sz = g.c1 * sinpi(2.0 * z);
     double p1 = sz * aeta, e1 = fma(sz, aeta, -p1);
     ph += frac_rint(p0) + e0 + frac_rint(p1) + e1 + (g.c0 + sz) * sgn * dg;
-    out[id] = e2pi(ph);
+    const double2 e = e2pi(ph);
+    const double av = amp_at(am, z, gam, (double)g.N);
+    out[id] = zc(e.x * av, e.y * av);
 }
 
 // B^[l+1]: group (alpha at spatial level l, sigma at frequency level L-l-1)
@@ -321,7 +343,7 @@ static void bf_generate(fio_bf_s *bf, hipStream_t s) {
         gen_B<<<grid1d(nT, T), T, 0, s>>>(g, bf->h + lev, base + bf->offB[lev]);
     }
     size_t nM = (size_t)bf->N * bf->q * bf->q;
-    gen_M<<<grid1d(nM, T), T, 0, s>>>(g, base + bf->offM);
+    gen_M<<<grid1d(nM, T), T, 0, s>>>(g, bf->amp, base + bf->offM);
     gen_U<<<grid1d(nV, T), T, 0, s>>>(g, base + bf->offU);
     FIO_HIP(hipGetLastError());
     // structured transfer twiddles and the shared Lagrange matrices

@@ -555,6 +555,7 @@ void apply2(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long
 // ---------------------------------------------------------------------------
 fio_status bf2d_plan(const fio_bf_desc *d, fio_bf_s *bf) {
     if (d->n < 4 || d->n > (1L << 15) || (d->n & (d->n - 1))) return FIO_ERR_ARG;
+    if (d->amp_terms != 0) return FIO_ERR_UNSUPPORTED;         // variable amplitude: 1D only
     if (d->q < 2 || d->q > 16 || d->level_offset < 1) return FIO_ERR_ARG;
     int L = 0;
     while ((1L << L) < d->n) ++L;

@@ -1,0 +1,118 @@
+"""GPU parity of the variable-amplitude FIO (Section 5.1: Gaussian-sum amplitude, m = 10,
+sigma^2 = 0.1, phase (2 + sin 2 pi x)/8 |xi|): factor generation and applies against the
+oracle and the dense amplitude-weighted K, solves to 1e-8, the full-size configuration."""
+import numpy as np
+import pytest
+
+import fio_inputs as fi
+from oracle import bf as obf, fio as ofio, solve as osolve
+from gpu_common import fiohss, dev, host, rel, step
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(float).eps
+SIGMA2 = 0.1
+
+
+def amp_of(n, seed=1):
+    cx, cxi = fi.amplitude_centers(seed, n)
+    return (cx, cxi, SIGMA2), ofio.gaussian_amplitude(n, cx, cxi, SIGMA2)
+
+
+def gpu_bf_amp(F, n, amp, precs=None, factors=None):
+    c0, c1 = ofio.PHASE_SIN8
+    return F.BF(n, 9, c0, c1, precs=precs or (F.FIO_PREC_FP64,), amp=amp, factors=factors)
+
+
+@pytest.mark.parametrize("n", [1024, 4096])
+def test_factors_with_amplitude_match_oracle(n):
+    F = fiohss()
+    step("amplitude factors n=%d" % n)
+    amp, a = amp_of(n)
+    B = gpu_bf_amp(F, n, amp)
+    ob = obf.BF1D(n, 9, ofio.PHASE_SIN8, amp=a)
+    got, ref = B.export(), ob.export_factors()
+    # the amplitude (a sum of 10 terms <= 1) multiplies the unit-modulus middle entries; the
+    # oracle evaluates each phase naively (2 pi eps |Phi|, |Phi| <= 0.75 N / 2 at this phase)
+    tol = 10 * (8 * np.pi * EPS * 0.75 * n + 1e-13)
+    assert np.max(np.abs(got - ref)) < tol
+    x = fi.complex_gaussian(41, fi.PURPOSE_PROBE, n, 5)
+    assert rel(host(B.apply(dev(x))), ob.apply(x)) < 20 * tol
+    assert rel(host(B.apply_adj(dev(x))), ob.apply_adj(x)) < 20 * tol
+    # imported oracle factors: the apply kernels alone
+    Bi = gpu_bf_amp(F, n, amp, factors=ref)
+    assert rel(host(Bi.apply(dev(x))), ob.apply(x)) < 1e-12
+
+
+def test_apply_with_amplitude_vs_dense_K():
+    F = fiohss()
+    n = 1024
+    step("amplitude vs dense K")
+    amp, a = amp_of(n, seed=2)
+    B = gpu_bf_amp(F, n, amp, precs=(0, 1, 2))
+    K = ofio.dense_K(n, ofio.PHASE_SIN8, a)
+    f = fi.rhs(0, n, 3)
+    e = rel(host(B.apply(dev(f))), K @ f)
+    # q = 9 at this amplitude: the oracle's butterfly is 1.6e-5 from K at N = 1024
+    assert 1e-7 < e < 1e-4
+    ea = rel(host(B.apply_adj(dev(f))), K.conj().T @ f)
+    assert 1e-7 < ea < 1e-4
+    for p in (1, 2):
+        assert rel(host(B.apply(dev(f), prec=p)), host(B.apply(dev(f)))) < 2e-5
+
+
+def test_solve_with_amplitude():
+    F = fiohss()
+    n = 4096
+    step("amplitude solve n=%d" % n)
+    amp, a = amp_of(n, seed=3)
+    B = gpu_bf_amp(F, n, amp, precs=(0, 1, 2))
+    U = F.ULV(F.HSS.from_bf(B, tol=1e-3, p=10, seed=13))
+    f = fi.rhs(1, n, 8)
+    u = B.apply(dev(f))
+    fd, _ = F.approx_solve(B, U, u)
+    assert osolve.col_rel_err(host(fd), f) < 5e-2
+    for p in (0, 1, 2):
+        fr, info = F.approx_solve(B, U, u, mode=F.FIO_SOLVE_IR, prec=p, rel_res_tol=1e-10, max_ir=10)
+        assert info.rel_res <= 1e-10 and osolve.col_rel_err(host(fr), f) < 1e-8
+    fp, info = F.approx_solve(B, U, u, mode=F.FIO_SOLVE_PCG, rel_res_tol=1e-12, max_ir=30)
+    assert info.ir_steps <= 10 and osolve.col_rel_err(host(fp), f) < 1e-10
+
+
+def test_full_size_section51_configuration():
+    """N = 2^18, Section 5.1's amplitude and phase: sampled rows of the dense K, the adjoint
+    identity, and the split-FP16 refinement to 1e-8 on 16 right-hand sides."""
+    F = fiohss()
+    n, k = 1 << 18, 16
+    step("amplitude full size build")
+    amp, a = amp_of(n, seed=4)
+    B = gpu_bf_amp(F, n, amp, precs=(0, 1, 2))
+    f = fi.rhs(1, n, k)
+    y = host(B.apply(dev(f)))
+    rows = np.sort(np.random.default_rng(6).choice(n, 48, replace=False))
+    Kr = ofio.dense_K_rows(n, rows, ofio.PHASE_SIN8, a)
+    e = rel(y[np.ix_(rows, [0, 7])], Kr @ f[:, [0, 7]])
+    assert 1e-7 < e < 1e-4
+    g = fi.complex_gaussian(42, fi.PURPOSE_PROBE, n, 2)
+    z = host(B.apply_adj(dev(g)))
+    lhs = np.einsum('ik,ik->k', g.conj(), y[:, :2])
+    rhs = np.einsum('ik,ik->k', z.conj(), f[:, :2])
+    assert np.max(np.abs(lhs - rhs) / np.abs(lhs)) < 1e-12
+    step("amplitude full size solve")
+    U = F.ULV(F.HSS.from_bf(B, tol=1e-3, p=10, seed=14))
+    u = B.apply(dev(f))
+    fr, info = F.approx_solve(B, U, u, mode=F.FIO_SOLVE_IR, prec=F.FIO_PREC_SPLIT_FP16, rel_res_tol=5e-9,
+                              max_ir=8)
+    assert info.rel_res <= 5e-9 and osolve.col_rel_err(host(fr), f) < 1e-8
+
+
+def test_amplitude_argument_errors():
+    F = fiohss()
+    c0, c1 = ofio.PHASE_SIN8
+    cx, cxi = fi.amplitude_centers(1, 1024, m=17)
+    with pytest.raises(F.FioError):
+        F.BF(1024, 9, c0, c1, amp=(cx, cxi, SIGMA2))         # more than 16 terms
+    cx, cxi = fi.amplitude_centers(1, 1024)
+    with pytest.raises(F.FioError):
+        F.BF(1024, 9, c0, c1, amp=(cx, cxi, 0.0))            # sigma^2 must be positive
+    with pytest.raises(F.FioError):
+        F.BF(16, 9, 2.0 / 16, 1.0 / 16, dim=2, amp=(cx, cxi, SIGMA2))   # 1D only
