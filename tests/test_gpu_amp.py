@@ -80,7 +80,9 @@ def test_solve_with_amplitude():
 
 def test_full_size_section51_configuration():
     """N = 2^18, Section 5.1's amplitude and phase: sampled rows of the dense K, the adjoint
-    identity, and the split-FP16 refinement to 1e-8 on 16 right-hand sides."""
+    identity, and the split-FP16 refinement to 1e-8 on 16 right-hand sides.  The amplitude makes
+    K~ worse conditioned than the unit-amplitude operator (a residual of 5e-9 leaves errors near
+    2e-8 on some of 64 columns), so the refinement runs to a residual of 1e-9."""
     F = fiohss()
     n, k = 1 << 18, 16
     step("amplitude full size build")
@@ -100,9 +102,9 @@ def test_full_size_section51_configuration():
     step("amplitude full size solve")
     U = F.ULV(F.HSS.from_bf(B, tol=1e-3, p=10, seed=14))
     u = B.apply(dev(f))
-    fr, info = F.approx_solve(B, U, u, mode=F.FIO_SOLVE_IR, prec=F.FIO_PREC_SPLIT_FP16, rel_res_tol=5e-9,
+    fr, info = F.approx_solve(B, U, u, mode=F.FIO_SOLVE_IR, prec=F.FIO_PREC_SPLIT_FP16, rel_res_tol=1e-9,
                               max_ir=8)
-    assert info.rel_res <= 5e-9 and osolve.col_rel_err(host(fr), f) < 1e-8
+    assert info.rel_res <= 1e-9 and osolve.col_rel_err(host(fr), f) < 1e-8
 
 
 def test_amplitude_argument_errors():
