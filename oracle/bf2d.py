@@ -2,9 +2,9 @@
 
 Oracle (test infrastructure only).  Section 2.2, eq. (bf) and (bf_mid), with
 the quadtree of Section 2.2 in two dimensions, the outermost factors at level
-L' = max(L - 3, h) (implementation note of Section 5.3), and L = log2 n.
+L' = max(L - 3, h) (implementation note of Section 5.2), and L = log2 n.
 
-Odd L (a reading; Section 2.2 assumes L even while Section 5.3 reports 2D runs
+Odd L (a reading; Section 2.2 assumes L even while Sections 5.2 and 5.3 report 2D runs
 with L = 7): the middle level is h = ceil(L/2) on both sides, lc = L - h.
   U side: pairs (tau at spatial level h, sigma' at frequency level lc).
   V side: pairs (tau' at spatial level lc, sigma at frequency level h).
@@ -21,7 +21,8 @@ Lagrange basis is the product of the 1D bases.
 
 Factor entries (Section 2.2), y, eta box centers:
   V_{tau',sigma}(i, xi) = exp(2 pi i (Phi(y_tau', xi) - Phi(y_tau', gamma_sigma,i))) q_sigma,i(xi)
-  M_{tau,sigma}(i, j)   = k(z_tau,i, gamma_sigma,j)
+  M_{tau,sigma}(i, j)   = k(z_tau,i, gamma_sigma,j)   (k = a exp(2 pi i Phi), the amplitude
+                                                     enters here only, as in 1D)
   U_{tau,sigma'}(x, i)  = exp(2 pi i (Phi(x, eta_sigma') - Phi(z_tau,i, eta_sigma'))) p_tau,i(x)
 
 export_factors() writes them in the library's import layout (Morton box order,
@@ -34,7 +35,8 @@ from .fio2d import phase, kernel, morton_code, morton_decode
 
 
 class BF2D:
-    def __init__(self, n, q, params, level_offset=3):
+    def __init__(self, n, q, params, level_offset=3, amp=None):
+        self.amp = amp
         L = int(round(np.log2(n)))
         if 2 ** L != n or L < 2:
             raise ValueError("n must be 2^L, L >= 2")
@@ -94,7 +96,7 @@ class BF2D:
         z = self._s_cheb(self.h)
         g = self._f_cheb(self.h)
         return kernel(z[u1][None, None, :, None, None, None], z[u2][None, None, None, :, None, None],
-                      g[:, None, None, None, :, None], g[None, :, None, None, None, :], self.params)
+                      g[:, None, None, None, :, None], g[None, :, None, None, None, :], self.params, self.amp)
 
     def U_blocks(self, u1, u2):
         """U_{tau,sigma'} for tau = (u1, u2) at level h and every sigma' at level lc:

@@ -2,17 +2,21 @@
 
 Oracle (test infrastructure only).  Section 1, eq. (fio) and (fio_mat) in two
 dimensions with n points per dimension, N = n^2: X = {(i1/n, i2/n)},
-Xi = {(j1 - n/2, j2 - n/2)}, 0 <= i, j < n, K = exp(2 pi i Phi(x, xi)) (a = 1).
+Xi = {(j1 - n/2, j2 - n/2)}, 0 <= i, j < n, K = a(x, xi) exp(2 pi i Phi(x, xi)), with
+a = 1 unless a callable ``amp(x1, x2, xi1, xi2)`` is given; ``hankel_amplitude``
+builds Section 5.3's variable amplitude.
 
 User ordering (a reading; the paper defines only the sets): entry i1*n + i2 of a
 spatial vector is x = (i1/n, i2/n); entry j1*n + j2 of a frequency vector is
 xi = (j1 - n/2, j2 - n/2) ("lexicographic, first coordinate major").
 
-Phase family of Section 5.3 (constant amplitude):
+Phase family of Section 5.2 (constant amplitude):
     Phi(x, xi) = x . xi + sqrt(c1(x)^2 xi1^2 + c2(x)^2 xi2^2),
     c1(x) = a0 + a1 sin(2 pi x1) sin(2 pi x2),  c2(x) = a0 + a1 cos(2 pi x1) cos(2 pi x2),
 with (a0, a1) = (2/16, 1/16) for the paper's workload and (0, 0) for the plain
-2D DFT.
+2D DFT.  Parameters (a0, a1, "iso") select Section 5.3's isotropic phase
+    Phi(x, xi) = x . xi + c(x) ||xi||,  c(x) = a0 + a1 sin(2 pi x1) sin(2 pi x2),
+with (a0, a1) = (3/8, 1/8) there; it is the family above with c2 = c1.
 
 Internal ordering (library-private, used by the HSS tree): Morton order, the
 bits of the first coordinate above those of the second at every level, so the
@@ -20,9 +24,11 @@ points of every dyadic box are contiguous and the box index at level l is the
 Morton code of the box coordinates.
 """
 import numpy as np
+from scipy.special import hankel1
 
 PHASE2_DFT = (0.0, 0.0)
 PHASE2_ANISO16 = (2.0 / 16.0, 1.0 / 16.0)
+PHASE2_ISO38 = (3.0 / 8.0, 1.0 / 8.0, "iso")
 
 
 def spatial_grid(n):
@@ -37,35 +43,61 @@ def frequency_grid(n):
 
 
 def coeffs(x1, x2, params):
-    a0, a1 = params
+    a0, a1 = params[0], params[1]
     s1, s2 = np.sin(2 * np.pi * x1), np.sin(2 * np.pi * x2)
+    c1 = a0 + a1 * s1 * s2
+    if len(params) > 2 and params[2] == "iso":
+        return c1, c1
     c1_, c2_ = np.cos(2 * np.pi * x1), np.cos(2 * np.pi * x2)
-    return a0 + a1 * s1 * s2, a0 + a1 * c1_ * c2_
+    return c1, a0 + a1 * c1_ * c2_
+
+
+def rho(x1, x2, k1, k2, params):
+    """The nonlinear part of the phase, Phi(x, xi) - x . xi."""
+    x1, x2 = np.asarray(x1, np.float64), np.asarray(x2, np.float64)
+    k1, k2 = np.asarray(k1, np.float64), np.asarray(k2, np.float64)
+    c1, c2 = coeffs(x1, x2, params)
+    return np.sqrt(c1 * c1 * k1 * k1 + c2 * c2 * k2 * k2)
 
 
 def phase(x1, x2, k1, k2, params):
     """Phi(x, xi), broadcasting over all four arguments."""
     x1, x2 = np.asarray(x1, np.float64), np.asarray(x2, np.float64)
     k1, k2 = np.asarray(k1, np.float64), np.asarray(k2, np.float64)
-    c1, c2 = coeffs(x1, x2, params)
-    return x1 * k1 + x2 * k2 + np.sqrt(c1 * c1 * k1 * k1 + c2 * c2 * k2 * k2)
+    return x1 * k1 + x2 * k2 + rho(x1, x2, k1, k2, params)
 
 
-def kernel(x1, x2, k1, k2, params):
-    return np.exp(2j * np.pi * phase(x1, x2, k1, k2, params))
+def hankel_amplitude(params):
+    """Section 5.3's amplitude a(x, xi) = H0^(1)(2 pi rho(x, xi)) exp(-2 pi i rho(x, xi)), with
+    rho the nonlinear part of the phase (H0^(1) the Hankel function of the first kind, order 0).
+    It is infinite at xi = 0, a point of the frequency grid (the butterfly evaluates it only at
+    Chebyshev points, never there)."""
+    def amp(x1, x2, k1, k2):
+        r = rho(x1, x2, k1, k2, params)
+        with np.errstate(invalid="ignore", over="ignore"):
+            return hankel1(0, 2 * np.pi * r) * np.exp(-2j * np.pi * r)
+    return amp
 
 
-def dense_K(n, params):
+def kernel(x1, x2, k1, k2, params, amp=None):
+    """k(x, xi) = a(x, xi) exp(2 pi i Phi(x, xi)) (a = 1 when amp is None)."""
+    k = np.exp(2j * np.pi * phase(x1, x2, k1, k2, params))
+    if amp is not None:
+        k = k * amp(*np.broadcast_arrays(*(np.asarray(v, np.float64) for v in (x1, x2, k1, k2))))
+    return k
+
+
+def dense_K(n, params, amp=None):
     x1, x2 = spatial_grid(n)
     k1, k2 = frequency_grid(n)
-    return kernel(x1[:, None], x2[:, None], k1[None, :], k2[None, :], params)
+    return kernel(x1[:, None], x2[:, None], k1[None, :], k2[None, :], params, amp)
 
 
-def dense_K_rows(n, rows, params):
+def dense_K_rows(n, rows, params, amp=None):
     x1, x2 = spatial_grid(n)
     rows = np.asarray(rows)
     k1, k2 = frequency_grid(n)
-    return kernel(x1[rows][:, None], x2[rows][:, None], k1[None, :], k2[None, :], params)
+    return kernel(x1[rows][:, None], x2[rows][:, None], k1[None, :], k2[None, :], params, amp)
 
 
 def dft2_apply(f, n):
