@@ -244,7 +244,7 @@ def chosen(report):
 
 
 def workload_2d(F, torch, fi, steps, warmup, rel_res=5e-9, solve=True):
-    """2D workload (Section 5.3 phase, a = 1): n = 128 per dimension (N = 16384, odd L), q = 9
+    """2D workload (Section 5.2 phase, a = 1): n = 128 per dimension (N = 16384, odd L), q = 9
     (r = 81), 8 right-hand sides.  Times the BF applies (FP64 and FP32, forward and adjoint) with
     per-kernel events, and, after the offline HSS (tolerance 1e-3, p = 10) and ULV construction,
     the direct FP64 solve and the refinement to a relative residual of 5e-9 (FP64 and mixed)."""
@@ -300,7 +300,7 @@ def workload_2d(F, torch, fi, steps, warmup, rel_res=5e-9, solve=True):
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(byts / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "avg_launch_ms": round(avg, 4), "algorithmic_bytes_per_launch": int(byts),
             "algorithmic_flops_per_launch": flops}
-    res = {"workload": "2D FIO n=128 (N=16384), Phi = x.xi + sqrt(c1^2 xi1^2 + c2^2 xi2^2) of Section 5.3, "
+    res = {"workload": "2D FIO n=128 (N=16384), Phi = x.xi + sqrt(c1^2 xi1^2 + c2^2 xi2^2) of Section 5.2, "
                        "q=9, 8 RHS (seed 1)",
            "bf_build_s": round(t_bf, 3), "autotuned_tiles": tuned, "apply": applies, "roofline_middle": roof,
            "kernels_ms": {kk: {kn: [c, round(m, 3)] for kn, (c, m) in v.items()} for kk, v in kstats.items()}}

@@ -59,8 +59,8 @@ typedef struct hss_ulv_s *hss_ulv_t;
  * Butterfly factorization (Section 2.2, eq. bf):
  *   K~ = U^[L'] B^[L'] ... B^[h+1] M^[h] C^[h+1] ... C^[L'] V^[L'],
  * with q first-kind Chebyshev points per box and dimension on the closed box,
- * L' = max(L - level_offset, h) (the outer level of the implementation notes of
- * Sections 5.2 and 5.3), amplitude 1, and
+ * L' = max(L - level_offset, h) (the outer level of Section 5.2's implementation
+ * note), and
  *
  * dim = 1: N = n = 2^L points (L even), h = L/2, phase
  *     Phi(x, xi) = x xi + (c0 + c1 sin(2 pi x)) |xi|;
@@ -69,7 +69,7 @@ typedef struct hss_ulv_s *hss_ulv_t;
  * dim = 2: n = 2^L points per dimension, N = n^2, quadtrees in space and
  *   frequency, h = ceil(L/2) (odd L: the U and V sides both stop at level h and
  *   M couples each U pair with the 4 V pairs of its parent spatial box and the
- *   frequency children of its box), phase of Section 5.3
+ *   frequency children of its box), phase of Section 5.2
  *     Phi(x, xi) = x.xi + sqrt(c1(x)^2 xi1^2 + c2(x)^2 xi2^2),
  *     c1(x) = c0 + c1 sin(2 pi x1) sin(2 pi x2),  c2(x) = c0 + c1 cos(2 pi x1) cos(2 pi x2);
  *   (c0, c1) = (1/8, 1/16) is the paper's 2D workload, (0, 0) the 2D DFT.

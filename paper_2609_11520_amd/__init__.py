@@ -67,7 +67,7 @@ class BF:
     """Butterfly factorization K~ (Section 2.2) of
     dim 1: Phi = x xi + (c0 + c1 sin 2 pi x)|xi|, n points;
     dim 2: Phi = x.xi + sqrt(c1(x)^2 xi1^2 + c2(x)^2 xi2^2) with c1 = c0 + c1 sin sin,
-           c2 = c0 + c1 cos cos (Section 5.3), n points per dimension, N = n^2."""
+           c2 = c0 + c1 cos cos (Section 5.2), n points per dimension, N = n^2."""
 
     def __init__(self, n, q=9, c0=2.0 / 16, c1=1.0 / 16, level_offset=3, precs=(FIO_PREC_FP64,), factors=None,
                  dim=1, amp=None):

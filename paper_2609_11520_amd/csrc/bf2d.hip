@@ -1,5 +1,5 @@
 // Butterfly factorization of a 2D discrete FIO on gfx950 (Section 2.2 on a
-// quadtree, the phase of Section 5.3), for the levels where the outermost factors
+// quadtree, the phases of Sections 5.2 and 5.3), for the levels where the outermost factors
 // meet at the middle level (L' = h, no B or C factor): K~ = U M V.
 //
 // Trees: n = 2^L points per dimension, N = n^2, h = ceil(L/2), lc = L - h.
@@ -69,7 +69,7 @@ G2 g2_of(const fio_bf_s *bf) {
     return g;
 }
 
-// --- geometry and phase (Section 5.3) ---------------------------------------------
+// --- geometry and phase (Sections 5.2 and 5.3) ---------------------------------------------
 __device__ __forceinline__ void demorton(long m, int bits, int &j1, int &j2) {
     j1 = 0;
     j2 = 0;

@@ -1,6 +1,6 @@
 """GPU parity of the 2D path: index maps, butterfly apply (forward and adjoint, imported
 and GPU-built factors, FP64 and FP32), HSS of K~^* K~ over Morton-ordered frequencies, and
-the approximate solve, against the oracle (Section 2.2 on quadtrees, Section 5.3)."""
+the approximate solve, against the oracle (Section 2.2 on quadtrees, Section 5.2)."""
 import functools
 
 import numpy as np

@@ -1,4 +1,4 @@
-"""Pins of the 2D oracle: grids, kernel, index maps, butterfly (Section 2.2, Section 5.3)."""
+"""Pins of the 2D oracle: grids, kernel, index maps, butterfly (Section 2.2, Section 5.2)."""
 import json
 import os
 
@@ -43,7 +43,7 @@ def test_dense_kernel_dft_closed_form():
 
 
 def test_phase_values():
-    # Phi at a few points from the definition in Section 5.3, evaluated by hand
+    # Phi at a few points from the definition in Section 5.2, evaluated by hand
     P = f2.PHASE2_ANISO16
     assert f2.phase(0.0, 0.0, 3.0, -4.0, P) == pytest.approx(np.sqrt((2 / 16) ** 2 * 9 + (3 / 16) ** 2 * 16))
     x1, x2 = 0.25, 0.25          # sin sin = 1, cos cos = 0
@@ -143,7 +143,7 @@ def test_paper_ecbf_2d_64():
 
 def test_morton_frequency_wrapper_and_2d_solve():
     """The 2D solve composition: K~ with Morton-ordered frequencies, HSS of K~^*K~ in that order,
-    f^ mapped back to user order; refinement and PCG converge to f (Sec. 4.1, Sec. 5.3)."""
+    f^ mapped back to user order; refinement and PCG converge to f (Sec. 4.1, Sec. 5.2)."""
     import fio_inputs as fi
     from oracle import solve as osolve, ulv as oulv
     n = 16
@@ -163,6 +163,6 @@ def test_morton_frequency_wrapper_and_2d_solve():
     assert hist[-1] < 1e-12
     assert osolve.col_rel_err(f2.to_user(fr, n), f) < 1e-10
     fp, it = osolve.pcg(mf, fac, u[:, 0], tol=1e-12)
-    # the paper's preconditioned iteration counts in 2D are 5-6 (Sec. 5.3, iterative table)
+    # the paper's preconditioned iteration counts in 2D are 5-6 (Sec. 5.2, iterative table)
     assert it <= 8
     assert osolve.rel_err(f2.to_user(fp, n), f[:, 0]) < 1e-10
