@@ -243,16 +243,22 @@ def chosen(report):
     return [x.strip()[len("chosen "):] for x in report.split(";") if x.strip().startswith("chosen")]
 
 
-def workload_2d(F, torch, fi, steps, warmup, rel_res=5e-9, solve=True):
-    """2D workload (Section 5.2 phase, a = 1): n = 128 per dimension (N = 16384, odd L), q = 9
-    (r = 81), 8 right-hand sides.  Times the BF applies (FP64 and FP32, forward and adjoint) with
-    per-kernel events, and, after the offline HSS (tolerance 1e-3, p = 10) and ULV construction,
-    the direct FP64 solve and the refinement to a relative residual of 5e-9 (FP64 and mixed)."""
+def workload_2d(F, torch, fi, steps, warmup, rel_res=5e-9, solve=True, var_amp=False):
+    """2D workload (Section 5.2 phase, a = 1; with var_amp, Section 5.3's isotropic phase
+    c(x)||xi||, c = (3 + sin 2 pi x1 sin 2 pi x2)/8, and amplitude H0^(1)(2 pi rho) exp(-2 pi i rho)):
+    n = 128 per dimension (N = 16384, odd L), q = 9 (r = 81), 8 right-hand sides.  Times the BF
+    applies (FP64 and FP32, forward and adjoint) with per-kernel events, and, after the offline
+    HSS (tolerance 1e-3, p = 10) and ULV construction, the direct FP64 solve, the refinement to a
+    relative residual of 5e-9 (FP64 and mixed) and the preconditioned CG to 1e-12."""
     n, k, q = 128, 8, 9
     N = n * n
     dev = torch.device("cuda")
     t = time.perf_counter()
-    B = F.BF(n, q, 2.0 / 16, 1.0 / 16, precs=(F.FIO_PREC_FP64, F.FIO_PREC_FP32), dim=2)
+    if var_amp:
+        B = F.BF(n, q, 3.0 / 8, 1.0 / 8, precs=(F.FIO_PREC_FP64, F.FIO_PREC_FP32), dim=2,
+                 phase_kind=F.FIO_PHASE2_ISO, amp="hankel")
+    else:
+        B = F.BF(n, q, 2.0 / 16, 1.0 / 16, precs=(F.FIO_PREC_FP64, F.FIO_PREC_FP32), dim=2)
     torch.cuda.synchronize()
     t_bf = time.perf_counter() - t
     f_host = fi.rhs(1, N, k)
@@ -300,8 +306,10 @@ def workload_2d(F, torch, fi, steps, warmup, rel_res=5e-9, solve=True):
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(byts / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "avg_launch_ms": round(avg, 4), "algorithmic_bytes_per_launch": int(byts),
             "algorithmic_flops_per_launch": flops}
-    res = {"workload": "2D FIO n=128 (N=16384), Phi = x.xi + sqrt(c1^2 xi1^2 + c2^2 xi2^2) of Section 5.2, "
-                       "q=9, 8 RHS (seed 1)",
+    wl = ("2D FIO n=128 (N=16384), Phi = x.xi + c(x)||xi||, c = (3 + sin sin)/8, amplitude "
+          "H0(1)(2 pi rho) exp(-2 pi i rho) of Section 5.3" if var_amp else
+          "2D FIO n=128 (N=16384), Phi = x.xi + sqrt(c1^2 xi1^2 + c2^2 xi2^2) of Section 5.2")
+    res = {"workload": wl + ", q=9, 8 RHS (seed 1)",
            "bf_build_s": round(t_bf, 3), "autotuned_tiles": tuned, "apply": applies, "roofline_middle": roof,
            "kernels_ms": {kk: {kn: [c, round(m, 3)] for kn, (c, m) in v.items()} for kk, v in kstats.items()}}
     if solve:
@@ -630,6 +638,12 @@ def main():
         log("2D workload")
         w2d = workload_2d(F, torch, fi, a.steps, a.warmup, solve=not a.no_2d_solve)
         log("2d", json.dumps(w2d))
+    w2a = None
+    if not a.no_2d and not a.no_amp:
+        torch.cuda.empty_cache()
+        log("2D variable-amplitude workload")
+        w2a = workload_2d(F, torch, fi, a.steps, a.warmup, solve=not a.no_2d_solve, var_amp=True)
+        log("2d_var_amp", json.dumps(w2a))
 
     wamp = None
     if not a.no_amp:
@@ -665,7 +679,8 @@ def main():
         "latency_ms": mixed["latency_ms"],
         "offline_s": {"bf": round(t_bf, 3), "hss": round(t_hss, 3), "ulv": round(t_ulv, 3)},
         "kernels_ms": {p: {kn: [c, round(m, 3)] for kn, (c, m) in d.items()} for p, d in kernel_stats.items()},
-        "serving": serve, "workload_2d": w2d, "workload_var_amp": wamp, "roofline": roof, "cpu_baseline": cpu,
+        "serving": serve, "workload_2d": w2d, "workload_var_amp": wamp, "workload_2d_var_amp": w2a,
+        "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 

@@ -51,6 +51,9 @@ typedef enum {
                                     MFMA with fp32 accumulation (see fio_bf_apply) */
 } fio_prec;
 
+typedef enum { FIO_AMP_ONE = 0, FIO_AMP_GAUSSIAN_SUM = 1, FIO_AMP_HANKEL = 2 } fio_amp_kind;
+typedef enum { FIO_PHASE2_ANISO = 0, FIO_PHASE2_ISO = 1 } fio_phase2_kind;
+
 typedef struct fio_bf_s *fio_bf_t;
 typedef struct hss_s *hss_t;
 typedef struct hss_ulv_s *hss_ulv_t;
@@ -60,7 +63,7 @@ typedef struct hss_ulv_s *hss_ulv_t;
  *   K~ = U^[L'] B^[L'] ... B^[h+1] M^[h] C^[h+1] ... C^[L'] V^[L'],
  * with q first-kind Chebyshev points per box and dimension on the closed box,
  * L' = max(L - level_offset, h) (the outer level of Section 5.2's implementation
- * note), and
+ * note), amplitude a (see amp_kind below; 1 by default), and
  *
  * dim = 1: N = n = 2^L points (L even), h = L/2, phase
  *     Phi(x, xi) = x xi + (c0 + c1 sin(2 pi x)) |xi|;
@@ -87,14 +90,27 @@ typedef struct {
     unsigned prec_mask;      /* bit p set: keep a copy of the factors in fio_prec p resident;
                                 FIO_PREC_SPLIT_FP16 (dim 1, q = 9 only, else FIO_ERR_UNSUPPORTED
                                 at build/import) also keeps the FP32 copy */
-    /* Amplitude (dim 1 only; dim 2 with amp_terms > 0 returns FIO_ERR_UNSUPPORTED):
-     * amp_terms = 0 gives a = 1; 1 <= amp_terms <= 16 gives Section 5.1's variable amplitude
+    /* 2D phase (fio_phase2_kind; must be 0 for dim 1, else FIO_ERR_UNSUPPORTED):
+     * FIO_PHASE2_ANISO is Section 5.2's family above; FIO_PHASE2_ISO is Section 5.3's
+     *   Phi(x, xi) = x.xi + c(x) ||xi||,  c(x) = c0 + c1 sin(2 pi x1) sin(2 pi x2)
+     * (the family with c2 = c1), (c0, c1) = (3/8, 1/8) there.  FIO_ERR_ARG for other values. */
+    int phase_kind;
+    /* Amplitude (fio_amp_kind).  The interpolation factors U, B, C, V do not depend on it; it
+     * enters the middle factor only, M = k(Z, Gamma) with k = a exp(2 pi i Phi)
+     * (eq. bf_kernel_func_low_rank), so every apply path and precision serves it unchanged.
+     * FIO_AMP_ONE: a = 1; the other amplitude fields are ignored.
+     * FIO_AMP_GAUSSIAN_SUM (dim 1 only): Section 5.1's
      *   a(x, xi) = sum_k exp(-((x - x_k)^2 + ((xi - xi_k) / N)^2) / amp_sigma2),
-     * with the centers in HOST memory at amp_centers (x_1 .. x_m, then xi_1 .. xi_m), copied
-     * when the descriptor is planned (build, import, factor count).  The interpolation factors
-     * U, B, C, V do not depend on a; it enters the middle factor, M = k(Z, Gamma) with
-     * k = a exp(2 pi i Phi) (eq. bf_kernel_func_low_rank).  FIO_ERR_ARG for amp_terms outside
-     * 0..16, amp_sigma2 <= 0 or a NULL amp_centers with amp_terms > 0. */
+     *   k = 1 .. amp_terms (at most 16), with the centers in HOST memory at amp_centers
+     *   (x_1 .. x_m, then xi_1 .. xi_m), copied when the descriptor is planned (build, import,
+     *   factor count).  FIO_ERR_ARG for amp_terms outside 1..16, amp_sigma2 <= 0 or a NULL
+     *   amp_centers.
+     * FIO_AMP_HANKEL (dim 2 only): Section 5.3's a(x, xi) = H0^(1)(2 pi rho) exp(-2 pi i rho),
+     *   rho = Phi(x, xi) - x.xi, H0^(1) the Hankel function of the first kind of order 0.  It
+     *   is infinite at xi = 0; the butterfly evaluates it at Chebyshev points only, which never
+     *   fall on xi = 0, so K~ is finite there.
+     * A kind not valid for the dimension returns FIO_ERR_UNSUPPORTED, other values FIO_ERR_ARG. */
+    int amp_kind;
     int amp_terms;
     double amp_sigma2;
     const double *amp_centers;

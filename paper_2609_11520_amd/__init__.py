@@ -13,10 +13,12 @@ import numpy as np
 
 from . import _lib
 from ._lib import (FIO_PREC_FP64, FIO_PREC_FP32, FIO_PREC_SPLIT_FP16, FIO_SOLVE_DIRECT, FIO_SOLVE_IR,
-                   FIO_SOLVE_PCG, FioError)
+                   FIO_SOLVE_PCG, FIO_AMP_ONE, FIO_AMP_GAUSSIAN_SUM, FIO_AMP_HANKEL, FIO_PHASE2_ANISO,
+                   FIO_PHASE2_ISO, FioError)
 
 __all__ = ["BF", "HSS", "ULV", "approx_solve", "colmajor", "empty", "FIO_PREC_FP64", "FIO_PREC_FP32",
-           "FIO_PREC_SPLIT_FP16", "FIO_SOLVE_DIRECT", "FIO_SOLVE_IR", "FIO_SOLVE_PCG", "FioError", "lib"]
+           "FIO_PREC_SPLIT_FP16", "FIO_SOLVE_DIRECT", "FIO_SOLVE_IR", "FIO_SOLVE_PCG", "FIO_AMP_ONE",
+           "FIO_AMP_GAUSSIAN_SUM", "FIO_AMP_HANKEL", "FIO_PHASE2_ANISO", "FIO_PHASE2_ISO", "FioError", "lib"]
 
 
 def lib():
@@ -67,23 +69,29 @@ class BF:
     """Butterfly factorization K~ (Section 2.2) of
     dim 1: Phi = x xi + (c0 + c1 sin 2 pi x)|xi|, n points;
     dim 2: Phi = x.xi + sqrt(c1(x)^2 xi1^2 + c2(x)^2 xi2^2) with c1 = c0 + c1 sin sin,
-           c2 = c0 + c1 cos cos (Section 5.2), n points per dimension, N = n^2."""
+           c2 = c0 + c1 cos cos (Section 5.2), n points per dimension, N = n^2; with
+           phase_kind=FIO_PHASE2_ISO, c2 = c1 (Section 5.3's Phi = x.xi + c(x)||xi||)."""
 
     def __init__(self, n, q=9, c0=2.0 / 16, c1=1.0 / 16, level_offset=3, precs=(FIO_PREC_FP64,), factors=None,
-                 dim=1, amp=None):
-        """amp: None (a = 1) or (centers_x, centers_xi, sigma2) for Section 5.1's Gaussian-sum amplitude."""
+                 dim=1, amp=None, phase_kind=FIO_PHASE2_ANISO):
+        """amp: None (a = 1), (centers_x, centers_xi, sigma2) for Section 5.1's Gaussian-sum
+        amplitude (dim 1), or "hankel" for Section 5.3's H0^(1)(2 pi rho) exp(-2 pi i rho) (dim 2)."""
         L = lib()
         mask = 0
         for p in precs:
             mask |= 1 << p
+        self._amp = None
         if amp is None:
-            self._amp = None
-            self.desc = _lib.BfDesc(dim, n, c0, c1, q, level_offset, mask, 0, 0.0, None)
+            self.desc = _lib.BfDesc(dim, n, c0, c1, q, level_offset, mask, phase_kind, FIO_AMP_ONE, 0, 0.0, None)
+        elif isinstance(amp, str):
+            if amp != "hankel":
+                raise ValueError("amp: None, 'hankel' or (centers_x, centers_xi, sigma2)")
+            self.desc = _lib.BfDesc(dim, n, c0, c1, q, level_offset, mask, phase_kind, FIO_AMP_HANKEL, 0, 0.0, None)
         else:
             cx, cxi, s2 = amp
             self._amp = np.ascontiguousarray(np.concatenate([np.asarray(cx, float), np.asarray(cxi, float)]))
-            self.desc = _lib.BfDesc(dim, n, c0, c1, q, level_offset, mask, len(cx), float(s2),
-                                    self._amp.ctypes.data_as(C.c_void_p))
+            self.desc = _lib.BfDesc(dim, n, c0, c1, q, level_offset, mask, phase_kind, FIO_AMP_GAUSSIAN_SUM,
+                                    len(cx), float(s2), self._amp.ctypes.data_as(C.c_void_p))
         self.dim, self.q = dim, q
         self.n = n if dim == 1 else n * n          # vector length
         h = C.c_void_p()

@@ -9,6 +9,8 @@ FIO_OK = 0
 FIO_WARN_RANK_CAP = 1
 FIO_PREC_FP64, FIO_PREC_FP32, FIO_PREC_SPLIT_FP16 = 0, 1, 2
 FIO_SOLVE_DIRECT, FIO_SOLVE_IR, FIO_SOLVE_PCG = 0, 1, 2
+FIO_AMP_ONE, FIO_AMP_GAUSSIAN_SUM, FIO_AMP_HANKEL = 0, 1, 2
+FIO_PHASE2_ANISO, FIO_PHASE2_ISO = 0, 1
 
 STATUS = {0: "FIO_OK", -1: "FIO_ERR_ARG", -2: "FIO_ERR_OOM", -3: "FIO_ERR_HIP", -4: "FIO_ERR_NOT_HPD",
           -5: "FIO_ERR_NOT_CONVERGED", -6: "FIO_ERR_UNSUPPORTED", -7: "FIO_ERR_CALLBACK", 1: "FIO_WARN_RANK_CAP"}
@@ -22,7 +24,8 @@ class FioError(RuntimeError):
 
 class BfDesc(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_long), ("c0", C.c_double), ("c1", C.c_double), ("q", C.c_int),
-                ("level_offset", C.c_int), ("prec_mask", C.c_uint), ("amp_terms", C.c_int),
+                ("level_offset", C.c_int), ("prec_mask", C.c_uint), ("phase_kind", C.c_int),
+                ("amp_kind", C.c_int), ("amp_terms", C.c_int),
                 ("amp_sigma2", C.c_double), ("amp_centers", C.c_void_p)]
 
 

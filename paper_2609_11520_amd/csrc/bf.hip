@@ -26,15 +26,20 @@ fio_status bf_plan(const fio_bf_desc *d, fio_bf_s *bf) {
     while ((1L << L) < d->n) ++L;
     if (L % 2) return FIO_ERR_UNSUPPORTED;
     if (d->q < 2 || d->q > 16 || d->level_offset < 1) return FIO_ERR_ARG;
-    if (d->amp_terms < 0 || d->amp_terms > kMaxAmpTerms) return FIO_ERR_ARG;
-    if (d->amp_terms > 0 && (!(d->amp_sigma2 > 0.0) || !d->amp_centers)) return FIO_ERR_ARG;
+    if (d->phase_kind != FIO_PHASE2_ANISO) return FIO_ERR_UNSUPPORTED;   // 2D phases only
+    if (d->amp_kind < FIO_AMP_ONE || d->amp_kind > FIO_AMP_HANKEL) return FIO_ERR_ARG;
+    if (d->amp_kind == FIO_AMP_HANKEL) return FIO_ERR_UNSUPPORTED;       // 2D amplitude only
+    const int terms = d->amp_kind == FIO_AMP_GAUSSIAN_SUM ? d->amp_terms : 0;
+    if (d->amp_kind == FIO_AMP_GAUSSIAN_SUM &&
+        (terms < 1 || terms > kMaxAmpTerms || !(d->amp_sigma2 > 0.0) || !d->amp_centers))
+        return FIO_ERR_ARG;
     bf->desc = *d;
     bf->desc.amp_centers = nullptr;          // the handle keeps its own copy
-    bf->amp.m = d->amp_terms;
-    bf->amp.s2 = d->amp_terms > 0 ? d->amp_sigma2 : 1.0;
-    for (int k = 0; k < d->amp_terms; ++k) {
+    bf->amp.m = terms;
+    bf->amp.s2 = terms > 0 ? d->amp_sigma2 : 1.0;
+    for (int k = 0; k < terms; ++k) {
         bf->amp.x[k] = d->amp_centers[k];
-        bf->amp.xi[k] = d->amp_centers[d->amp_terms + k];
+        bf->amp.xi[k] = d->amp_centers[terms + k];
     }
     bf->N = d->n;
     bf->n1 = d->n;

@@ -48,6 +48,8 @@ struct G2 {
     int n, L, h, lc, b, hb, q, q2, b2;
     long S, T, rr;                // 4^h, 4^lc, 4^(h-lc)
     double a0, a1;                // phase parameters
+    int iso;                      // Section 5.3's isotropic phase (c2 = c1)
+    int hankel;                   // Section 5.3's amplitude
 };
 
 G2 g2_of(const fio_bf_s *bf) {
@@ -66,6 +68,8 @@ G2 g2_of(const fio_bf_s *bf) {
     g.rr = g.S / g.T;
     g.a0 = bf->desc.c0;
     g.a1 = bf->desc.c1;
+    g.iso = bf->desc.phase_kind == FIO_PHASE2_ISO;
+    g.hankel = bf->desc.amp_kind == FIO_AMP_HANKEL;
     return g;
 }
 
@@ -102,7 +106,7 @@ __device__ double lagr1(double u, int t, int q) {
 
 __device__ __forceinline__ double rho2(const G2 &g, double x1, double x2, double k1, double k2) {
     const double c1 = g.a0 + g.a1 * sinpi(2.0 * x1) * sinpi(2.0 * x2);
-    const double c2 = g.a0 + g.a1 * cospi(2.0 * x1) * cospi(2.0 * x2);
+    const double c2 = g.iso ? c1 : g.a0 + g.a1 * cospi(2.0 * x1) * cospi(2.0 * x2);
     return sqrt(c1 * c1 * k1 * k1 + c2 * c2 * k2 * k2);
 }
 
@@ -172,7 +176,18 @@ __global__ void gen2_M(G2 g, double2 *out) {
     const double hs = 0.5 * ws, hf = 0.5 * wf;
     const double x1 = z1 + hs + hs * cheb_node(i / g.q, g.q), x2 = z2 + hs + hs * cheb_node(i % g.q, g.q);
     const double k1 = f1 + hf + hf * cheb_node(j / g.q, g.q), k2 = f2 + hf + hf * cheb_node(j % g.q, g.q);
-    out[id] = e2pi(x1 * k1 + x2 * k2 + rho2(g, x1, x2, k1, k2));
+    const double r = rho2(g, x1, x2, k1, k2);
+    if (!g.hankel) {
+        out[id] = e2pi(x1 * k1 + x2 * k2 + r);
+        return;
+    }
+    // a exp(2 pi i Phi) with a = H0^(1)(2 pi rho) exp(-2 pi i rho): the rho terms of the two
+    // exponentials cancel, leaving H0^(1)(2 pi rho) exp(2 pi i x.xi), H0^(1) = J0 + i Y0.
+    // Chebyshev points never fall on xi = 0, so rho > 0 here.
+    const double z = 2.0 * M_PI * r;
+    const double hr = j0(z), hi = y0(z);
+    const double2 e = e2pi(x1 * k1 + x2 * k2);
+    out[id] = zc(hr * e.x - hi * e.y, hr * e.y + hi * e.x);
 }
 
 // U(s, i) of pair p = tau * T + sigma'
@@ -555,7 +570,9 @@ void apply2(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long
 // ---------------------------------------------------------------------------
 fio_status bf2d_plan(const fio_bf_desc *d, fio_bf_s *bf) {
     if (d->n < 4 || d->n > (1L << 15) || (d->n & (d->n - 1))) return FIO_ERR_ARG;
-    if (d->amp_terms != 0) return FIO_ERR_UNSUPPORTED;         // variable amplitude: 1D only
+    if (d->phase_kind < FIO_PHASE2_ANISO || d->phase_kind > FIO_PHASE2_ISO) return FIO_ERR_ARG;
+    if (d->amp_kind < FIO_AMP_ONE || d->amp_kind > FIO_AMP_HANKEL) return FIO_ERR_ARG;
+    if (d->amp_kind == FIO_AMP_GAUSSIAN_SUM) return FIO_ERR_UNSUPPORTED;   // 1D amplitude only
     if (d->q < 2 || d->q > 16 || d->level_offset < 1) return FIO_ERR_ARG;
     int L = 0;
     while ((1L << L) < d->n) ++L;
@@ -566,6 +583,7 @@ fio_status bf2d_plan(const fio_bf_desc *d, fio_bf_s *bf) {
     if (h > 7) return FIO_ERR_UNSUPPORTED;                      // 4^h leaf boxes on one grid axis
     if (d->q * d->q > 128) return FIO_ERR_UNSUPPORTED;
     bf->desc = *d;
+    bf->desc.amp_centers = nullptr;          // not used in 2D
     bf->dim = 2;
     bf->n1 = d->n;
     bf->N = d->n * d->n;
