@@ -32,41 +32,99 @@ __global__ void k_axpy(double2 *__restrict__ F, long ldf, const double2 *__restr
 }
 
 // out[j] = sum_i |X(i, j)|^2, one workgroup per column (fixed reduction order)
-__global__ void k_colnorm2(const double2 *__restrict__ X, long ldx, long n, double *out) {
-    __shared__ double sh[4];
-    const int j = blockIdx.x;
-    double p = 0.0;
-    for (long i = threadIdx.x; i < n; i += blockDim.x) {
-        double2 v = X[i + (size_t)j * ldx];
-        p += v.x * v.x + v.y * v.y;
-    }
-    for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = p;
-    __syncthreads();
-    if (threadIdx.x == 0) out[j] = sh[0] + sh[1] + sh[2] + sh[3];
+// Column reductions in two stages with a fixed order: each column is cut into kRedChunks
+// row ranges (the cut depends on n only, so a column's result does not depend on the
+// other columns of the batch), one workgroup reduces a range into a partial, and one wave
+// per column sums the partials.
+constexpr int kRedChunks = 32;
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
 }
 
-// out[j] = sum_i conj(A(i, j)) B(i, j), one workgroup of 256 per column (fixed reduction order)
-__global__ void k_coldot(const double2 *__restrict__ A, long lda, const double2 *__restrict__ B, long ldb, long n,
-                         double2 *out) {
+// part[j kRedChunks + c] = sum over rows of chunk c of |X(i, j)|^2
+__global__ void __launch_bounds__(256) k_colnorm2_part(const double2 *__restrict__ X, long ldx, long n,
+                                                      double *__restrict__ part) {
+    __shared__ double sh[4];
+    const int c = blockIdx.x % kRedChunks, j = blockIdx.x / kRedChunks, t = threadIdx.x;
+    const long len = (n + kRedChunks - 1) / kRedChunks;
+    const long i0 = c * len, i1 = i0 + len < n ? i0 + len : n;
+    const double2 *x = X + (size_t)j * ldx;
+    double p[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long i = i0 + t; i < i1; i += 1024) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const long r = i + 256 * u;
+            if (r < i1) {
+                const double2 v = x[r];
+                p[u] += v.x * v.x + v.y * v.y;
+            }
+        }
+    }
+    const double w = wave_sum((p[0] + p[1]) + (p[2] + p[3]));
+    if ((t & 63) == 0) sh[t >> 6] = w;
+    __syncthreads();
+    if (t == 0) part[(size_t)j * kRedChunks + c] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// part[j kRedChunks + c] = sum over rows of chunk c of conj(A(i, j)) B(i, j)
+__global__ void __launch_bounds__(256) k_coldot_part(const double2 *__restrict__ A, long lda,
+                                                    const double2 *__restrict__ B, long ldb, long n,
+                                                    double2 *__restrict__ part) {
     __shared__ double shr[4], shi[4];
-    const int j = blockIdx.x;
-    double pr = 0.0, pi = 0.0;
-    for (long i = threadIdx.x; i < n; i += blockDim.x) {
-        const double2 a = A[i + (size_t)j * lda], b = B[i + (size_t)j * ldb];
-        pr += a.x * b.x + a.y * b.y;
-        pi += a.x * b.y - a.y * b.x;
+    const int c = blockIdx.x % kRedChunks, j = blockIdx.x / kRedChunks, t = threadIdx.x;
+    const long len = (n + kRedChunks - 1) / kRedChunks;
+    const long i0 = c * len, i1 = i0 + len < n ? i0 + len : n;
+    const double2 *a = A + (size_t)j * lda, *b = B + (size_t)j * ldb;
+    double pr[4] = {0.0, 0.0, 0.0, 0.0}, pi[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long i = i0 + t; i < i1; i += 1024) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const long r = i + 256 * u;
+            if (r < i1) {
+                const double2 av = a[r], bv = b[r];
+                pr[u] += av.x * bv.x + av.y * bv.y;
+                pi[u] += av.x * bv.y - av.y * bv.x;
+            }
+        }
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        pr += __shfl_xor(pr, o);
-        pi += __shfl_xor(pi, o);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        shr[threadIdx.x >> 6] = pr;
-        shi[threadIdx.x >> 6] = pi;
+    const double wr = wave_sum((pr[0] + pr[1]) + (pr[2] + pr[3]));
+    const double wi = wave_sum((pi[0] + pi[1]) + (pi[2] + pi[3]));
+    if ((t & 63) == 0) {
+        shr[t >> 6] = wr;
+        shi[t >> 6] = wi;
     }
     __syncthreads();
-    if (threadIdx.x == 0) out[j] = zc(shr[0] + shr[1] + shr[2] + shr[3], shi[0] + shi[1] + shi[2] + shi[3]);
+    if (t == 0) part[(size_t)j * kRedChunks + c] = zc((shr[0] + shr[1]) + (shr[2] + shr[3]),
+                                                      (shi[0] + shi[1]) + (shi[2] + shi[3]));
+}
+
+// out[j] = sum_c part[j kRedChunks + c], one wave per column
+__global__ void __launch_bounds__(64) k_colsum(const double *__restrict__ part, double *__restrict__ out) {
+    const int j = blockIdx.x, t = threadIdx.x;
+    const double v = wave_sum(t < kRedChunks ? part[(size_t)j * kRedChunks + t] : 0.0);
+    if (t == 0) out[j] = v;
+}
+
+__global__ void __launch_bounds__(64) k_colsum2(const double2 *__restrict__ part, double2 *__restrict__ out) {
+    const int j = blockIdx.x, t = threadIdx.x;
+    const double2 p = t < kRedChunks ? part[(size_t)j * kRedChunks + t] : zc(0.0, 0.0);
+    const double vr = wave_sum(p.x), vi = wave_sum(p.y);
+    if (t == 0) out[j] = zc(vr, vi);
+}
+
+// out[j] = ||X(:, j)||^2 for j < nrhs; part holds nrhs * kRedChunks doubles
+static void colnorm2(const double2 *X, long ldx, long n, int nrhs, double *part, double *out, hipStream_t s) {
+    k_colnorm2_part<<<(unsigned)nrhs * kRedChunks, 256, 0, s>>>(X, ldx, n, part);
+    k_colsum<<<nrhs, 64, 0, s>>>(part, out);
+}
+
+// out[j] = A(:, j)^* B(:, j) for j < nrhs; part holds nrhs * kRedChunks complex values
+static void coldot(const double2 *A, long lda, const double2 *B, long ldb, long n, int nrhs, double2 *part,
+                   double2 *out, hipStream_t s) {
+    k_coldot_part<<<(unsigned)nrhs * kRedChunks, 256, 0, s>>>(A, lda, B, ldb, n, part);
+    k_colsum2<<<nrhs, 64, 0, s>>>(part, out);
 }
 
 __device__ __forceinline__ double2 zdiv(double2 a, double2 b) {
@@ -121,6 +179,7 @@ struct SolveWs {
     double2 *t, *R;
     void *bfws, *ulvws;
     double *nrm;
+    double *part;                      // partials of the column reductions
 };
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -128,7 +187,8 @@ static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 static size_t pcg_ws_bytes(fio_bf_s *bf, hss_ulv_s *f, int nrhs) {
     const size_t blk = align256((size_t)bf->N * nrhs * sizeof(double2));
     return 5 * blk + align256(bf_ws_bytes(bf, nrhs, FIO_PREC_FP64)) + align256(ulv_ws_bytes_pub(f, nrhs)) +
-           align256(3 * nrhs * sizeof(double2)) + align256(2 * nrhs * sizeof(double)) + 256;
+           align256(3 * nrhs * sizeof(double2)) + align256(2 * nrhs * sizeof(double)) +
+           align256((size_t)nrhs * kRedChunks * sizeof(double2)) + 256;
 }
 
 static size_t solve_ws_bytes(fio_bf_s *bf, hss_ulv_s *f, int nrhs, const fio_solve_opts *o) {
@@ -137,7 +197,8 @@ static size_t solve_ws_bytes(fio_bf_s *bf, hss_ulv_s *f, int nrhs, const fio_sol
     size_t bfw = bf_ws_bytes(bf, nrhs, (fio_prec)o->prec);
     size_t b64 = bf_ws_bytes(bf, nrhs, FIO_PREC_FP64);
     if (o->mode == FIO_SOLVE_IR && b64 > bfw) bfw = b64;
-    return 2 * blk + align256(bfw) + align256(ulv_ws_bytes_pub(f, nrhs)) + align256(2 * nrhs * sizeof(double)) + 256;
+    return 2 * blk + align256(bfw) + align256(ulv_ws_bytes_pub(f, nrhs)) + align256(2 * nrhs * sizeof(double)) +
+           align256((size_t)nrhs * kRedChunks * sizeof(double)) + 256;
 }
 
 static SolveWs carve(fio_bf_s *bf, hss_ulv_s *f, int nrhs, const fio_solve_opts *o, void *ws) {
@@ -156,6 +217,8 @@ static SolveWs carve(fio_bf_s *bf, hss_ulv_s *f, int nrhs, const fio_solve_opts 
     w.ulvws = p;
     p += align256(ulv_ws_bytes_pub(f, nrhs));
     w.nrm = (double *)p;
+    p += align256(2 * nrhs * sizeof(double));
+    w.part = (double *)p;
     return w;
 }
 
@@ -180,6 +243,8 @@ static fio_status pcg_impl(fio_bf_s *bf, hss_ulv_s *f, const double2 *U, long ld
     double2 *pap = (double2 *)q + 2 * nrhs;
     q += align256(3 * nrhs * sizeof(double2));
     double *nrm = (double *)q;             // [0, nrhs): ||r_j||^2, [nrhs, 2 nrhs): ||b_j||^2
+    q += align256(2 * nrhs * sizeof(double));
+    double2 *part = (double2 *)q;          // partials of the column reductions
     const unsigned TB = 256;
     const size_t ne = (size_t)N * nrhs;
     const unsigned g = grid1d(ne, TB);
@@ -193,10 +258,10 @@ static fio_status pcg_impl(fio_bf_s *bf, hss_ulv_s *f, const double2 *U, long ld
     }
     // r = b = K~^* u, x = 0, z = G~^{-1} r, p = z
     bf_apply_impl(bf, true, U, ldu, R, N, nrhs, FIO_PREC_FP64, bfws, s, d2);
-    if (measure) k_colnorm2<<<nrhs, 256, 0, s>>>(R, N, N, nrm + nrhs);
+    if (measure) colnorm2(R, N, N, nrhs, (double *)part, nrm + nrhs, s);
     k_zero<<<g, TB, 0, s>>>(X, ldxx, N, nrhs);
     ulv_solve_impl(f, R, N, Z, N, nrhs, ulvws, s);
-    k_coldot<<<nrhs, 256, 0, s>>>(R, N, Z, N, N, rz[0]);
+    coldot(R, N, Z, N, N, nrhs, part, rz[0], s);
     k_copy<<<g, TB, 0, s>>>(P, Z, N, N, nrhs);
     int cur = 0;
     fio_status st = FIO_OK;
@@ -204,11 +269,11 @@ static fio_status pcg_impl(fio_bf_s *bf, hss_ulv_s *f, const double2 *U, long ld
         // A p = K~^* (K~ p), K~ p staged in Z
         bf_apply_impl(bf, false, P, N, Z, N, nrhs, FIO_PREC_FP64, bfws, s, d2);
         bf_apply_impl(bf, true, Z, N, AP, N, nrhs, FIO_PREC_FP64, bfws, s, d2);
-        k_coldot<<<nrhs, 256, 0, s>>>(P, N, AP, N, N, pap);
+        coldot(P, N, AP, N, N, nrhs, part, pap, s);
         k_cg_step<<<g, TB, 0, s>>>(X, ldxx, R, P, AP, N, N, nrhs, rz[cur], pap);
         if (info) info->ir_steps = it;
         if (measure) {
-            k_colnorm2<<<nrhs, 256, 0, s>>>(R, N, N, nrm);
+            colnorm2(R, N, N, nrhs, (double *)part, nrm, s);
             FIO_HIP(hipMemcpyAsync(hn.data(), nrm, 2 * nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
             FIO_HIP(hipStreamSynchronize(s));
             double worst = 0.0;
@@ -223,7 +288,7 @@ static fio_status pcg_impl(fio_bf_s *bf, hss_ulv_s *f, const double2 *U, long ld
         }
         if (it == o->max_ir) break;
         ulv_solve_impl(f, R, N, Z, N, nrhs, ulvws, s);
-        k_coldot<<<nrhs, 256, 0, s>>>(R, N, Z, N, N, rz[1 - cur]);
+        coldot(R, N, Z, N, N, nrhs, part, rz[1 - cur], s);
         k_cg_dir<<<g, TB, 0, s>>>(P, Z, N, N, nrhs, rz[1 - cur], rz[cur]);
         cur = 1 - cur;
     }
@@ -257,7 +322,7 @@ static fio_status solve_impl(fio_bf_s *bf, hss_ulv_s *f, const double2 *U, long 
     }
     if (o->mode != FIO_SOLVE_IR) return FIO_OK;
     std::vector<double> hn(2 * nrhs);
-    if (o->rel_res_tol > 0.0) k_colnorm2<<<nrhs, 256, 0, s>>>(U, ldu, N, w.nrm + nrhs);
+    if (o->rel_res_tol > 0.0) colnorm2(U, ldu, N, nrhs, w.part, w.nrm + nrhs, s);
     for (int step = 0;; ++step) {
         const bool measure = o->rel_res_tol > 0.0;
         if (!measure && step == o->max_ir) break;
@@ -265,7 +330,7 @@ static fio_status solve_impl(fio_bf_s *bf, hss_ulv_s *f, const double2 *U, long 
         bf_apply_impl(bf, false, F, ldf, w.R, N, nrhs, FIO_PREC_FP64, w.bfws, s);
         k_resid<<<grid1d(ne, TB), TB, 0, s>>>(U, ldu, w.R, N, N, nrhs);
         if (measure) {
-            k_colnorm2<<<nrhs, 256, 0, s>>>(w.R, N, N, w.nrm);
+            colnorm2(w.R, N, N, nrhs, w.part, w.nrm, s);
             FIO_HIP(hipMemcpyAsync(hn.data(), w.nrm, 2 * nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
             FIO_HIP(hipStreamSynchronize(s));
             double worst = 0.0;
