@@ -238,6 +238,39 @@ def serving(F, torch, fi, duration, rate, seed=4, rel_res=5e-9):
             "max_col_rel_err": err, "ir_steps": [o["nir"] for o in ops]}
 
 
+def graph_replay(F, torch, fn, out, f_host, k, steps, warmup):
+    """Capture fn (one solve into out, no host synchronisation, no allocation) into a graph and
+    time its replays; the error of the replayed result is checked against f_host afterwards."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    out.zero_()
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        lat.append((e0, e1))
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    lat_ms = np.array([x.elapsed_time(y) for x, y in lat])
+    err = np.linalg.norm(out.cpu().numpy() - f_host, axis=0) / np.linalg.norm(f_host, axis=0)
+    del g
+    return {"value": k / (ms / 1e3), "ms_per_step": ms, "max_col_rel_err": float(err.max()),
+            "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))}}
+
+
 def chosen(report):
     """The choices of a fio_bf_autotune report."""
     return [x.strip()[len("chosen "):] for x in report.split(";") if x.strip().startswith("chosen")]
@@ -561,9 +594,14 @@ def main():
         results[name] = {"value": k / (ms_step / 1e3), "ms_per_step": ms_step, "max_col_rel_err": float(err.max()),
                          "ir_steps": int(max(steps_taken)), "residual_checked": checked[name],
                          "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))}}
+        # the same solve captured once into a hipGraph and replayed: the same kernels, without the
+        # per-launch host overhead between them
+        out.zero_()
+        results[name]["graph"] = graph_replay(F, torch, lambda: F.approx_solve(B, U, u, **kw), out, f_host, k,
+                                              a.steps, a.warmup)
         log(name, json.dumps(results[name]))
 
-    # direct solve (no refinement) for reference: one K~^* apply and one ULV solve
+    # the headline launch mode: eager or graph replay, whichever is faster for the head variant
     out = F.empty(n, k)
     for _ in range(a.warmup):
         F.approx_solve(B, U, u, out=out)
@@ -598,6 +636,7 @@ def main():
 
     # the headline mixed path: the faster of the two low-precision variants
     head = "split16" if results["split16"]["value"] > results["mixed"]["value"] else "mixed"
+    launch = "hipGraph replay" if results[head]["graph"]["value"] > results[head]["value"] else "eager"
     # roofline of the dominant kernel of the headline path
     ks = kernel_stats[head]
     dom = max(ks, key=lambda kn: ks[kn][1])
@@ -658,10 +697,14 @@ def main():
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(n, q, k, results["fp64"]["ir_steps"])
 
-    mixed = results[head]
+    mixed = dict(results[head])
+    if launch != "eager":
+        mixed.update({kk: results[head]["graph"][kk] for kk in ("value", "ms_per_step", "max_col_rel_err",
+                                                                "latency_ms")})
     for nm, r in results.items():
-        if r["max_col_rel_err"] > 1e-8:
-            log("ERROR: %s path missed rel err 1e-8: %g" % (nm, r["max_col_rel_err"]))
+        for lm, rr in (("eager", r), ("graph", r["graph"])):
+            if rr["max_col_rel_err"] > 1e-8:
+                log("ERROR: %s path (%s) missed rel err 1e-8: %g" % (nm, lm, rr["max_col_rel_err"]))
     line = {
         "metric": METRIC, "value": round(mixed["value"], 2), "unit": "RHS/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(mixed["ms_per_step"], 3), "higher_is_better": True,
@@ -670,7 +713,8 @@ def main():
         "config": {"workload": "1D FIO N=2^%d, c(x)=(2+sin 2pi x)/16, q=%d, HSS tol %g, p=10, %d RHS, "
                                "refinement steps calibrated to rel residual %g" % (int(np.log2(n)), q, a.hss_tol, k,
                                                                                     a.rel_res),
-                   "n": n, "nrhs": k, "q": q, "hss_tol": a.hss_tol, "mixed_variant": head, "autotuned_tiles": tuned,
+                   "n": n, "nrhs": k, "q": q, "hss_tol": a.hss_tol, "mixed_variant": head, "launch": launch,
+                   "autotuned_tiles": tuned,
                    "hss_max_rank_per_level": {str(l): int(max(v)) for l, v in ranks.items()}},
         "mixed": results["mixed"], "split16": results["split16"], "fp64": results["fp64"],
         "direct_fp64": {"ms_per_step": round(ms_direct, 3), "value": k / (ms_direct / 1e3),
