@@ -395,6 +395,11 @@ def set_fused(on=True):
     lib().fio_set_fused(1 if on else 0)
 
 
+def set_leaf_fused(on=True):
+    """Forward applies: the leaf factor folded into the first fused pass (default) or its own kernel."""
+    lib().fio_set_leaf_fused(1 if on else 0)
+
+
 def set_hss_big_node(rows):
     """HSS construction: levels whose largest node has >= rows rows use the multi-workgroup
     reflector path (rows <= 0: default 256)."""

@@ -65,6 +65,7 @@ PROTOS = {
     "fio_bf_set_tile": (i32, [vp, i32, i32, i32, i32, i32, i32]),
     "fio_bf_destroy": (None, [vp]),
     "fio_set_fused": (None, [i32]),
+    "fio_set_leaf_fused": (None, [i32]),
     "fio_hss_set_big_node": (None, [i32]),
     "fio_ulv_set_big_node": (None, [i32]),
     "fio_permute2d": (i32, [lg, i32, vp, lg, vp, lg, i32, vp]),

@@ -76,6 +76,8 @@ fio_status bf_plan(const fio_bf_desc *d, fio_bf_s *bf) {
 static bool g_fused_off = false;
 bool fused_disabled() { return g_fused_off; }
 void set_fused_disabled(bool v) { g_fused_off = v; }
+static bool g_leaf_fused_off = false;
+bool leaf_fused_disabled() { return g_leaf_fused_off; }
 
 size_t bf_tw_off(const fio_bf_s *bf, bool cside, int lev) {
     const size_t ntw = (size_t)(bf->N / 2) * 8 * bf->q;
@@ -668,6 +670,7 @@ extern "C" fio_status fio_bf_autotune(fio_bf_t bf, const void *X, long ldx, void
 extern "C" void fio_bf_destroy(fio_bf_t bf) { delete bf; }
 
 extern "C" void fio_set_fused(int on) { set_fused_disabled(on == 0); }
+extern "C" void fio_set_leaf_fused(int on) { g_leaf_fused_off = on == 0; }
 
 extern "C" const char *fio_status_str(fio_status s) {
     switch (s) {

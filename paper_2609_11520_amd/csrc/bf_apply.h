@@ -10,6 +10,7 @@ namespace fio {
 
 constexpr int kLeafPts = 8;
 bool fused_disabled();
+bool leaf_fused_disabled();
 
 // Split-FP16 transfer passes on the matrix cores (bf_lowprec.hip): KL <= 3 transfer factors of
 // one side per launch, FP32 coefficient buffers in and out, as the structured passes; the
@@ -419,16 +420,22 @@ template <typename T, int Q> struct StructArgs {
     cpx<T> *out;
     int nrhs;
     int cside;               // 1: C factors (P transposed, child index c_in)
+    const cpx<T> *V;         // LEAF: the leaf factor V^[L'] (blocks V[sigma][tau], q x 8)
+    const double2 *X;        // LEAF: the input block (column-major, leading dimension ldx)
+    long ldx;
     T P[2][Q][Q];            // P_c(i, t)
     T PT[2][Q][Q];           // P_c(t, i): the transposes, so that every variant reads one pattern
 };
 
 // Register budget: single precision keeps 8 waves per SIMD (four 37 KB workgroups per CU at
 // KL = 3, <= 64 VGPRs), double precision 4 (two 74 KB workgroups, LDS-bound anyway).
-template <typename T, int Q, int KL, bool ADJ, bool EPI_M, bool CS>
+// LEAF (forward first C pass, 3 levels): the pass also applies the leaf factor V^[L'], reading
+// the input vectors instead of the leaf coefficients (see the load phase).
+template <typename T, int Q, int KL, bool ADJ, bool EPI_M, bool CS, bool LEAF = false>
 __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_struct_fused(StructArgs<T, Q> a) {
     using C = cpx<T>;
     constexpr int P = 1 << KL, NG = P / 2;
+    static_assert(!LEAF || (!ADJ && CS && KL == 3), "the leaf factor folds into a forward 3-level C pass");
     // double precision: the twiddles of the current factor's NG groups, fetched into registers
     // during the previous factor (vector loads) and read back from LDS as broadcasts; single
     // precision reads them through the scalar cache (its register budget has no room)
@@ -442,7 +449,18 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_stru
     const int col = blockIdx.y * 64 + lane;
     const bool act = col < a.nrhs;
     const long nS = (2 * a.G0) >> KL;
-    const long A = blockIdx.x / nS, S = blockIdx.x % nS;
+    long A, S;
+    if constexpr (LEAF) {
+        // the 8 workgroups that read the same 64 input rows (one per coarse partner A) are
+        // dispatched one after another on one XCD (workgroups go round-robin over the 8 XCDs),
+        // so the rows come from HBM once and from that XCD's L2 after; needs nS % 8 == 0
+        const long b = blockIdx.x, k = b >> 3;
+        A = k & 7;
+        S = ((k >> 3) << 3) | (b & 7);
+    } else {
+        A = blockIdx.x / nS;
+        S = blockIdx.x % nS;
+    }
     const long Glast = a.G0 >> (KL - 1);
     const size_t ld = (size_t)a.nrhs;
     static_assert(NTW <= P * 64, "one twiddle per thread");
@@ -457,7 +475,38 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_stru
     constexpr int NMP = (Q * Q + 63) / 64;
     C mpf[NMP];
     if (TWL && tid < NTW) stw[tid] = tw_src(ADJ ? KL - 1 : 0, tid);
-    {
+    if constexpr (LEAF) {
+        // The input pairs are (coarse partner A, leaf boxes 8S .. 8S + 7): pair A 2^L' + box holds
+        // V[box][A] applied to rows 8 box .. 8 box + 7 of the input.  The workgroup stages rows
+        // 64S .. 64S + 63 of its 64 columns in the tile (lanes along rows, coalesced), each wave
+        // takes its box's 8 rows for its lane's column, and after a barrier writes the pair's q
+        // coefficients where the load would have put them.  Same operations, in the same order,
+        // as the leaf kernel followed by the load.
+        constexpr int XP = 65;                                   // padded column stride of the staged rows
+        static_assert(64 * XP <= P * Q * 64, "the staged rows fit the tile");
+        const int cb = blockIdx.y * 64;
+        const int ncol = a.nrhs - cb < 64 ? a.nrhs - cb : 64;
+        const double2 *xs = a.X + (size_t)S * (P * kLeafPts);
+        for (int e = tid; e < 64 * 64; e += P * 64) {
+            const int r = e & 63, cc = e >> 6;
+            const double2 v = cc < ncol ? xs[r + (size_t)(cb + cc) * a.ldx] : zc(0.0, 0.0);
+            lds[cc * XP + r] = cmake<C>((T)v.x, (T)v.y);
+        }
+        __syncthreads();
+        C x[kLeafPts];
+#pragma unroll
+        for (int t = 0; t < kLeafPts; ++t) x[t] = lds[lane * XP + wave * kLeafPts + t];
+        __syncthreads();
+        const long box = S * P + wave;
+        const C *blk = a.V + ((size_t)box * kLeafPts + A) * (Q * kLeafPts);   // nsl = 8 partners
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            C acc = czero<C>();
+#pragma unroll
+            for (int t = 0; t < kLeafPts; ++t) cfma(acc, blk[i * kLeafPts + t], x[t]);
+            lds[(wave * Q + i) * 64 + lane] = acc;
+        }
+    } else {
         const int lp = wave;
         const long gp = ADJ ? (A * P + lp) * Glast + S : A * 2 * a.G0 + S * P + lp;
         const C *src = a.in + (size_t)gp * Q * ld + col;
@@ -600,6 +649,24 @@ static void launch_struct(const StructArgs<T, Q> &sa, bool adj, bool epi, long N
         launch_struct_cs<T, Q, KL, true>(sa, adj, epi, grid, block, s);
     else
         launch_struct_cs<T, Q, KL, false>(sa, adj, epi, grid, block, s);
+}
+
+// The leaf factor folds into a 3-level pass when the pass's tile (8 q coefficient rows of
+// 64 columns) can hold the 64 staged input rows of its 64 columns.
+template <typename T, int Q> constexpr bool leaf_foldable() { return fused_max_kl<T, Q>() >= 3 && 8 * Q >= 65; }
+
+// The forward first C pass of 3 levels with the leaf factor folded in (k_struct_fused, LEAF).
+template <typename T, int Q>
+static void run_struct_leaf(const StructArgs<T, Q> &sa, bool epi, long N, hipStream_t s) {
+    if constexpr (leaf_foldable<T, Q>()) {
+        const dim3 grid((unsigned)(N >> 3), (unsigned)((sa.nrhs + 63) / 64)), block(8 * 64);
+        if (epi)
+            k_struct_fused<T, Q, 3, false, true, true, true><<<grid, block, 0, s>>>(sa);
+        else
+            k_struct_fused<T, Q, 3, false, false, true, true><<<grid, block, 0, s>>>(sa);
+    } else {
+        throw Err{FIO_ERR_UNSUPPORTED};
+    }
 }
 
 template <typename T, int Q>
@@ -784,7 +851,7 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
         const int tk = bf_tile(bf, adj, pr, nrhs).kmax;
         if (tk > 0 && tk < kmax) kmax = tk;
     }
-    auto pass = [&](bool a, bool cside, int lo, int hi, bool epi) {
+    auto pass = [&](bool a, bool cside, int lo, int hi, bool epi, bool leaf = false) {
         if constexpr (fused_q<Q>()) {
             const int kl = hi - lo;
             if constexpr (std::is_same<T, float>::value && Q == 9) {
@@ -817,14 +884,22 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
                 sa.out = nxt;
                 sa.nrhs = nrhs;
                 sa.cside = cside ? 1 : 0;
+                sa.V = F + bf->offV;
+                sa.X = X;
+                sa.ldx = ldx;
                 for (int c = 0; c < 2; ++c)
                     for (int i = 0; i < Q; ++i)
                         for (int t = 0; t < Q; ++t) {
                             sa.P[c][i][t] = (T)bf->Pchild[(c * Q + i) * Q + t];
                             sa.PT[c][t][i] = sa.P[c][i][t];
                         }
-                FIO_TIMED(f64 ? "bf_struct_f64" : "bf_struct_f32", s);
-                run_struct<T, Q>(sa, kl, a, epi, bf->N, s);
+                if (leaf) {
+                    FIO_TIMED(f64 ? "bf_struct_leaf_f64" : "bf_struct_leaf_f32", s);
+                    run_struct_leaf<T, Q>(sa, epi, bf->N, s);
+                } else {
+                    FIO_TIMED(f64 ? "bf_struct_f64" : "bf_struct_f32", s);
+                    run_struct<T, Q>(sa, kl, a, epi, bf->N, s);
+                }
                 std::swap(cur, nxt);
                 return;
             }
@@ -863,7 +938,11 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
     const bool tiled = ((1L << bf->Lp) % 4) == 0;
     const dim3 tgrid((unsigned)((1L << bf->Lp) / 4), (unsigned)((nrhs + 63) / 64));
     if (!adj) {
-        {
+        // V^[L'] folds into the first C pass when that pass is a structured one of 3 levels (one
+        // leaf box per wave) and its workgroups can be grouped by 8 per XCD (2^L' / 8 % 8 == 0)
+        const bool leaf_fused = leaf_foldable<T, Q>() && fused && bf->structured && !split &&
+                                !leaf_fused_disabled() && (kmax < bf->nl ? kmax : bf->nl) == 3 && bf->Lp >= 6;
+        if (!leaf_fused) {
             FIO_TIMED(f64 ? "bf_leaf_in_f64" : "bf_leaf_in_f32", s);
             if (tiled)
                 k_leaf_io<T, Q, true, true><<<tgrid, 256, 0, s>>>(g, F + bf->offV, X, ldx, nullptr, cur, nullptr, 0,
@@ -875,7 +954,7 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
             // C^[L'] .. C^[h+1] in passes from the top; the last pass also applies M
             for (int hi = bf->nl; hi > 0;) {
                 const int lo = hi - kmax > 0 ? hi - kmax : 0;
-                pass(false, true, lo, hi, lo == 0);
+                pass(false, true, lo, hi, lo == 0, leaf_fused && hi == bf->nl);
                 hi = lo;
             }
             for (int lo = 0; lo < bf->nl;) {

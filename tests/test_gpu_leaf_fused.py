@@ -1,0 +1,72 @@
+"""The forward apply with the leaf factor V^[L'] folded into its first 3-level pass against
+the same apply with the leaf factor as its own kernel (bitwise), and against the oracle."""
+import numpy as np
+import pytest
+
+import fio_inputs as fi
+from gpu_common import fiohss, dev, host, rel, step, oracle_bf, gpu_bf
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(float).eps
+
+
+def entry_tol(n):
+    # GPU-built factors: the oracle evaluates every phase naively (|Phi| <= 0.6 N), the GPU
+    # evaluates phase differences, as in the factor generation tests
+    return 8 * np.pi * EPS * 0.6 * n + 1e-13
+
+
+def forward(F, B, x, prec):
+    return host(B.apply(dev(x), prec=prec))
+
+
+# n = 4096 has one 3-level C pass (which also applies M), 2^14 and 2^16 a 3-level first pass
+# followed by one of 1 and 2 levels, 2^18 two 3-level passes; k covers one column, ragged
+# tiles and several 64-column tiles
+@pytest.mark.parametrize("n,k", [(4096, 1), (4096, 64), (1 << 14, 37), (1 << 16, 130), (1 << 18, 64)])
+def test_leaf_folded_pass_is_bitwise_equal_to_the_leaf_kernel(n, k):
+    F = fiohss()
+    step("leaf fused n=%d k=%d" % (n, k))
+    B = gpu_bf(F, n, 9, "sin16", imported=False, precs=(F.FIO_PREC_FP64, F.FIO_PREC_FP32))
+    x = fi.complex_gaussian(61, fi.PURPOSE_PROBE, n, k)
+    try:
+        for prec in (F.FIO_PREC_FP64, F.FIO_PREC_FP32):
+            F.set_leaf_fused(False)
+            y0 = forward(F, B, x, prec)
+            F.set_leaf_fused(True)
+            y1 = forward(F, B, x, prec)
+            assert np.array_equal(y0, y1)
+            assert np.all(np.isfinite(y1))
+    finally:
+        F.set_leaf_fused(True)
+
+
+@pytest.mark.parametrize("n", [4096, 1 << 14])
+def test_leaf_folded_pass_matches_oracle(n):
+    """GPU-built (structured) factors, the only ones the folded pass serves, against the
+    oracle: within the GPU-built factor tolerance (phases evaluated in another order)."""
+    F = fiohss()
+    step("leaf fused vs oracle n=%d" % n)
+    B = gpu_bf(F, n, 9, "sin16", imported=False, precs=(F.FIO_PREC_FP64, F.FIO_PREC_FP32))
+    ob = oracle_bf(n, 9, "sin16")
+    x = fi.complex_gaussian(62, fi.PURPOSE_PROBE, n, 70)
+    ref = ob.apply(x)
+    assert rel(forward(F, B, x, F.FIO_PREC_FP64), ref) < 20 * entry_tol(n)
+    assert rel(forward(F, B, x, F.FIO_PREC_FP32), ref) < 2e-5
+
+
+def test_other_pass_splits_keep_the_leaf_kernel():
+    """With 1 or 2 levels per pass the leaf factor runs as its own kernel; every split gives
+    the same FP64 result."""
+    F = fiohss()
+    n = 1 << 14
+    step("leaf fused pass splits")
+    B = gpu_bf(F, n, 9, "sin16", imported=False, precs=(F.FIO_PREC_FP64,))
+    x = fi.complex_gaussian(63, fi.PURPOSE_PROBE, n, 64)
+    ref = forward(F, B, x, F.FIO_PREC_FP64)
+    try:
+        for kmax in (1, 2):
+            B.set_tile(64, F.FIO_PREC_FP64, False, 0, 0, kmax)
+            assert np.array_equal(forward(F, B, x, F.FIO_PREC_FP64), ref)
+    finally:
+        B.set_tile(64, F.FIO_PREC_FP64, False, 0, 0, 0)
