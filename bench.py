@@ -632,6 +632,12 @@ def main():
         e = float((np.linalg.norm(out.cpu().numpy() - f_host, axis=0) / np.linalg.norm(f_host, axis=0)).max())
         pcg[label] = {"value": k / (ms / 1e3), "ms_per_step": round(ms, 3), "iterations": int(info.ir_steps),
                       "rel_res": info.rel_res, "max_col_rel_err": e}
+    # the fixed-iteration PCG (no host synchronisation) replayed from a captured hipGraph
+    kwg = dict(mode=F.FIO_SOLVE_PCG, prec=F.FIO_PREC_FP64, rel_res_tol=0.0,
+               max_ir=pcg["residual_checked"]["iterations"], out=out, ws=wsp)
+    out.zero_()
+    pcg["fixed_iterations"]["graph"] = graph_replay(F, torch, lambda: F.approx_solve(B, U, u, **kwg), out, f_host,
+                                                    k, a.steps, a.warmup)
     log("pcg", json.dumps(pcg))
 
     # the headline mixed path: the faster of the two low-precision variants
