@@ -81,7 +81,7 @@ def copy_calibration(torch, nbytes=1 << 30):
 
 
 def pass_plan(n, kmax=3):
-    """Structured butterfly passes of one apply: (levels, applies M) per launch (see the design notes)."""
+    """Structured butterfly passes of one apply: (levels, applies M) per launch."""
     L = int(np.log2(n))
     nl = max(L - 3, L // 2) - L // 2
     plan = []
@@ -491,8 +491,8 @@ def main():
     ap.add_argument("--no-amp", action="store_true", help="skip the variable-amplitude workload")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see the design notes on "
-              "sharding); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path; run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -39,7 +39,7 @@ typedef enum {
     FIO_ERR_HIP = -3,            /* a HIP runtime call failed */
     FIO_ERR_NOT_HPD = -4,        /* a Cholesky pivot of the ULV factorization was not positive */
     FIO_ERR_NOT_CONVERGED = -5,  /* refinement did not reach the requested residual */
-    FIO_ERR_UNSUPPORTED = -6,    /* valid request outside what this build implements */
+    FIO_ERR_UNSUPPORTED = -6,    /* valid request outside what the library implements */
     FIO_ERR_CALLBACK = -7,       /* a caller callback returned non-zero */
     FIO_WARN_RANK_CAP = 1        /* HSS ranks hit the cap; the result is valid but less accurate */
 } fio_status;
@@ -122,8 +122,9 @@ size_t fio_bf_factor_count(const fio_bf_desc *desc);
 
 /* Builds the factors on the GPU from the definitions of Section 2.2: every
  * entry of U, B, M, C, V is evaluated by a kernel from Phi, the Chebyshev
- * points and the Lagrange basis (phase differences are evaluated as
- * differences, see the design notes).  Synchronizes `stream` before returning. */
+ * points and the Lagrange basis (each exponent is a phase difference between nearby
+ * points, evaluated as such, so it stays accurate at any N).  Synchronizes `stream`
+ * before returning. */
 fio_status fio_bf_build(const fio_bf_desc *desc, void *stream, fio_bf_t *out);
 
 /* Creates a handle from explicit factors held in HOST memory, `count`

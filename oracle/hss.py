@@ -16,7 +16,7 @@ Oracle (test infrastructure only).  Follows Section 3 step by step:
   with children a1, a2, partition D^[l]_tau by (r_a1, r_a2) into A blocks;
   B_{a2,a1} = A_21 and D_a = D_res_a + U_a A_aa U_a^*.
 
-Readings of points the paper leaves open (stated once more in the design notes):
+Readings of points the paper leaves open:
   * ranks are per node (Def. hss_matrix); the effective leaf size of a
     nonleaf node is m_tau = r_a1 + r_a2, and one s_l serves a whole level:
     s_l = max_tau m_tau + rhat + p with the rank guess rhat = max_tau m_tau
