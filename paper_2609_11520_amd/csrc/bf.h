@@ -56,6 +56,9 @@ size_t bf_coef_elems(const fio_bf_s *bf, int nrhs);   // complex entries of one 
 // the user's lexicographic order (the order of the HSS tree over frequencies).
 void bf_apply_impl(fio_bf_s *bf, bool adjoint, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs,
                    fio_prec prec, void *ws, hipStream_t s, bool freq_internal = false);
+// R = U - K~ X (FP64) in one pass where the leaf kernel can subtract (1D); false otherwise
+bool bf_residual_f64(fio_bf_s *bf, const double2 *X, long ldx, const double2 *U, long ldu, double2 *R, long ldr,
+                     int nrhs, void *ws, hipStream_t s);
 // 2D butterflies (bf2d.hip)
 fio_status bf2d_plan(const fio_bf_desc *d, fio_bf_s *bf);
 size_t bf2d_ws_bytes(const fio_bf_s *bf, int nrhs, fio_prec prec);

@@ -392,7 +392,7 @@ static void bf_make_copies(fio_bf_s *bf, hipStream_t s) {
 }
 
 void bf_apply_f64(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs,
-                 const double2 *F, void *ws, hipStream_t s);
+                 const double2 *F, void *ws, hipStream_t s, const double2 *Ysub = nullptr, long ldsub = 0);
 void bf_apply_f32(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs,
                  const float2 *F, void *ws, hipStream_t s, bool split);
 
@@ -460,6 +460,15 @@ void bf_apply_impl(fio_bf_s *bf, bool adjoint, const double2 *X, long ldx, doubl
             bf_apply_split16(bf, adjoint, X, ldx, Y, ldy, nrhs, ws, s);
             break;
     }
+}
+
+// R = U - K~ X in FP64 with the subtraction done by the leaf kernel that writes K~ X (1D);
+// returns false, doing nothing, where that form does not exist (2D)
+bool bf_residual_f64(fio_bf_s *bf, const double2 *X, long ldx, const double2 *U, long ldu, double2 *R, long ldr,
+                     int nrhs, void *ws, hipStream_t s) {
+    if (bf->dim != 1) return false;
+    if (nrhs > 0) bf_apply_f64(bf, false, X, ldx, R, ldr, nrhs, bf->f64.as<double2>(), ws, s, U, ldu);
+    return true;
 }
 
 }  // namespace fio

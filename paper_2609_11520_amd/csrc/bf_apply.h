@@ -172,7 +172,8 @@ __global__ void __launch_bounds__(256) k_middle(const cpx<T> *__restrict__ M, co
 // U (forward): y[tau b + s] = sum_sigma sum_i U[tau][sigma][s][i] coef[(tau nsl + sigma) q + i]
 template <typename T, int Q>
 __global__ void k_leaf_out_fwd(Geo g, const cpx<T> *__restrict__ U, const cpx<T> *__restrict__ in,
-                               double2 *__restrict__ Y, long ldy, int nrhs) {
+                               double2 *__restrict__ Y, long ldy, int nrhs, const double2 *__restrict__ Ysub,
+                               long ldsub) {
     using C = cpx<T>;
     size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     size_t nunit = (size_t)1 << g.Lp;
@@ -195,6 +196,16 @@ __global__ void k_leaf_out_fwd(Geo g, const cpx<T> *__restrict__ U, const cpx<T>
         }
     }
     double2 *yp = Y + (size_t)col * ldy + tau * kLeafPts;
+    if (Ysub) {
+        // Y = Ysub - (the apply), the residual of a refinement step
+        const double2 *up = Ysub + (size_t)col * ldsub + tau * kLeafPts;
+#pragma unroll
+        for (int s = 0; s < kLeafPts; ++s) {
+            const double2 u = up[s];
+            yp[s] = zc(u.x - (double)acc[s].x, u.y - (double)acc[s].y);
+        }
+        return;
+    }
 #pragma unroll
     for (int s = 0; s < kLeafPts; ++s) yp[s] = zc((double)acc[s].x, (double)acc[s].y);
 }
@@ -697,7 +708,8 @@ template <typename T, int Q, bool IN, bool VSIDE>
 __global__ void __launch_bounds__(256, 4) k_leaf_io(Geo g, const cpx<T> *__restrict__ Fblk,
                                                  const double2 *__restrict__ Xin, long ldx,
                                                  const cpx<T> *__restrict__ cin, cpx<T> *__restrict__ cout,
-                                                 double2 *__restrict__ Yout, long ldy, int nrhs) {
+                                                 double2 *__restrict__ Yout, long ldy, int nrhs,
+                                                 const double2 *__restrict__ Ysub, long ldsub) {
     using C = cpx<T>;
     constexpr int NB = 4;                           // leaf boxes per workgroup
     constexpr int R = NB * kLeafPts;                // rows per workgroup
@@ -807,7 +819,13 @@ __global__ void __launch_bounds__(256, 4) k_leaf_io(Geo g, const cpx<T> *__restr
             const int r = e % R, cc = e / R;
             if (cc < ncol) {
                 C v = tile[cc][r];
-                Yout[(box0 * kLeafPts + r) + (size_t)(c0 + cc) * ldy] = zc((double)v.x, (double)v.y);
+                double2 y = zc((double)v.x, (double)v.y);
+                if (Ysub) {
+                    // Yout = Ysub - (the apply), the residual of a refinement step
+                    const double2 u = Ysub[(box0 * kLeafPts + r) + (size_t)(c0 + cc) * ldsub];
+                    y = zc(u.x - y.x, u.y - y.y);
+                }
+                Yout[(box0 * kLeafPts + r) + (size_t)(c0 + cc) * ldy] = y;
             }
         }
     }
@@ -815,7 +833,8 @@ __global__ void __launch_bounds__(256, 4) k_leaf_io(Geo g, const cpx<T> *__restr
 
 template <typename T, int Q>
 static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs,
-                    const cpx<T> *F, cpx<T> *c0, cpx<T> *c1, hipStream_t s, bool split) {
+                    const cpx<T> *F, cpx<T> *c0, cpx<T> *c1, hipStream_t s, bool split, const double2 *Ysub,
+                    long ldsub) {
     Geo g = geo_of(bf);
     const unsigned TB = 256;
     const bool uni = (nrhs % 64) == 0;
@@ -946,7 +965,7 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
             FIO_TIMED(f64 ? "bf_leaf_in_f64" : "bf_leaf_in_f32", s);
             if (tiled)
                 k_leaf_io<T, Q, true, true><<<tgrid, 256, 0, s>>>(g, F + bf->offV, X, ldx, nullptr, cur, nullptr, 0,
-                                                                  nrhs);
+                                                                  nrhs, nullptr, 0);
             else
                 k_leaf_in_fwd<T, Q><<<grid1d(nleaf * nrhs, TB), TB, 0, s>>>(g, F + bf->offV, X, ldx, cur, nrhs);
         }
@@ -970,16 +989,16 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
         FIO_TIMED(f64 ? "bf_leaf_out_f64" : "bf_leaf_out_f32", s);
         if (tiled)
             k_leaf_io<T, Q, false, false><<<tgrid, 256, 0, s>>>(g, F + bf->offU, nullptr, 0, cur, nullptr, Y, ldy,
-                                                                nrhs);
+                                                                nrhs, Ysub, ldsub);
         else
             k_leaf_out_fwd<T, Q><<<grid1d(((size_t)1 << bf->Lp) * nrhs, TB), TB, 0, s>>>(g, F + bf->offU, cur, Y,
-                                                                                           ldy, nrhs);
+                                                                                           ldy, nrhs, Ysub, ldsub);
     } else {
         {
             FIO_TIMED(f64 ? "bf_leaf_in_f64" : "bf_leaf_in_f32", s);
             if (tiled)
                 k_leaf_io<T, Q, true, false><<<tgrid, 256, 0, s>>>(g, F + bf->offU, X, ldx, nullptr, cur, nullptr, 0,
-                                                                   nrhs);
+                                                                   nrhs, nullptr, 0);
             else
                 k_leaf_in_adj<T, Q><<<grid1d(nleaf * nrhs, TB), TB, 0, s>>>(g, F + bf->offU, X, ldx, cur, nrhs);
         }
@@ -1003,7 +1022,7 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
         FIO_TIMED(f64 ? "bf_leaf_out_f64" : "bf_leaf_out_f32", s);
         if (tiled)
             k_leaf_io<T, Q, false, true><<<tgrid, 256, 0, s>>>(g, F + bf->offV, nullptr, 0, cur, nullptr, Y, ldy,
-                                                               nrhs);
+                                                               nrhs, nullptr, 0);
         else
             k_leaf_out_adj<T, Q><<<grid1d(((size_t)1 << bf->Lp) * nrhs, TB), TB, 0, s>>>(g, F + bf->offV, cur, Y,
                                                                                            ldy, nrhs);
@@ -1013,12 +1032,13 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
 
 template <typename T>
 void apply_t(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs,
-                    const cpx<T> *F, void *ws, hipStream_t s, bool split = false) {
+                    const cpx<T> *F, void *ws, hipStream_t s, bool split = false, const double2 *Ysub = nullptr,
+                    long ldsub = 0) {
     cpx<T> *c0 = reinterpret_cast<cpx<T> *>(ws);
     cpx<T> *c1 = c0 + bf_coef_elems(bf, nrhs);
     switch (bf->q) {
 #define FIO_Q(QQ) \
-    case QQ: apply_q<T, QQ>(bf, adj, X, ldx, Y, ldy, nrhs, F, c0, c1, s, split); break;
+    case QQ: apply_q<T, QQ>(bf, adj, X, ldx, Y, ldy, nrhs, F, c0, c1, s, split, Ysub, ldsub); break;
         FIO_Q(2) FIO_Q(3) FIO_Q(4) FIO_Q(5) FIO_Q(6) FIO_Q(7) FIO_Q(8) FIO_Q(9)
         FIO_Q(10) FIO_Q(11) FIO_Q(12) FIO_Q(13) FIO_Q(14) FIO_Q(15) FIO_Q(16)
 #undef FIO_Q

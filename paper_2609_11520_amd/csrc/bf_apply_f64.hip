@@ -3,7 +3,7 @@
 
 namespace fio {
 void bf_apply_f64(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs,
-                 const cpx<double> *F, void *ws, hipStream_t s) {
-    apply_t<double>(bf, adj, X, ldx, Y, ldy, nrhs, F, ws, s);
+                 const cpx<double> *F, void *ws, hipStream_t s, const double2 *Ysub, long ldsub) {
+    apply_t<double>(bf, adj, X, ldx, Y, ldy, nrhs, F, ws, s, false, Ysub, ldsub);
 }
 }  // namespace fio

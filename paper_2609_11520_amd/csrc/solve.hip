@@ -327,8 +327,10 @@ static fio_status solve_impl(fio_bf_s *bf, hss_ulv_s *f, const double2 *U, long 
         const bool measure = o->rel_res_tol > 0.0;
         if (!measure && step == o->max_ir) break;
         // R = u - K~ f in FP64
-        bf_apply_impl(bf, false, F, ldf, w.R, N, nrhs, FIO_PREC_FP64, w.bfws, s);
-        k_resid<<<grid1d(ne, TB), TB, 0, s>>>(U, ldu, w.R, N, N, nrhs);
+        if (!bf_residual_f64(bf, F, ldf, U, ldu, w.R, N, nrhs, w.bfws, s)) {
+            bf_apply_impl(bf, false, F, ldf, w.R, N, nrhs, FIO_PREC_FP64, w.bfws, s);
+            k_resid<<<grid1d(ne, TB), TB, 0, s>>>(U, ldu, w.R, N, N, nrhs);
+        }
         if (measure) {
             colnorm2(w.R, N, N, nrhs, w.part, w.nrm, s);
             FIO_HIP(hipMemcpyAsync(hn.data(), w.nrm, 2 * nrhs * sizeof(double), hipMemcpyDeviceToHost, s));

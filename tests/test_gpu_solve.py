@@ -114,3 +114,23 @@ def test_n2e16_sixteen_rhs_and_dft_sanity(phase):
         assert info.rel_res <= 1e-10 and osolve.col_rel_err(host(fr), f) < 1e-8
         fp, info = F.approx_solve(B, U, u, mode=F.FIO_SOLVE_PCG, rel_res_tol=1e-12, max_ir=30)
         assert info.ir_steps <= 8 and osolve.col_rel_err(host(fp), f) < 1e-10
+
+
+@pytest.mark.parametrize("n,prec", [(1 << 14, 2), (1 << 14, 0), (4096, 1)])
+def test_refinement_step_equals_its_parts(n, prec):
+    """One refinement step (Section 4 direct solve, then f + F K~^*_p (u - K~ f) with the
+    residual formed inside the FP64 apply's leaf kernel) equals, bitwise, the same step
+    assembled from separate calls: direct solve, FP64 apply, subtraction, direct solve of the
+    residual, addition."""
+    F = fiohss()
+    step("refinement step parts n=%d prec=%d" % (n, prec))
+    B = F.BF(n, 9, 2.0 / 16, 1.0 / 16, precs=(F.FIO_PREC_FP64, F.FIO_PREC_FP32, F.FIO_PREC_SPLIT_FP16))
+    U = F.ULV(F.HSS.from_bf(B, tol=1e-3, p=10, seed=31))
+    f = fi.rhs(4, n, 37)
+    u = B.apply(dev(f))
+    f1, info = F.approx_solve(B, U, u, mode=F.FIO_SOLVE_IR, prec=prec, rel_res_tol=0.0, max_ir=1)
+    assert info.ir_steps == 1
+    f0, _ = F.approx_solve(B, U, u, prec=prec)
+    r = u - B.apply(f0)
+    d, _ = F.approx_solve(B, U, r, prec=prec)
+    assert np.array_equal(host(f1), host(f0 + d))
