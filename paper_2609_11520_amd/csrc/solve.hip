@@ -8,7 +8,8 @@
 struct hss_ulv_s;
 
 namespace fio {
-void ulv_solve_impl(hss_ulv_s *f, const double2 *Y, long ldy, double2 *C, long ldc, int nrhs, void *ws, hipStream_t s);
+void ulv_solve_impl(hss_ulv_s *f, const double2 *Y, long ldy, double2 *C, long ldc, int nrhs, void *ws, hipStream_t s,
+                    bool accumulate = false);
 size_t ulv_ws_bytes_pub(const hss_ulv_s *f, int nrhs);
 
 // R = U - R (in place), N x nrhs blocks
@@ -348,14 +349,14 @@ static fio_status solve_impl(fio_bf_s *bf, hss_ulv_s *f, const double2 *U, long 
             if (worst <= o->rel_res_tol) return FIO_OK;
             if (step == o->max_ir) return FIO_ERR_NOT_CONVERGED;
         }
-        // f += F K~^*_prec r
+        // f += F K~^*_prec r (1D: the ULV solve's last level adds to f)
         bf_apply_impl(bf, true, w.R, N, w.t, N, nrhs, lp, w.bfws, s, d2);
-        ulv_solve_impl(f, w.t, N, w.t, N, nrhs, w.ulvws, s);
         if (d2) {
+            ulv_solve_impl(f, w.t, N, w.t, N, nrhs, w.ulvws, s);
             permute2d((int)bf->n1, false, w.t, N, w.R, N, nrhs, s);
             k_axpy<<<grid1d(ne, TB), TB, 0, s>>>(F, ldf, w.R, N, N, nrhs);
         } else {
-            k_axpy<<<grid1d(ne, TB), TB, 0, s>>>(F, ldf, w.t, N, N, nrhs);
+            ulv_solve_impl(f, w.t, N, F, ldf, nrhs, w.ulvws, s, true);
         }
         if (info && !measure) info->ir_steps = step + 1;
     }

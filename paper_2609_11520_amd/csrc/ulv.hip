@@ -539,11 +539,21 @@ struct LevelArgs {
     const long *yoff, *roff;
 };
 
+// The solve's output: written, or added to what the output holds (accum != 0: the update
+// f += G~^{-1} y of a refinement step, fused into the last level)
+__device__ __forceinline__ void ulv_store(double2 *p, double2 v, int accum) {
+    if (accum) {
+        const double2 o = *p;
+        v = zc(o.x + v.x, o.y + v.y);
+    }
+    *p = v;
+}
+
 template <bool DOWN>
 __global__ void __launch_bounds__(256) k_ulv_level(LevelArgs a, const double2 *__restrict__ Yin, long ldin,
                                                    double2 *__restrict__ Bh, long ldb, double2 *__restrict__ Ylo,
                                                    long ldlo, double2 *__restrict__ Yout, long ldout, int nrhs,
-                                                   int tilesN) {
+                                                   int tilesN, int accum) {
     const int node = blockIdx.y;
     const int m = a.m[node], k = a.k[node];
     const int tm = blockIdx.x / tilesN, tn = blockIdx.x % tilesN;
@@ -612,7 +622,7 @@ __global__ void __launch_bounds__(256) k_ulv_level(LevelArgs a, const double2 *_
             int gn = n0 + ty + 16 * y;
             if (gn >= nrhs) continue;
             if (DOWN)
-                Yout[(yo + gm) + (size_t)gn * ldout] = acc[x][y];
+                ulv_store(Yout + (yo + gm) + (size_t)gn * ldout, acc[x][y], accum);
             else if (gm < k)
                 Bh[(yo + gm) + (size_t)gn * ldb] = acc[x][y];
             else
@@ -628,7 +638,8 @@ __global__ void __launch_bounds__(256) k_ulv_level(LevelArgs a, const double2 *_
 template <bool DOWN>
 __global__ void __launch_bounds__(256) k_ulv_level64(LevelArgs a, const double2 *__restrict__ Yin, long ldin,
                                                      double2 *__restrict__ Bh, long ldb, double2 *__restrict__ Ylo,
-                                                     long ldlo, double2 *__restrict__ Yout, long ldout, int nrhs) {
+                                                     long ldlo, double2 *__restrict__ Yout, long ldout, int nrhs,
+                                                     int accum) {
     const int node = blockIdx.y;
     const int m = a.m[node], k = a.k[node];
     const int n0 = blockIdx.x * 64;
@@ -703,7 +714,7 @@ __global__ void __launch_bounds__(256) k_ulv_level64(LevelArgs a, const double2 
             const int gn = n0 + ty + 16 * y;
             if (gn >= nrhs) continue;
             if (DOWN)
-                Yout[(yo + gm) + (size_t)gn * ldout] = acc[x][y];
+                ulv_store(Yout + (yo + gm) + (size_t)gn * ldout, acc[x][y], accum);
             else if (gm < k)
                 Bh[(yo + gm) + (size_t)gn * ldb] = acc[x][y];
             else
@@ -776,7 +787,7 @@ __global__ void __launch_bounds__(64) k_ulv_narrow(LevelArgs a, const double2 *_
 template <bool DOWN>
 __global__ void k_ulv_narrow_sum(LevelArgs a, const double2 *__restrict__ P, int S, long rows, int nrhs, int c0,
                                  double2 *__restrict__ Bh, long ldb, double2 *__restrict__ Ylo, long ldlo,
-                                 double2 *__restrict__ Yout, long ldout) {
+                                 double2 *__restrict__ Yout, long ldout, int accum) {
     const int node = blockIdx.y;
     const int m = a.m[node], k = a.k[node];
     const long yo = a.yoff[node], ro = a.roff[node];
@@ -787,7 +798,7 @@ __global__ void k_ulv_narrow_sum(LevelArgs a, const double2 *__restrict__ P, int
         double2 v = zc(0.0, 0.0);
         for (int q = 0; q < S; ++q) v = cadd(v, P[((size_t)q * rows + yo + r) * kNarrowCols + c]);
         if (DOWN)
-            Yout[(yo + r) + (size_t)(c0 + c) * ldout] = v;
+            ulv_store(Yout + (yo + r) + (size_t)(c0 + c) * ldout, v, accum);
         else if (r < k)
             Bh[(yo + r) + (size_t)(c0 + c) * ldb] = v;
         else
@@ -1088,8 +1099,9 @@ static size_t ulv_ws_bytes(const hss_ulv_s *f, int nrhs) {
     return (rows + 8 * (size_t)(f->Lh + 2)) * (size_t)nrhs * sizeof(double2) + part * sizeof(double2) + 8192;
 }
 
+// C = G~^{-1} Y, or C += G~^{-1} Y with accumulate (the last level adds to C)
 void ulv_solve_impl(hss_ulv_s *f, const double2 *Y, long ldy, double2 *C, long ldc, int nrhs, void *ws,
-                    hipStream_t s) {
+                    hipStream_t s, bool accumulate = false) {
     if (nrhs <= 0) return;
     const int Lh = f->Lh;
     double2 *base = reinterpret_cast<double2 *>(ws);
@@ -1144,16 +1156,16 @@ void ulv_solve_impl(hss_ulv_s *f, const double2 *Y, long ldy, double2 *C, long l
                                                      S, f->rows[l], part);
                 dim3 g2((unsigned)((mmax(l) * kNarrowCols + 255) / 256), (unsigned)f->m[l].size());
                 k_ulv_narrow_sum<false><<<g2, 256, 0, s>>>(args(l), part, S, f->rows[l], nrhs, c0, Bl[l], f->rows[l],
-                                                           Yl[l - 1], f->rows[l - 1], nullptr, 0);
+                                                           Yl[l - 1], f->rows[l - 1], nullptr, 0, 0);
             }
         } else if (mmax(l) > 32 && mmax(l) <= 64) {
             dim3 grid((unsigned)((nrhs + 63) / 64), f->m[l].size());
             k_ulv_level64<false><<<grid, 256, 0, s>>>(args(l), yin, ldin, Bl[l], f->rows[l], Yl[l - 1],
-                                                      f->rows[l - 1], nullptr, 0, nrhs);
+                                                      f->rows[l - 1], nullptr, 0, nrhs, 0);
         } else {
             dim3 grid(tilesM * tilesN, f->m[l].size());
             k_ulv_level<false><<<grid, 256, 0, s>>>(args(l), yin, ldin, Bl[l], f->rows[l], Yl[l - 1], f->rows[l - 1],
-                                                    nullptr, 0, nrhs, tilesN);
+                                                    nullptr, 0, nrhs, tilesN, 0);
         }
     }
     // root: Y0 <- Linv^* Linv Y0
@@ -1170,6 +1182,7 @@ void ulv_solve_impl(hss_ulv_s *f, const double2 *Y, long ldy, double2 *C, long l
         if (tilesM == 0) continue;
         double2 *yout = (l == Lh) ? C : Yl[l];
         long ldout = (l == Lh) ? ldc : f->rows[l];
+        const int acc_l = (l == Lh && accumulate) ? 1 : 0;
         FIO_TIMED("ulv_down", s);
         if (narrow(l)) {
             const int S = slices(l);
@@ -1179,16 +1192,16 @@ void ulv_solve_impl(hss_ulv_s *f, const double2 *Y, long ldy, double2 *C, long l
                                                     Yl[l - 1], f->rows[l - 1], nrhs, c0, S, f->rows[l], part);
                 dim3 g2((unsigned)((mmax(l) * kNarrowCols + 255) / 256), (unsigned)f->m[l].size());
                 k_ulv_narrow_sum<true><<<g2, 256, 0, s>>>(args(l), part, S, f->rows[l], nrhs, c0, nullptr, 0,
-                                                          nullptr, 0, yout, ldout);
+                                                          nullptr, 0, yout, ldout, acc_l);
             }
         } else if (mmax(l) > 32 && mmax(l) <= 64) {
             dim3 grid((unsigned)((nrhs + 63) / 64), f->m[l].size());
             k_ulv_level64<true><<<grid, 256, 0, s>>>(args(l), nullptr, 0, Bl[l], f->rows[l], Yl[l - 1],
-                                                     f->rows[l - 1], yout, ldout, nrhs);
+                                                     f->rows[l - 1], yout, ldout, nrhs, acc_l);
         } else {
             dim3 grid(tilesM * tilesN, f->m[l].size());
             k_ulv_level<true><<<grid, 256, 0, s>>>(args(l), nullptr, 0, Bl[l], f->rows[l], Yl[l - 1], f->rows[l - 1],
-                                                   yout, ldout, nrhs, tilesN);
+                                                   yout, ldout, nrhs, tilesN, acc_l);
         }
     }
     FIO_HIP(hipGetLastError());
