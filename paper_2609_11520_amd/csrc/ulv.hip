@@ -633,8 +633,9 @@ __global__ void __launch_bounds__(256) k_ulv_level(LevelArgs a, const double2 *_
 
 // The same level product for nodes of at most 64 rows (the leaf level): one workgroup per
 // node and 64 right-hand sides, 4 x 4 outputs per thread, so W and the vector block are read
-// once and every LDS operand read feeds four multiply-adds.  Accumulation runs over k in the
-// order of k_ulv_level, so both kernels give identical results.
+// once and every LDS operand read feeds four multiply-adds; the next 16-deep tiles of both
+// operands are fetched into registers while the current ones are used.  Accumulation runs
+// over k in the order of k_ulv_level, so both kernels give identical results.
 template <bool DOWN>
 __global__ void __launch_bounds__(256) k_ulv_level64(LevelArgs a, const double2 *__restrict__ Yin, long ldin,
                                                      double2 *__restrict__ Bh, long ldb, double2 *__restrict__ Ylo,
@@ -654,33 +655,40 @@ __global__ void __launch_bounds__(256) k_ulv_level64(LevelArgs a, const double2 
     for (int x = 0; x < 4; ++x)
 #pragma unroll
         for (int y = 0; y < 4; ++y) acc[x][y] = zc(0.0, 0.0);
-    for (int k0 = 0; k0 < m; k0 += 16) {
+    // element r of this thread's share of a 16-deep A / B tile, and its LDS slot
+    int amm[4], akk[4], bkk[4], bnn[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int e = tid + 256 * r;
+        if (DOWN) {
+            akk[r] = e % 16;
+            amm[r] = e / 16;
+        } else {
+            amm[r] = e % 64;
+            akk[r] = e / 64;
+        }
+        bkk[r] = e % 16;
+        bnn[r] = e / 16;
+    }
+    double2 pa[4], pb[4];
+    auto fetch = [&](int k0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int e = tid + 256 * r;
-            int mm, kk;
+            const int gm = amm[r], gk = k0 + akk[r];
             double2 v = zc(0.0, 0.0);
-            if (DOWN) {      // op(A) = W^*: element (row, kk) = conj(W(kk, row))
-                kk = e % 16;
-                mm = e / 16;
-                const int gm = mm, gk = k0 + kk;
-                if (gm < m && gk < m) {
+            if (gm < m && gk < m) {
+                if (DOWN) {
                     const double2 t = W[gk + (size_t)gm * m];
                     v = zc(t.x, -t.y);
+                } else {
+                    v = W[gm + (size_t)gk * m];
                 }
-            } else {
-                mm = e % 64;
-                kk = e / 64;
-                const int gm = mm, gk = k0 + kk;
-                if (gm < m && gk < m) v = W[gm + (size_t)gk * m];
             }
-            As[kk][mm] = v;
+            pa[r] = v;
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int e = tid + 256 * r;
-            const int kk = e % 16, nn = e / 16;
-            const int gk = k0 + kk, gn = n0 + nn;
+            const int gk = k0 + bkk[r], gn = n0 + bnn[r];
             double2 v = zc(0.0, 0.0);
             if (gk < m && gn < nrhs) {
                 if (DOWN)
@@ -688,9 +696,19 @@ __global__ void __launch_bounds__(256) k_ulv_level64(LevelArgs a, const double2 
                 else
                     v = Yin[(yo + gk) + (size_t)gn * ldin];
             }
-            Bs[kk][nn] = v;
+            pb[r] = v;
+        }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < m; k0 += 16) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            As[akk[r]][amm[r]] = pa[r];
+            Bs[bkk[r]][bnn[r]] = pb[r];
         }
         __syncthreads();
+        // the next tile is fetched while this one is used
+        if (k0 + 16 < m) fetch(k0 + 16);
 #pragma unroll
         for (int kk = 0; kk < 16; ++kk) {
             double2 av[4], bv[4];
