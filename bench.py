@@ -397,7 +397,20 @@ def workload_2d(F, torch, fi, steps, warmup, rel_res=5e-9, solve=True, var_amp=F
         err = np.linalg.norm(fd.cpu().numpy() - f_host, axis=0) / np.linalg.norm(f_host, axis=0)
         sol["pcg_fp64"] = {"ms": round(ms, 3), "rhs_per_s": k / (ms / 1e3), "iterations": nit,
                            "max_col_rel_err": float(err.max())}
-        res.update({"offline_s": {"hss": round(t_hss, 2), "ulv": round(t_ulv, 2)},
+        # the same construction with the K~^* K~ samples applied in FP32 (hss_opts.sample_prec)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        H32 = F.HSS.from_bf(B, tol=1e-3, p=10, seed=1003, sample_prec=F.FIO_PREC_FP32)
+        torch.cuda.synchronize()
+        t_hss32 = time.perf_counter() - t
+        U32 = F.ULV(H32)
+        _, info32 = F.approx_solve(B, U32, u, mode=F.FIO_SOLVE_IR, prec=F.FIO_PREC_FP32, rel_res_tol=rel_res,
+                                   max_ir=10, out=fd)
+        err32 = np.linalg.norm(fd.cpu().numpy() - f_host, axis=0) / np.linalg.norm(f_host, axis=0)
+        sol["mixed_on_fp32_sampled_hss"] = {"ir_steps": int(info32.ir_steps), "max_col_rel_err": float(err32.max())}
+        del H32, U32
+        res.update({"offline_s": {"hss": round(t_hss, 2), "ulv": round(t_ulv, 2),
+                                  "hss_fp32_samples": round(t_hss32, 2)},
                     "hss_max_rank_per_level": {str(l): int(max(v)) for l, v in H.ranks().items()},
                     "solve": sol})
     return res

@@ -266,6 +266,10 @@ typedef struct {
     int rhat;           /* rank guess added to the sample count; <= 0: m_max */
     double norm_est;    /* scale of the tolerance; <= 0: estimated from the leaf samples */
     int rank_cap;       /* <= 0: no cap; else ranks are truncated at rank_cap (FIO_WARN_RANK_CAP) */
+    int sample_prec;    /* fio_hss_build only: fio_prec of the K~^* K~ sample applies, FIO_PREC_FP64
+                           (0, default) or FIO_PREC_FP32 (needs the handle's FP32 copy, else FIO_ERR_ARG;
+                           its ~1e-6 relative rounding sits far below the truncation tolerances the
+                           construction is used with); ignored by hss_build_from_samples */
 } hss_opts;
 
 /* Y = H X for ncols columns (device, column-major).  Return 0 on success. */
@@ -282,7 +286,7 @@ fio_status hss_build_from_samples(long n, const hss_opts *opts, hss_matvec_fn ma
                                   hss_omega_fn omega, void *omega_ctx, void *stream, hss_t *out);
 
 /* Algorithm alg:fio_inv step 2: hss_build_from_samples with the matvec
- * X -> K~^* (K~ X) applied in FP64 by this library's BF kernels. */
+ * X -> K~^* (K~ X) applied by this library's BF kernels, in opts->sample_prec. */
 fio_status fio_hss_build(fio_bf_t bf, const hss_opts *opts, hss_omega_fn omega, void *omega_ctx,
                          void *stream, hss_t *out);
 

@@ -237,11 +237,14 @@ class HSS:
         return _lib.HssOpts(leaf, tol, p, rhat, norm_est, rank_cap)
 
     @classmethod
-    def from_bf(cls, bf, tol, p=10, leaf=64, omega=None, seed=1000, rhat=0, norm_est=0.0, rank_cap=0):
-        """Algorithm alg:fio_inv step 2 with K~^* K~ applied by the library's BF kernels."""
+    def from_bf(cls, bf, tol, p=10, leaf=64, omega=None, seed=1000, rhat=0, norm_est=0.0, rank_cap=0,
+                sample_prec=FIO_PREC_FP64):
+        """Algorithm alg:fio_inv step 2 with K~^* K~ applied by the library's BF kernels, in
+        sample_prec (FP64, or FP32 when the handle holds the FP32 copy)."""
         cb = omega if omega is not None else omega_torch(seed)
         h = C.c_void_p()
         o = cls._opts(tol, p, leaf, rhat, norm_est, rank_cap)
+        o.sample_prec = sample_prec
         st = lib().fio_hss_build(bf.h, C.byref(o), cb, None, _stream(), C.byref(h))
         _lib.check(st, "fio_hss_build", allow_warn=True)
         obj = cls(h)

@@ -1021,6 +1021,7 @@ extern "C" fio_status hss_build_from_samples(long n, const hss_opts *opts, hss_m
 namespace {
 struct BfGram {
     fio_bf_s *bf;
+    fio_prec prec;           // precision of the sample applies
     DevBuf ws, tmp;
 };
 int bf_gram_matvec(void *ctx, const void *X, long ldx, void *Y, long ldy, int ncols, void *stream) {
@@ -1033,14 +1034,14 @@ int bf_gram_matvec(void *ctx, const void *X, long ldx, void *Y, long ldy, int nc
         const bool fint = g->bf->dim == 2;
         const int chunk = fint ? 64 : ncols;
         const int c1 = ncols < chunk ? ncols : chunk;
-        g->ws.ensure(bf_ws_bytes(g->bf, c1, FIO_PREC_FP64));
+        g->ws.ensure(bf_ws_bytes(g->bf, c1, g->prec));
         g->tmp.ensure((size_t)g->bf->N * c1 * sizeof(double2));
         for (int c0 = 0; c0 < ncols; c0 += chunk) {
             const int nc = ncols - c0 < chunk ? ncols - c0 : chunk;
             bf_apply_impl(g->bf, false, (const double2 *)X + (size_t)c0 * ldx, ldx, g->tmp.as<double2>(), g->bf->N,
-                          nc, FIO_PREC_FP64, g->ws.p, s, fint);
+                          nc, g->prec, g->ws.p, s, fint);
             bf_apply_impl(g->bf, true, g->tmp.as<double2>(), g->bf->N, (double2 *)Y + (size_t)c0 * ldy, ldy, nc,
-                          FIO_PREC_FP64, g->ws.p, s, fint);
+                          g->prec, g->ws.p, s, fint);
         }
         return FIO_OK;
     });
@@ -1050,9 +1051,11 @@ int bf_gram_matvec(void *ctx, const void *X, long ldx, void *Y, long ldy, int nc
 
 extern "C" fio_status fio_hss_build(fio_bf_t bf, const hss_opts *opts, hss_omega_fn omega, void *omega_ctx,
                                     void *stream, hss_t *out) {
-    FIO_CHECK_ARG(bf);
+    FIO_CHECK_ARG(bf && opts);
+    FIO_CHECK_ARG(opts->sample_prec == FIO_PREC_FP64 || (opts->sample_prec == FIO_PREC_FP32 && bf->f32.p));
     BfGram g;
     g.bf = bf;
+    g.prec = (fio_prec)opts->sample_prec;
     Sampler sm{bf_gram_matvec, &g, omega, omega_ctx};
     return build_impl(bf->N, opts, sm, as_stream(stream), out);
 }
