@@ -199,35 +199,23 @@ __global__ void __launch_bounds__(1024) k_ulv_node(FactArgs a) {
         if (tid == 0) atomicAdd(a.fail, 1);
         return;
     }
-    // Dhat21 = Dchk21 L11^{-*} in place in T(k.., 0..k): X L^* = B, forward over columns
-    for (int i = tid; i < r; i += nt) {
-        double2 *row = T + k + i;
-        for (int j = 0; j < k; ++j) {
-            double2 acc = row[(size_t)j * m];
-            for (int l = 0; l < j; ++l) {
-                double2 x = row[(size_t)l * m], Ljl = T[j + (size_t)l * m];
-                // acc -= x conj(Ljl)
-                acc.x -= x.x * Ljl.x + x.y * Ljl.y;
-                acc.y -= x.y * Ljl.x - x.x * Ljl.y;
-            }
-            double d = T[j + (size_t)j * m].x;
-            row[(size_t)j * m] = zc(acc.x / d, acc.y / d);
+    // X = Dhat21^* = L11^{-1} Dchk12 (k x r; Dchk is Hermitian, so Dchk12 = Dchk21^*), in place
+    // in T(0..k, k..m), forward substitution per column
+    for (int c = tid; c < r; c += nt) {
+        double2 *col = T + (size_t)(k + c) * m;
+        for (int i = 0; i < k; ++i) {
+            double2 acc = col[i];
+            for (int l = 0; l < i; ++l) acc = csub(acc, cmul(T[i + (size_t)l * m], col[l]));
+            const double d = T[i + (size_t)i * m].x;
+            col[i] = zc(acc.x / d, acc.y / d);
         }
     }
-    __syncthreads();
-    // Dhat22 = Dchk22 - Dhat21 Dhat21^*
+    // Dhat22 starts as Dchk22; the level's batched GEMM subtracts X^* X
     double2 *D22 = a.D22 + a.soff[node];
     for (int e = tid; e < r * r; e += nt) {
-        int i = e % r, j = e / r;
-        double2 acc = T[(k + i) + (size_t)(k + j) * m];
-        for (int l = 0; l < k; ++l) {
-            double2 x = T[(k + i) + (size_t)l * m], y = T[(k + j) + (size_t)l * m];
-            acc.x -= x.x * y.x + x.y * y.y;
-            acc.y -= x.y * y.x - x.x * y.y;
-        }
-        D22[e] = acc;
+        const int i = e % r, j = e / r;
+        D22[e] = T[(k + i) + (size_t)(k + j) * m];
     }
-    __syncthreads();
     // W1 = L11^{-1} Q1^* (k x m), forward substitution per column c of Q1^*
     for (int c = tid; c < m; c += nt) {
         for (int i = 0; i < k; ++i) {
@@ -241,17 +229,11 @@ __global__ void __launch_bounds__(1024) k_ulv_node(FactArgs a) {
             Wm[i + (size_t)c * m] = zc(acc.x / d, acc.y / d);
         }
     }
-    __syncthreads();
-    // W2 = Q2^* - Dhat21 W1 (r x m)
+    // W2 starts as Q2^* (r x m); the level's batched GEMM subtracts X^* W1 (= Dhat21 W1)
     for (int e = tid; e < r * m; e += nt) {
-        int i = e % r, c = e / r;
-        double2 q = Q[c + (size_t)(k + i) * m];
-        double2 acc = zc(q.x, -q.y);
-        for (int l = 0; l < k; ++l) {
-            double2 t = cmul(T[(k + i) + (size_t)l * m], Wm[l + (size_t)c * m]);
-            acc = csub(acc, t);
-        }
-        Wm[(k + i) + (size_t)c * m] = acc;
+        const int i = e % r, c = e / r;
+        const double2 q = Q[c + (size_t)(k + i) * m];
+        Wm[(k + i) + (size_t)c * m] = zc(q.x, -q.y);
     }
 }
 
@@ -977,6 +959,27 @@ static fio_status factor_impl(hss_s *h, hipStream_t s, hss_ulv_t *out) {
             }
             k_ulv_node<1><<<nn, ulv_threads(mlev), 0, s>>>(fa);
             FIO_HIP(hipGetLastError());
+            {
+                // Dhat22 = Dchk22 - X^* X and W2 = Q2^* - X^* W1 for every node of the level, with
+                // X = Dhat21^* (k x r) left in T(0..k, k..m) by the node kernel
+                ZgemmBatch g3, g4;
+                double2 *sc = scr.as<double2>();
+                double2 *W = f->W.as<double2>();
+                double2 *D22b = fa.D22;
+                for (int j = 0; j < nn; ++j) {
+                    const int m = f->m[l][j], r = f->r[l][j], k = m - r;
+                    if (m == 0 || r == 0 || k == 0) continue;
+                    double2 *T = sc + scoff[j] + 2 * (size_t)m * m;
+                    const double2 *X = T + (size_t)k * m;
+                    g3.add(X, m, X, m, D22b + soff[j], r, r, r, k);
+                    g4.add(X, m, W + f->woff[l][j], m, W + f->woff[l][j] + k, m, r, m, k);
+                }
+                g3.upload(s);
+                g4.upload(s);
+                g3.run(true, zc(-1.0, 0.0), zc(1.0, 0.0), s);
+                g4.run(true, zc(-1.0, 0.0), zc(1.0, 0.0), s);
+                FIO_HIP(hipStreamSynchronize(s));   // the descriptor lists are released here
+            }
             // merge into level l-1
             const int np = h->nodes(l - 1);
             std::vector<size_t> dooff(np), uooff(np), toff(np), upoff(np, 0);
