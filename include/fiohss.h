@@ -231,11 +231,11 @@ fio_status fio_permute2d(long n, int to_internal, const void *X, long ldx, void 
  * thread-safe with respect to concurrent applies. */
 void fio_set_fused(int on);
 
-/* With fused passes on: on != 0 (default) folds the leaf factor V^[L'] of a forward apply
- * into its first pass of transfer factors when that pass holds 3 levels (FP64 and FP32
- * structured factors, 2^L' >= 64; the pass then reads the input vectors instead of the leaf
- * coefficients); on == 0 runs the leaf factor as its own kernel.  Both give bitwise identical
- * results.  Not thread-safe with respect to concurrent applies. */
+/* With fused passes on: on != 0 (default) folds the first leaf factor of an apply (V^[L']
+ * forward, U^[L']* adjoint) into its first pass of transfer factors when that pass holds 3
+ * levels (FP64 and FP32 structured factors, 2^L' >= 64; the pass then reads the input vectors
+ * instead of the leaf coefficients); on == 0 runs the leaf factor as its own kernel.  Both give
+ * bitwise identical results.  Not thread-safe with respect to concurrent applies. */
 void fio_set_leaf_fused(int on);
 
 /* Selects how the HSS construction (hss_build_from_samples, fio_hss_build) runs the node

@@ -431,7 +431,8 @@ template <typename T, int Q> struct StructArgs {
     cpx<T> *out;
     int nrhs;
     int cside;               // 1: C factors (P transposed, child index c_in)
-    const cpx<T> *V;         // LEAF: the leaf factor V^[L'] (blocks V[sigma][tau], q x 8)
+    const cpx<T> *V;         // LEAF: the leaf factor, V^[L'] forward (blocks V[sigma][tau], q x 8),
+                             // U^[L'] adjoint (blocks U[tau][sigma], 8 x q)
     const double2 *X;        // LEAF: the input block (column-major, leading dimension ldx)
     long ldx;
     T P[2][Q][Q];            // P_c(i, t)
@@ -440,13 +441,14 @@ template <typename T, int Q> struct StructArgs {
 
 // Register budget: single precision keeps 8 waves per SIMD (four 37 KB workgroups per CU at
 // KL = 3, <= 64 VGPRs), double precision 4 (two 74 KB workgroups, LDS-bound anyway).
-// LEAF (forward first C pass, 3 levels): the pass also applies the leaf factor V^[L'], reading
-// the input vectors instead of the leaf coefficients (see the load phase).
+// LEAF (first pass of 3 levels: forward C side or adjoint B side): the pass also applies the
+// leaf factor (V^[L'] forward, U^[L']* adjoint), reading the input vectors instead of the leaf
+// coefficients (see the load phase).
 template <typename T, int Q, int KL, bool ADJ, bool EPI_M, bool CS, bool LEAF = false>
 __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_struct_fused(StructArgs<T, Q> a) {
     using C = cpx<T>;
     constexpr int P = 1 << KL, NG = P / 2;
-    static_assert(!LEAF || (!ADJ && CS && KL == 3), "the leaf factor folds into a forward 3-level C pass");
+    static_assert(!LEAF || (KL == 3 && CS != ADJ), "the leaf factor folds into a first 3-level pass");
     // double precision: the twiddles of the current factor's NG groups, fetched into registers
     // during the previous factor (vector loads) and read back from LDS as broadcasts; single
     // precision reads them through the scalar cache (its register budget has no room)
@@ -462,12 +464,18 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_stru
     const long nS = (2 * a.G0) >> KL;
     long A, S;
     if constexpr (LEAF) {
-        // the 8 workgroups that read the same 64 input rows (one per coarse partner A) are
-        // dispatched one after another on one XCD (workgroups go round-robin over the 8 XCDs),
-        // so the rows come from HBM once and from that XCD's L2 after; needs nS % 8 == 0
+        // the 8 workgroups that read the same 64 input rows (one per coarse partner: A forward,
+        // S adjoint) are dispatched one after another on one XCD (workgroups go round-robin over
+        // the 8 XCDs), so the rows come from HBM once and from that XCD's L2 after; needs
+        // nS % 8 == 0 forward, nS == 8 and 8 | (number of A) adjoint
         const long b = blockIdx.x, k = b >> 3;
-        A = k & 7;
-        S = ((k >> 3) << 3) | (b & 7);
+        if constexpr (!ADJ) {
+            A = k & 7;
+            S = ((k >> 3) << 3) | (b & 7);
+        } else {
+            S = k & 7;
+            A = ((k >> 3) << 3) | (b & 7);
+        }
     } else {
         A = blockIdx.x / nS;
         S = blockIdx.x % nS;
@@ -487,17 +495,19 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_stru
     C mpf[NMP];
     if (TWL && tid < NTW) stw[tid] = tw_src(ADJ ? KL - 1 : 0, tid);
     if constexpr (LEAF) {
-        // The input pairs are (coarse partner A, leaf boxes 8S .. 8S + 7): pair A 2^L' + box holds
-        // V[box][A] applied to rows 8 box .. 8 box + 7 of the input.  The workgroup stages rows
-        // 64S .. 64S + 63 of its 64 columns in the tile (lanes along rows, coalesced), each wave
-        // takes its box's 8 rows for its lane's column, and after a barrier writes the pair's q
-        // coefficients where the load would have put them.  Same operations, in the same order,
-        // as the leaf kernel followed by the load.
+        // Forward, the input pairs are (coarse partner A, leaf boxes 8S .. 8S + 7): pair
+        // A 2^L' + box holds V[box][A] applied to rows 8 box .. 8 box + 7 of the input.  Adjoint,
+        // they are (leaf boxes 8A .. 8A + 7, coarse partner S): pair 8 box + S holds U[box][S]^*
+        // applied to the same rows.  The workgroup stages its 64 rows of its 64 columns in the
+        // tile (lanes along rows, coalesced), each wave takes its box's 8 rows for its lane's
+        // column, and after a barrier writes the pair's q coefficients where the load would have
+        // put them.  Same operations, in the same order, as the leaf kernel followed by the load.
         constexpr int XP = 65;                                   // padded column stride of the staged rows
         static_assert(64 * XP <= P * Q * 64, "the staged rows fit the tile");
         const int cb = blockIdx.y * 64;
         const int ncol = a.nrhs - cb < 64 ? a.nrhs - cb : 64;
-        const double2 *xs = a.X + (size_t)S * (P * kLeafPts);
+        const long box0 = ADJ ? A * P : S * P;                   // first leaf box of the workgroup
+        const double2 *xs = a.X + (size_t)box0 * kLeafPts;
         for (int e = tid; e < 64 * 64; e += P * 64) {
             const int r = e & 63, cc = e >> 6;
             const double2 v = cc < ncol ? xs[r + (size_t)(cb + cc) * a.ldx] : zc(0.0, 0.0);
@@ -508,13 +518,19 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_stru
 #pragma unroll
         for (int t = 0; t < kLeafPts; ++t) x[t] = lds[lane * XP + wave * kLeafPts + t];
         __syncthreads();
-        const long box = S * P + wave;
-        const C *blk = a.V + ((size_t)box * kLeafPts + A) * (Q * kLeafPts);   // nsl = 8 partners
+        const long box = box0 + wave;
+        const long partner = ADJ ? S : A;
+        const C *blk = a.V + ((size_t)box * kLeafPts + partner) * (Q * kLeafPts);   // nsl = 8 partners
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             C acc = czero<C>();
 #pragma unroll
-            for (int t = 0; t < kLeafPts; ++t) cfma(acc, blk[i * kLeafPts + t], x[t]);
+            for (int t = 0; t < kLeafPts; ++t) {
+                if constexpr (ADJ)
+                    cfmac(acc, blk[t * Q + i], x[t]);
+                else
+                    cfma(acc, blk[i * kLeafPts + t], x[t]);
+            }
             lds[(wave * Q + i) * 64 + lane] = acc;
         }
     } else {
@@ -666,15 +682,22 @@ static void launch_struct(const StructArgs<T, Q> &sa, bool adj, bool epi, long N
 // 64 columns) can hold the 64 staged input rows of its 64 columns.
 template <typename T, int Q> constexpr bool leaf_foldable() { return fused_max_kl<T, Q>() >= 3 && 8 * Q >= 65; }
 
-// The forward first C pass of 3 levels with the leaf factor folded in (k_struct_fused, LEAF).
+// The first pass of 3 levels with the leaf factor folded in (k_struct_fused, LEAF): forward
+// C side or adjoint B side.
 template <typename T, int Q>
-static void run_struct_leaf(const StructArgs<T, Q> &sa, bool epi, long N, hipStream_t s) {
+static void run_struct_leaf(const StructArgs<T, Q> &sa, bool adj, bool epi, long N, hipStream_t s) {
     if constexpr (leaf_foldable<T, Q>()) {
         const dim3 grid((unsigned)(N >> 3), (unsigned)((sa.nrhs + 63) / 64)), block(8 * 64);
-        if (epi)
+        if (adj) {
+            if (epi)
+                k_struct_fused<T, Q, 3, true, true, false, true><<<grid, block, 0, s>>>(sa);
+            else
+                k_struct_fused<T, Q, 3, true, false, false, true><<<grid, block, 0, s>>>(sa);
+        } else if (epi) {
             k_struct_fused<T, Q, 3, false, true, true, true><<<grid, block, 0, s>>>(sa);
-        else
+        } else {
             k_struct_fused<T, Q, 3, false, false, true, true><<<grid, block, 0, s>>>(sa);
+        }
     } else {
         throw Err{FIO_ERR_UNSUPPORTED};
     }
@@ -903,7 +926,7 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
                 sa.out = nxt;
                 sa.nrhs = nrhs;
                 sa.cside = cside ? 1 : 0;
-                sa.V = F + bf->offV;
+                sa.V = F + (a ? bf->offU : bf->offV);
                 sa.X = X;
                 sa.ldx = ldx;
                 for (int c = 0; c < 2; ++c)
@@ -914,7 +937,7 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
                         }
                 if (leaf) {
                     FIO_TIMED(f64 ? "bf_struct_leaf_f64" : "bf_struct_leaf_f32", s);
-                    run_struct_leaf<T, Q>(sa, epi, bf->N, s);
+                    run_struct_leaf<T, Q>(sa, a, epi, bf->N, s);
                 } else {
                     FIO_TIMED(f64 ? "bf_struct_f64" : "bf_struct_f32", s);
                     run_struct<T, Q>(sa, kl, a, epi, bf->N, s);
@@ -994,7 +1017,10 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
             k_leaf_out_fwd<T, Q><<<grid1d(((size_t)1 << bf->Lp) * nrhs, TB), TB, 0, s>>>(g, F + bf->offU, cur, Y,
                                                                                            ldy, nrhs, Ysub, ldsub);
     } else {
-        {
+        // U^[L']* folds into the first B* pass under the same conditions as V^[L'] forward
+        const bool leaf_fused = leaf_foldable<T, Q>() && fused && bf->structured && !split &&
+                                !leaf_fused_disabled() && (kmax < bf->nl ? kmax : bf->nl) == 3 && bf->Lp >= 6;
+        if (!leaf_fused) {
             FIO_TIMED(f64 ? "bf_leaf_in_f64" : "bf_leaf_in_f32", s);
             if (tiled)
                 k_leaf_io<T, Q, true, false><<<tgrid, 256, 0, s>>>(g, F + bf->offU, X, ldx, nullptr, cur, nullptr, 0,
@@ -1006,7 +1032,7 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
             // B^[L']* .. B^[h+1]* in passes from the top; the last pass also applies M*
             for (int hi = bf->nl; hi > 0;) {
                 const int lo = hi - kmax > 0 ? hi - kmax : 0;
-                pass(true, false, lo, hi, lo == 0);
+                pass(true, false, lo, hi, lo == 0, leaf_fused && hi == bf->nl);
                 hi = lo;
             }
             for (int lo = 0; lo < bf->nl;) {

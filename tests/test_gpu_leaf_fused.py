@@ -1,5 +1,6 @@
-"""The forward apply with the leaf factor V^[L'] folded into its first 3-level pass against
-the same apply with the leaf factor as its own kernel (bitwise), and against the oracle."""
+"""The applies with the leaf factor (V^[L'] forward, U^[L']* adjoint) folded into their first
+3-level pass against the same applies with the leaf factor as its own kernel (bitwise), and
+against the oracle."""
 import numpy as np
 import pytest
 
@@ -31,12 +32,13 @@ def test_leaf_folded_pass_is_bitwise_equal_to_the_leaf_kernel(n, k):
     x = fi.complex_gaussian(61, fi.PURPOSE_PROBE, n, k)
     try:
         for prec in (F.FIO_PREC_FP64, F.FIO_PREC_FP32):
-            F.set_leaf_fused(False)
-            y0 = forward(F, B, x, prec)
-            F.set_leaf_fused(True)
-            y1 = forward(F, B, x, prec)
-            assert np.array_equal(y0, y1)
-            assert np.all(np.isfinite(y1))
+            for fn in (B.apply, B.apply_adj):
+                F.set_leaf_fused(False)
+                y0 = host(fn(dev(x), prec=prec))
+                F.set_leaf_fused(True)
+                y1 = host(fn(dev(x), prec=prec))
+                assert np.array_equal(y0, y1)
+                assert np.all(np.isfinite(y1))
     finally:
         F.set_leaf_fused(True)
 
@@ -50,9 +52,11 @@ def test_leaf_folded_pass_matches_oracle(n):
     B = gpu_bf(F, n, 9, "sin16", imported=False, precs=(F.FIO_PREC_FP64, F.FIO_PREC_FP32))
     ob = oracle_bf(n, 9, "sin16")
     x = fi.complex_gaussian(62, fi.PURPOSE_PROBE, n, 70)
-    ref = ob.apply(x)
+    ref, refa = ob.apply(x), ob.apply_adj(x)
     assert rel(forward(F, B, x, F.FIO_PREC_FP64), ref) < 20 * entry_tol(n)
     assert rel(forward(F, B, x, F.FIO_PREC_FP32), ref) < 2e-5
+    assert rel(host(B.apply_adj(dev(x))), refa) < 20 * entry_tol(n)
+    assert rel(host(B.apply_adj(dev(x), prec=F.FIO_PREC_FP32)), refa) < 2e-5
 
 
 def test_other_pass_splits_keep_the_leaf_kernel():
