@@ -897,7 +897,10 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
         if constexpr (fused_q<Q>()) {
             const int kl = hi - lo;
             if constexpr (std::is_same<T, float>::value && Q == 9) {
-                if (split) {
+                // split FP16 runs every pass on the matrix cores except a first pass with the
+                // leaf factor folded in, which runs as the FP32 structured pass (same coefficient
+                // layout, more precise; saves the separate leaf kernel)
+                if (split && !leaf) {
                     SplitPass sp;
                     for (int jj = 0; jj < 3; ++jj) sp.A[jj] = nullptr;
                     for (int jj = 0; jj < kl; ++jj)
@@ -982,7 +985,7 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
     if (!adj) {
         // V^[L'] folds into the first C pass when that pass is a structured one of 3 levels (one
         // leaf box per wave) and its workgroups can be grouped by 8 per XCD (2^L' / 8 % 8 == 0)
-        const bool leaf_fused = leaf_foldable<T, Q>() && fused && bf->structured && !split &&
+        const bool leaf_fused = leaf_foldable<T, Q>() && fused && bf->structured &&
                                 !leaf_fused_disabled() && (kmax < bf->nl ? kmax : bf->nl) == 3 && bf->Lp >= 6;
         if (!leaf_fused) {
             FIO_TIMED(f64 ? "bf_leaf_in_f64" : "bf_leaf_in_f32", s);
@@ -1018,7 +1021,7 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
                                                                                            ldy, nrhs, Ysub, ldsub);
     } else {
         // U^[L']* folds into the first B* pass under the same conditions as V^[L'] forward
-        const bool leaf_fused = leaf_foldable<T, Q>() && fused && bf->structured && !split &&
+        const bool leaf_fused = leaf_foldable<T, Q>() && fused && bf->structured &&
                                 !leaf_fused_disabled() && (kmax < bf->nl ? kmax : bf->nl) == 3 && bf->Lp >= 6;
         if (!leaf_fused) {
             FIO_TIMED(f64 ? "bf_leaf_in_f64" : "bf_leaf_in_f32", s);

@@ -74,3 +74,25 @@ def test_other_pass_splits_keep_the_leaf_kernel():
             assert np.array_equal(forward(F, B, x, F.FIO_PREC_FP64), ref)
     finally:
         B.set_tile(64, F.FIO_PREC_FP64, False, 0, 0, 0)
+
+
+@pytest.mark.parametrize("n,k", [(4096, 64), (1 << 14, 37), (1 << 16, 64)])
+def test_split_path_with_folded_first_pass(n, k):
+    """Split FP16: with the fold the first pass runs as the FP32 structured pass (leaf factor
+    included), the others on the matrix cores; both forms stay within the split tolerance of
+    the FP64 apply (per column, 2e-5) in both directions."""
+    F = fiohss()
+    step("split with folded first pass n=%d k=%d" % (n, k))
+    B = gpu_bf(F, n, 9, "sin16", imported=False,
+               precs=(F.FIO_PREC_FP64, F.FIO_PREC_FP32, F.FIO_PREC_SPLIT_FP16))
+    x = fi.complex_gaussian(64, fi.PURPOSE_PROBE, n, k)
+    try:
+        for fn in (B.apply, B.apply_adj):
+            ref = host(fn(dev(x)))
+            for on in (True, False):
+                F.set_leaf_fused(on)
+                y = host(fn(dev(x), prec=F.FIO_PREC_SPLIT_FP16))
+                err = np.linalg.norm(y - ref, axis=0) / np.linalg.norm(ref, axis=0)
+                assert err.max() < 2e-5 and err.max() > 1e-9
+    finally:
+        F.set_leaf_fused(True)
