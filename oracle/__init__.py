@@ -9,6 +9,7 @@ Every function follows the paper's definitions and algorithm steps in the
 paper's order, in plain numpy/scipy complex128, with no blocking, fusion or
 reordering beyond the definitions:
 
+  dd.py           double-double arithmetic (Knuth, Dekker) for phases modulo 1
   fio.py          grids, phase, kernel and dense K            (Section 1, eq. fio / fio_mat)
   cheb.py         Chebyshev grids and Lagrange bases          (Section 2.2)
   bf.py           explicit butterfly factors and their apply  (Section 2.2, eq. bf, bf_mid, bf_recursive)

@@ -38,14 +38,16 @@ the next; in the pair numbering above the inputs are 2 sigma + c_in inside the
 alpha-th run of 2G pairs and the outputs are sigma + c_out G of the same run,
 with G the number of sigma per alpha.
 
-Entries are evaluated naively from Phi in FP64 (no phase-difference
-rewriting): the oracle's own rounding error in an entry is about
-2 pi eps |Phi| <= 2 pi eps (1 + max c) N / 2.
+Entries are evaluated from their definitions with the phases formed exactly
+modulo 1 (fio.phase_frac) and the Lagrange values in reference coordinates
+(cheb.lagrange_ref), so an entry carries only a few roundings of O(1)
+quantities whatever N is (pinned against 30-digit evaluations of the
+definitions).
 """
 import numpy as np
 
-from . import cheb
-from .fio import phase, kernel, spatial_grid, frequency_grid
+from . import cheb, dd
+from .fio import phase_frac, expi2pi, kernel, spatial_grid, frequency_grid
 
 
 class BF1D:
@@ -54,7 +56,7 @@ class BF1D:
     phase (Section 2.2 interpolates the residual phase factor); the amplitude enters through
     the kernel values of the middle factor, M = k(Z, Gamma) (eq. bf_kernel_func_low_rank)."""
 
-    def __init__(self, n, q, params, level_offset=3, amp=None):
+    def __init__(self, n, q, params, level_offset=3, amp=None, build=True):
         L = int(round(np.log2(n)))
         if 2 ** L != n or L % 2 != 0 or L < 2:
             raise ValueError("N must be 2^L with L even")
@@ -63,120 +65,118 @@ class BF1D:
         self.Lp = max(L - level_offset, self.h)
         self.b = n >> self.Lp                     # points per leaf box
         self.nl = self.Lp - self.h                # number of B (and C) factors
-        self._build()
+        if build:                                 # build=False: make_* give single factors
+            self._build()
 
     # --- geometry -------------------------------------------------------
-    def sbox(self, level, j):
-        w = 2.0 ** (-level)
-        return j * w, w
-
-    def fbox(self, level, j):
-        w = self.N * 2.0 ** (-level)
-        return -self.N / 2 + j * w, w
-
-    def s_center(self, level, j):
-        a, w = self.sbox(level, j)
-        return a + 0.5 * w
-
-    def f_center(self, level, j):
-        a, w = self.fbox(level, j)
-        return a + 0.5 * w
-
-    def s_cheb(self, level, j):
-        a, w = self.sbox(level, j)
-        return cheb.cheb_points(a, w, self.q)
-
-    def f_cheb(self, level, j):
-        a, w = self.fbox(level, j)
-        return cheb.cheb_points(a, w, self.q)
-
-    # --- factor construction (Section 2.2) ---------------------------------
-    # Each entry is evaluated from its definition; numpy broadcasting runs over
-    # all boxes of a level at once.
-    def _s_cheb_all(self, level):
-        """Chebyshev points of every spatial box at ``level``: (2^level, q)."""
-        w = 2.0 ** (-level)
-        a = np.arange(2 ** level) * w
-        return cheb.cheb_points(a[:, None], w, self.q)
-
-    def _f_cheb_all(self, level):
-        w = self.N * 2.0 ** (-level)
-        a = -self.N / 2 + np.arange(2 ** level) * w
-        return cheb.cheb_points(a[:, None], w, self.q)
-
+    # Centers are exact binary fractions (spatial) or multiples of 1/2 (frequency); a
+    # Chebyshev point is center + (w/2) t_i, carried as a double-double pair (cheb.py).
     def _s_center_all(self, level):
-        w = 2.0 ** (-level)
-        return (np.arange(2 ** level) + 0.5) * w
+        return (np.arange(2 ** level) + 0.5) * 2.0 ** (-level)
 
     def _f_center_all(self, level):
         w = self.N * 2.0 ** (-level)
         return -self.N / 2 + (np.arange(2 ** level) + 0.5) * w
 
+    def _s_cheb_all(self, level):
+        """Chebyshev points of every spatial box at ``level``: double-double (2^level, q)."""
+        return cheb.box_points_dd(self._s_center_all(level), 2.0 ** (-level - 1), self.q)
+
+    def _f_cheb_all(self, level):
+        return cheb.box_points_dd(self._f_center_all(level), self.N * 2.0 ** (-level - 1), self.q)
+
+    def s_cheb(self, level, j):
+        """Chebyshev points of spatial box j at ``level``, rounded to float64."""
+        return dd.to_float(self._s_cheb_all(level))[j]
+
+    def f_cheb(self, level, j):
+        return dd.to_float(self._f_cheb_all(level))[j]
+
+    # --- factor construction (Section 2.2) ---------------------------------
+    # Each entry is its definition: exp(2 pi i (Phi(p1, xi) - Phi(p2, xi))) times a Lagrange
+    # value.  The exponential is exp(2 pi i Phi(p1, xi)) * conj(exp(2 pi i Phi(p2, xi))), each
+    # from fio.phase_frac on exact points (so that the phase, which grows like N, carries no
+    # rounding of its integer part), and the Lagrange value p_t(x) is taken in the reference
+    # coordinate of x in the interpolating box, where it is the same for every box
+    # (cheb.child_lagrange, cheb.leaf_lagrange).  numpy broadcasting runs over all boxes.
+    def _E(self, x, xi):
+        return expi2pi(phase_frac(x, xi, self.params))
+
+    def make_V(self):
+        """V[sigma, tau, j, s] for sigma a frequency leaf (level L'), tau at spatial level L - L'."""
+        N, L, Lp, q, b = self.N, self.L, self.Lp, self.q, self.b
+        xis = frequency_grid(N).reshape(2 ** Lp, b)                 # (sigma, s), exact integers
+        gam = self._f_cheb_all(Lp)                                  # (sigma, j)
+        y = self._s_center_all(L - Lp)                              # (tau,)
+        E1 = self._E(y[None, :, None], xis[:, None, :])             # (sigma, tau, s)
+        E2 = self._E(y[None, :, None], (gam[0][:, None, :], gam[1][:, None, :]))   # (sigma, tau, j)
+        Q = cheb.leaf_lagrange(b, q)                                # (s, j) = q_sigma,j(xi_s)
+        return E1[:, :, None, :] * np.conj(E2)[:, :, :, None] * Q.T[None, None, :, :]
+
+    def make_C(self, lev):
+        """C^[h+1+lev] as (groups, 2q, 2q), group g = alpha 2^l + sigma (l = h + lev)."""
+        N, L, h, q = self.N, self.L, self.h, self.q
+        l = h + lev
+        G, nalpha = 2 ** l, 2 ** (L - l - 1)
+        y = self._s_center_all(L - l)                               # (tau,), tau = 2 alpha + c_out
+        gb = self._f_cheb_all(l + 1)                                # (beta, t), beta = 2 sigma + c_in
+        gs = self._f_cheb_all(l)                                    # (sigma, j)
+        E1 = self._E(y[:, None, None], (gb[0][None], gb[1][None]))  # (tau, beta, t)
+        E2 = self._E(y[:, None, None], (gs[0][None], gs[1][None]))  # (tau, sigma, j)
+        E1 = E1.reshape(nalpha, 2, G, 2, q)                         # (alpha, c_out, sigma, c_in, t)
+        E2 = E2.reshape(nalpha, 2, G, q)                            # (alpha, c_out, sigma, j)
+        P = cheb.child_lagrange(q)                                  # (c_in, t, j) = q_sigma,j(gamma_beta,t)
+        # A[alpha, sigma, c_out, j, c_in, t]
+        A = (E1.transpose(0, 2, 1, 3, 4)[:, :, :, None, :, :]
+             * np.conj(E2).transpose(0, 2, 1, 3)[:, :, :, :, None, None]
+             * P.transpose(2, 0, 1)[None, None, None, :, :, :])
+        return A.reshape(nalpha * G, 2 * q, 2 * q)
+
+    def make_M(self):
+        """M[p, i, j] = k(z_tau,i, gamma_sigma,j), p = tau 2^h + sigma (both at level h)."""
+        N, h, q = self.N, self.h, self.q
+        z = self._s_cheb_all(h)                                     # (tau, i)
+        g = self._f_cheb_all(h)                                     # (sigma, j)
+        Z = (z[0][:, None, :, None], z[1][:, None, :, None])
+        Gm = (g[0][None, :, None, :], g[1][None, :, None, :])
+        return kernel(Z, Gm, self.params, self.amp).reshape(N, q, q)
+
+    def make_B(self, lev):
+        """B^[h+1+lev] as (groups, 2q, 2q), group g = alpha 2^(L-l-1) + sigma (l = h + lev)."""
+        N, L, h, q = self.N, self.L, self.h, self.q
+        l = h + lev
+        G, nalpha = 2 ** (L - l - 1), 2 ** l
+        zt = self._s_cheb_all(l + 1)                                # (tau, i), tau = 2 alpha + c_out
+        za = self._s_cheb_all(l)                                    # (alpha, t)
+        eta = self._f_center_all(L - l)                             # (beta,), beta = 2 sigma + c_in
+        E1 = self._E((zt[0][:, :, None], zt[1][:, :, None]), eta[None, None, :])   # (tau, i, beta)
+        E2 = self._E((za[0][:, :, None], za[1][:, :, None]), eta[None, None, :])   # (alpha, t, beta)
+        E1 = E1.reshape(nalpha, 2, q, G, 2)                         # (alpha, c_out, i, sigma, c_in)
+        E2 = E2.reshape(nalpha, q, G, 2)                            # (alpha, t, sigma, c_in)
+        P = cheb.child_lagrange(q)                                  # (c_out, i, t) = p_alpha,t(z_tau,i)
+        # A[alpha, sigma, c_out, i, c_in, t]
+        A = (E1.transpose(0, 3, 1, 2, 4)[:, :, :, :, :, None]
+             * np.conj(E2).transpose(0, 2, 3, 1)[:, :, None, None, :, :]
+             * P[None, None, :, :, None, :])
+        return A.reshape(nalpha * G, 2 * q, 2 * q)
+
+    def make_U(self):
+        """U[tau, sigma, s, i] for tau a spatial leaf (level L'), sigma at frequency level L - L'."""
+        N, L, Lp, q, b = self.N, self.L, self.Lp, self.q, self.b
+        xs = spatial_grid(N).reshape(2 ** Lp, b)                    # (tau, s), exact i/N
+        z = self._s_cheb_all(Lp)                                    # (tau, i)
+        eta = self._f_center_all(L - Lp)                            # (sigma,)
+        E1 = self._E(xs[:, None, :], eta[None, :, None])            # (tau, sigma, s)
+        E2 = self._E((z[0][:, None, :], z[1][:, None, :]), eta[None, :, None])     # (tau, sigma, i)
+        Pm = cheb.leaf_lagrange(b, q)                               # (s, i) = p_tau,i(x_s)
+        return E1[:, :, :, None] * np.conj(E2)[:, :, None, :] * Pm[None, None, :, :]
+
     def _build(self):
-        N, L, h, Lp, q, b, P = self.N, self.L, self.h, self.Lp, self.q, self.b, self.params
-        xg, fg = spatial_grid(N), frequency_grid(N)
-        nsl = 2 ** (L - Lp)                      # boxes on the coarse side of the leaf level
-        e2pi = lambda ph: np.exp(2j * np.pi * ph)
-
-        # V: frequency leaves sigma (level L') x spatial boxes tau (level L - L')
-        xis = fg.reshape(2 ** Lp, b)                              # (sigma, s)
-        gam = self._f_cheb_all(Lp)                                # (sigma, j)
-        Q = cheb.lagrange_values(gam, xis)                        # (sigma, s, j) = q_sigma,j(xi_s)
-        y = self._s_center_all(L - Lp)                            # (tau,)
-        ph = (phase(y[None, :, None, None], xis[:, None, None, :], P)
-              - phase(y[None, :, None, None], gam[:, None, :, None], P))   # (sigma, tau, j, s)
-        self.V = e2pi(ph) * Q.transpose(0, 2, 1)[:, None, :, :]
-
-        # C^[l+1], l = h..L'-1
-        self.C = []
-        for lev in range(self.nl):
-            l = h + lev
-            G = 2 ** l
-            nalpha = 2 ** (L - l - 1)
-            gs = self._f_cheb_all(l)                              # (sigma, j)
-            gb = self._f_cheb_all(l + 1).reshape(G, 2, q)         # (sigma, c_in, t)
-            Qv = cheb.lagrange_values(gs[:, None, :].repeat(2, 1).reshape(2 * G, q),
-                                      gb.reshape(2 * G, q)).reshape(G, 2, q, q)  # (sigma, c_in, t, j)
-            yt = self._s_center_all(L - l).reshape(nalpha, 2)     # (alpha, c_out)
-            # ph[alpha, sigma, c_out, j, c_in, t]
-            Y = yt[:, None, :, None, None, None]
-            ph = (phase(Y, gb[None, :, None, None, :, :], P)
-                  - phase(Y, gs[None, :, None, :, None, None], P))
-            Qf = Qv.transpose(0, 3, 1, 2)[None, :, None, :, :, :]   # (1, sigma, 1, j, c_in, t)
-            A = e2pi(ph) * Qf
-            self.C.append(A.reshape(nalpha * G, 2 * q, 2 * q))
-
-        # M at the middle level h
-        z = self._s_cheb_all(h)                                   # (tau, i)
-        g = self._f_cheb_all(h)                                   # (sigma, j)
-        self.M = kernel(z[:, None, :, None], g[None, :, None, :], P, self.amp).reshape(N, q, q)
-
-        # B^[l+1], l = h..L'-1
-        self.B = []
-        for lev in range(self.nl):
-            l = h + lev
-            G = 2 ** (L - l - 1)
-            nalpha = 2 ** l
-            za = self._s_cheb_all(l)                              # (alpha, t)
-            zt = self._s_cheb_all(l + 1).reshape(nalpha, 2, q)    # (alpha, c_out, i)
-            Pv = cheb.lagrange_values(za[:, None, :].repeat(2, 1).reshape(2 * nalpha, q),
-                                      zt.reshape(2 * nalpha, q)).reshape(nalpha, 2, q, q)  # (alpha, c_out, i, t)
-            eta = self._f_center_all(L - l).reshape(G, 2)          # (sigma, c_in)
-            # ph[alpha, sigma, c_out, i, c_in, t]
-            E = eta[None, :, None, None, :, None]
-            ph = (phase(zt[:, None, :, :, None, None], E, P)
-                  - phase(za[:, None, None, None, None, :], E, P))
-            A = e2pi(ph) * Pv[:, None, :, :, None, :]
-            self.B.append(A.reshape(nalpha * G, 2 * q, 2 * q))
-
-        # U: spatial leaves tau (level L') x frequency boxes sigma (level L - L')
-        xs = xg.reshape(2 ** Lp, b)                               # (tau, s)
-        z = self._s_cheb_all(Lp)                                  # (tau, i)
-        Pm = cheb.lagrange_values(z, xs)                          # (tau, s, i)
-        eta = self._f_center_all(L - Lp)                          # (sigma,)
-        ph = (phase(xs[:, None, :, None], eta[None, :, None, None], P)
-              - phase(z[:, None, None, :], eta[None, :, None, None], P))   # (tau, sigma, s, i)
-        self.U = e2pi(ph) * Pm[:, None, :, :]
+        self.V = self.make_V()
+        self.C = [self.make_C(lev) for lev in range(self.nl)]
+        self.M = self.make_M()
+        self.B = [self.make_B(lev) for lev in range(self.nl)]
+        self.U = self.make_U()
 
     # --- apply (eq. bf) ------------------------------------------------------
     @staticmethod

@@ -31,7 +31,13 @@ column-major blocks, see the header of the C interface).
 import numpy as np
 
 from . import cheb
-from .fio2d import phase, kernel, morton_code, morton_decode
+from .fio import expi2pi
+from .fio2d import phase_frac, kernel, morton_code, morton_decode
+
+
+def _pick(a, idx):
+    """Index both halves of a double-double pair."""
+    return a[0][idx], a[1][idx]
 
 
 class BF2D:
@@ -50,13 +56,13 @@ class BF2D:
         self.r = 2 ** (self.h - self.lc)      # frequency children of a level-lc box per dimension
 
     # --- geometry --------------------------------------------------------------
+    # Centers are exact; Chebyshev points are double-double pairs (cheb.box_points_dd).
     def _s_cheb(self, level):
-        w = 2.0 ** (-level)
-        return cheb.cheb_points((np.arange(2 ** level) * w)[:, None], w, self.q)       # (box, q)
+        """Chebyshev points of every box at ``level`` along one dimension: double-double (box, q)."""
+        return cheb.box_points_dd(self._s_center(level), 2.0 ** (-level - 1), self.q)
 
     def _f_cheb(self, level):
-        w = self.n * 2.0 ** (-level)
-        return cheb.cheb_points((-self.n / 2 + np.arange(2 ** level) * w)[:, None], w, self.q)
+        return cheb.box_points_dd(self._f_center(level), self.n * 2.0 ** (-level - 1), self.q)
 
     def _s_center(self, level):
         return (np.arange(2 ** level) + 0.5) * 2.0 ** (-level)
@@ -73,64 +79,77 @@ class BF2D:
         return (np.arange(self.n) / self.n).reshape(2 ** self.h, self.b)
 
     # --- factor blocks ------------------------------------------------------------
+    # As in 1D (bf.py): exp(2 pi i (Phi(p1, xi) - Phi(p2, xi))) is the product of the two
+    # exponentials from fio2d.phase_frac on exact points, and the tensor-product Lagrange
+    # values are taken in reference coordinates (the leaf grid's u = (a - b/2) / (b/2)).
+    def _E(self, x1, x2, k1, k2):
+        return expi2pi(phase_frac(x1, x2, k1, k2, self.params))
+
     def V_blocks(self, t1, t2):
         """V_{tau',sigma} for tau' = (t1, t2) at level lc and every sigma at level h:
         array [s1, s2, i1, i2, a1, a2] (a = frequency offset inside sigma)."""
-        P = self.params
         y = self._s_center(self.lc)
         y1, y2 = y[t1], y[t2]
         g = self._f_cheb(self.h)                       # (s, i)
         xi = self._leaf_freqs()                        # (s, a)
-        Q = cheb.lagrange_values(g, xi)                # (s, a, i) = q_i(xi_a)
-        S = g.shape[0]
-        # phase at the frequencies and at the Chebyshev points of sigma
-        ph_xi = phase(y1, y2, xi[:, None, :, None], xi[None, :, None, :], P)        # (s1, s2, a1, a2)
-        ph_g = phase(y1, y2, g[:, None, :, None], g[None, :, None, :], P)           # (s1, s2, i1, i2)
-        lag = Q.transpose(0, 2, 1)[:, None, :, None, :, None] * Q.transpose(0, 2, 1)[None, :, None, :, None, :]
-        return (np.exp(2j * np.pi * (ph_xi[:, :, None, None, :, :] - ph_g[:, :, :, :, None, None]))
-                * lag.reshape(S, S, self.q, self.q, self.b, self.b))
+        Q = cheb.leaf_lagrange(self.b, self.q)         # (a, i) = q_i(xi_a)
+        E_xi = self._E(y1, y2, xi[:, None, :, None], xi[None, :, None, :])            # (s1, s2, a1, a2)
+        E_g = self._E(y1, y2, _pick(g, np.s_[:, None, :, None]), _pick(g, np.s_[None, :, None, :]))
+        lag = Q.T[:, None, :, None] * Q.T[None, :, None, :]                            # (i1, i2, a1, a2)
+        return E_xi[:, :, None, None, :, :] * np.conj(E_g)[:, :, :, :, None, None] * lag[None, None]
 
     def M_blocks(self, u1, u2):
         """k(Z_tau, Gamma_sigma) for tau = (u1, u2) at level h and every sigma at level h:
         array [s1, s2, i1, i2, j1, j2]."""
         z = self._s_cheb(self.h)
         g = self._f_cheb(self.h)
-        return kernel(z[u1][None, None, :, None, None, None], z[u2][None, None, None, :, None, None],
-                      g[:, None, None, None, :, None], g[None, :, None, None, None, :], self.params, self.amp)
+        S = slice(None)
+        return kernel(_pick(z, (u1, None, None, S, None, None, None)),
+                      _pick(z, (u2, None, None, None, S, None, None)),
+                      _pick(g, (S, None, None, None, S, None)),
+                      _pick(g, (None, S, None, None, None, S)), self.params, self.amp)
 
     def U_blocks(self, u1, u2):
         """U_{tau,sigma'} for tau = (u1, u2) at level h and every sigma' at level lc:
         array [v1, v2, a1, a2, i1, i2] (a = point offset inside tau)."""
-        P = self.params
         z = self._s_cheb(self.h)
         x = self._leaf_points()
-        Pm = cheb.lagrange_values(z, x)                # (u, a, i) = p_i(x_a)
+        Pm = cheb.leaf_lagrange(self.b, self.q)        # (a, i) = p_i(x_a)
         eta = self._f_center(self.lc)
-        z1, z2, x1, x2 = z[u1], z[u2], x[u1], x[u2]
-        ph_x = phase(x1[None, None, :, None], x2[None, None, None, :],
-                     eta[:, None, None, None], eta[None, :, None, None], P)           # (v1, v2, a1, a2)
-        ph_z = phase(z1[None, None, :, None], z2[None, None, None, :],
-                     eta[:, None, None, None], eta[None, :, None, None], P)           # (v1, v2, i1, i2)
-        lag = Pm[u1][:, None, :, None] * Pm[u2][None, :, None, :]                     # (a1, a2, i1, i2)
-        return (np.exp(2j * np.pi * (ph_x[:, :, :, :, None, None] - ph_z[:, :, None, None, :, :]))
-                * lag[None, None])
+        E_x = self._E(x[u1][None, None, :, None], x[u2][None, None, None, :],
+                      eta[:, None, None, None], eta[None, :, None, None])             # (v1, v2, a1, a2)
+        E_z = self._E(_pick(z, (u1, None, None, slice(None), None)), _pick(z, (u2, None, None, None, slice(None))),
+                      eta[:, None, None, None], eta[None, :, None, None])             # (v1, v2, i1, i2)
+        lag = Pm[:, None, :, None] * Pm[None, :, None, :]                             # (a1, a2, i1, i2)
+        return E_x[:, :, :, :, None, None] * np.conj(E_z)[:, :, None, None, :, :] * lag[None, None]
 
     # --- apply (eq. bf: K~ = U M V) -----------------------------------------------
     # Blocks are contracted with numpy's matmul over stacks of boxes; box indices are
     # (index along the first dimension, index along the second) in row-major order.
+    # Blocks are evaluated once per object when all of them fit in about 0.6 GB (n <= 32),
+    # else on every use; the values are the same either way.
+    def _cached(self, key, make):
+        if self.factor_count() > 4e7:
+            return make()
+        cache = self.__dict__.setdefault("_blocks", {})
+        if key not in cache:
+            cache[key] = make()
+        return cache[key]
+
     def _Vmat(self, t1, t2):
         """V_{tau',sigma} for all sigma as a stack (S^2, q^2, b^2)."""
         S, q, b = 2 ** self.h, self.q, self.b
-        return self.V_blocks(t1, t2).reshape(S * S, q * q, b * b)
+        return self._cached(("V", t1, t2), lambda: self.V_blocks(t1, t2).reshape(S * S, q * q, b * b))
 
     def _Mmat(self, u1, u2):
         S, q = 2 ** self.h, self.q
-        return self.M_blocks(u1, u2).reshape(S * S, q * q, q * q)
+        return self._cached(("M", u1, u2), lambda: self.M_blocks(u1, u2).reshape(S * S, q * q, q * q))
 
     def _Umat(self, u1, u2):
         """[U_{tau,sigma'}]_{sigma'} side by side: (b^2, T^2 q^2)."""
         T, q, b = 2 ** self.lc, self.q, self.b
-        return self.U_blocks(u1, u2).reshape(T * T, b * b, q * q).transpose(1, 0, 2).reshape(b * b, T * T * q * q)
+        return self._cached(("U", u1, u2), lambda: self.U_blocks(u1, u2).reshape(T * T, b * b, q * q)
+                            .transpose(1, 0, 2).reshape(b * b, T * T * q * q))
 
     def _group(self, W, k):
         """Sum of per-sigma (level h) terms over the level-lc box containing sigma: (S^2, r, k) -> (T^2, r, k)."""

@@ -13,8 +13,19 @@ Phase families (Section 5 uses Phi = x.xi + rho(x, xi)):
   1D:  Phi(x, xi) = x xi + (c0 + c1 sin(2 pi x)) |xi|.
        c0 = c1 = 0 is the shifted DFT; c0 = 1/8, c1 = 1/16 is the workload
        c(x) = (2 + sin 2 pi x)/16; c0 = 1/4, c1 = 1/8 is Section 5.1's phase.
+
+Precision.  An entry depends on Phi modulo 1 only, while |Phi| grows to about
+0.6 N.  ``phase_frac`` therefore forms Phi in double-double arithmetic (dd.py)
+from points given exactly (float64 values or double-double pairs), drops the
+integer part exactly and keeps the fraction as a double-double pair;
+``expi2pi`` turns a fraction into exp(2 pi i f) with one final rounding per
+component.  ``kernel`` and every factor entry of the butterfly use these, so
+an entry carries the rounding of an O(1) quantity at any N.  ``phase`` is the
+same formula in plain float64, for hand checks at small arguments.
 """
 import numpy as np
+
+from . import dd
 
 PHASE_DFT = (0.0, 0.0)
 PHASE_SIN16 = (2.0 / 16.0, 1.0 / 16.0)
@@ -41,6 +52,28 @@ def phase(x, xi, params):
     return x * xi + c_of_x(x, params) * np.abs(xi)
 
 
+def phase_frac(x, xi, params):
+    """Phi(x, xi) minus an integer, as a double-double pair in about [-1/2, 1/2].  x and xi are
+    float64 arrays (exact values) or double-double pairs; they broadcast against each other."""
+    x, xi = dd.as_dd(x), dd.as_dd(xi)
+    c0, c1 = params
+    s = dd.sincos_pi(dd.scale(x, 2.0))[0]                        # sin(2 pi x), on x's shape
+    cx = dd.add(dd.as_dd(np.full(x[0].shape, c0)), dd.mul(dd.as_dd(np.full(x[0].shape, c1)), s))
+    lin = dd.frac(dd.mul(x, xi))                                 # x xi mod 1
+    nonlin = dd.frac(dd.mul(cx, dd.absolute(xi)))                # c(x) |xi| mod 1
+    return dd.frac(dd.add(lin, nonlin))
+
+
+def expi2pi(f):
+    """exp(2 pi i f) for a double-double fraction f (|f| <= 1): the angle theta = 2 pi f is a
+    double-double (h, l), and exp(i theta) = (cos h - l sin h) + i (sin h + l cos h) to within
+    one rounding per component (|l| < 1e-15, so the l^2 terms are below float64 resolution)."""
+    f = dd.as_dd(f)
+    th = dd.mul(dd.scale(dd.PI, 2.0), f)
+    c, s = np.cos(th[0]), np.sin(th[0])
+    return (c - th[1] * s) + 1j * (s + th[1] * c)
+
+
 def gaussian_amplitude(n, centers_x, centers_xi, sigma2):
     """Section 5.1's amplitude: a(x, xi) = sum_k exp(-((x - x_k)^2 + ((xi - xi_k) / N)^2) / sigma^2),
     with centers (x_k, xi_k) given (the paper draws them at random in [0, 1] x [-N/2, N/2])."""
@@ -56,12 +89,12 @@ def gaussian_amplitude(n, centers_x, centers_xi, sigma2):
 
 
 def kernel(x, xi, params, amp=None):
-    """k(x, xi) = a(x, xi) exp(2 pi i Phi(x, xi)) (a = 1 when amp is None)."""
-    k = np.exp(2j * np.pi * phase(x, xi, params))
+    """k(x, xi) = a(x, xi) exp(2 pi i Phi(x, xi)) (a = 1 when amp is None); x, xi as in phase_frac.
+    The amplitude is smooth on the scale of the grid, so it takes the points rounded to float64."""
+    k = expi2pi(phase_frac(x, xi, params))
     if amp is not None:
-        x = np.asarray(x, dtype=np.float64)
-        xi = np.asarray(xi, dtype=np.float64)
-        k = k * amp(*np.broadcast_arrays(x, xi))
+        xh, xih = dd.to_float(dd.as_dd(x)), dd.to_float(dd.as_dd(xi))
+        k = k * amp(*np.broadcast_arrays(xh, xih))
     return k
 
 

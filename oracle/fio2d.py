@@ -18,6 +18,11 @@ with (a0, a1) = (2/16, 1/16) for the paper's workload and (0, 0) for the plain
     Phi(x, xi) = x . xi + c(x) ||xi||,  c(x) = a0 + a1 sin(2 pi x1) sin(2 pi x2),
 with (a0, a1) = (3/8, 1/8) there; it is the family above with c2 = c1.
 
+Precision: as in 1D (fio.py), ``phase_frac`` forms Phi modulo 1 in
+double-double arithmetic from exact points and ``kernel`` uses it; ``phase``,
+``rho`` and ``coeffs`` are the same formulas in plain float64, for hand checks
+and for the amplitude (which is smooth in x and xi).
+
 Internal ordering (library-private, used by the HSS tree): Morton order, the
 bits of the first coordinate above those of the second at every level, so the
 points of every dyadic box are contiguous and the box index at level l is the
@@ -25,6 +30,9 @@ Morton code of the box coordinates.
 """
 import numpy as np
 from scipy.special import hankel1
+
+from . import dd
+from .fio import expi2pi
 
 PHASE2_DFT = (0.0, 0.0)
 PHASE2_ANISO16 = (2.0 / 16.0, 1.0 / 16.0)
@@ -67,11 +75,34 @@ def phase(x1, x2, k1, k2, params):
     return x1 * k1 + x2 * k2 + rho(x1, x2, k1, k2, params)
 
 
+def _coeffs_dd(x1, x2, params):
+    a0 = dd.as_dd(np.float64(params[0]))
+    a1 = dd.as_dd(np.float64(params[1]))
+    s1, co1 = dd.sincos_pi(dd.scale(dd.as_dd(x1), 2.0))
+    s2, co2 = dd.sincos_pi(dd.scale(dd.as_dd(x2), 2.0))
+    c1 = dd.add(a0, dd.mul(a1, dd.mul(s1, s2)))
+    if len(params) > 2 and params[2] == "iso":
+        return c1, c1
+    return c1, dd.add(a0, dd.mul(a1, dd.mul(co1, co2)))
+
+
+def phase_frac(x1, x2, k1, k2, params):
+    """Phi(x, xi) minus an integer, as a double-double pair; arguments are float64 arrays (exact
+    values) or double-double pairs, broadcasting against each other."""
+    x1, x2, k1, k2 = (dd.as_dd(v) for v in (x1, x2, k1, k2))
+    c1, c2 = _coeffs_dd(x1, x2, params)
+    lin = dd.frac(dd.add(dd.frac(dd.mul(x1, k1)), dd.frac(dd.mul(x2, k2))))
+    t1, t2 = dd.mul(c1, k1), dd.mul(c2, k2)
+    nonlin = dd.frac(dd.sqrt(dd.add(dd.mul(t1, t1), dd.mul(t2, t2))))
+    return dd.frac(dd.add(lin, nonlin))
+
+
 def hankel_amplitude(params):
     """Section 5.3's amplitude a(x, xi) = H0^(1)(2 pi rho(x, xi)) exp(-2 pi i rho(x, xi)), with
     rho the nonlinear part of the phase (H0^(1) the Hankel function of the first kind, order 0).
     It is infinite at xi = 0, a point of the frequency grid (the butterfly evaluates it only at
-    Chebyshev points, never there)."""
+    Chebyshev points, never there).  With t = 2 pi rho rounded once, a = H0^(1)(t) exp(-i t): both
+    factors take the same t, and a is smooth in t, so that rounding moves a by ~eps |a|."""
     def amp(x1, x2, k1, k2):
         r = rho(x1, x2, k1, k2, params)
         with np.errstate(invalid="ignore", over="ignore"):
@@ -80,10 +111,11 @@ def hankel_amplitude(params):
 
 
 def kernel(x1, x2, k1, k2, params, amp=None):
-    """k(x, xi) = a(x, xi) exp(2 pi i Phi(x, xi)) (a = 1 when amp is None)."""
-    k = np.exp(2j * np.pi * phase(x1, x2, k1, k2, params))
+    """k(x, xi) = a(x, xi) exp(2 pi i Phi(x, xi)) (a = 1 when amp is None), arguments as in
+    phase_frac; the amplitude takes the points rounded to float64."""
+    k = expi2pi(phase_frac(x1, x2, k1, k2, params))
     if amp is not None:
-        k = k * amp(*np.broadcast_arrays(*(np.asarray(v, np.float64) for v in (x1, x2, k1, k2))))
+        k = k * amp(*np.broadcast_arrays(*(dd.to_float(dd.as_dd(v)) for v in (x1, x2, k1, k2))))
     return k
 
 
