@@ -9,6 +9,7 @@
 //   (p * q + i) * nrhs + col, so that consecutive lanes of a wave work on
 //   consecutive right-hand sides of the same pair.
 #include "bf_apply.h"
+#include "ddmath.h"
 
 #include <cmath>
 #include <cstring>
@@ -86,35 +87,20 @@ size_t bf_tw_off(const fio_bf_s *bf, bool cside, int lev) {
 
 size_t bf_coef_elems(const fio_bf_s *bf, int nrhs) { return (size_t)bf->N * bf->q * (size_t)nrhs; }
 
-// factor evaluation (Section 2.2).  Phase differences are formed as
-// differences (centers are exact binary fractions / integers), so an entry's
-// phase carries only the rounding of O(1)-sized terms; M's full phase keeps
-// its large exact parts exact (integer products and two-product splits).
-__device__ __forceinline__ double cheb_t(int i, int q) { return cospi((2.0 * i + 1.0) / (2.0 * q)); }
+// factor evaluation (Section 2.2).  Every entry is formed from exact points (box centers are
+// binary fractions or integers, Chebyshev points are center + (w/2) t_i with the nodes t_i to 106
+// bits) in double-double arithmetic (ddmath.h): phase differences, their products with the
+// frequencies and c(x) keep all their bits, the integer part of a phase is dropped exactly and
+// the entry is rounded once.  Lagrange values are taken in the reference coordinate u of the
+// point in its interpolation box, where p_t(u) is the same for every box.
 
-// Lagrange basis of node t on the reference first-kind grid, at u in [-1, 1].
-__device__ double lagr(double u, int t, int q) {
-    double tt = cheb_t(t, q), p = 1.0;
-    for (int k = 0; k < q; ++k) {
-        if (k == t) continue;
-        double tk = cheb_t(k, q);
-        p *= (u - tk) / (tt - tk);
-    }
-    return p;
-}
+// c(x) = c0 + c1 sin(2 pi x)
+__device__ dd c_dd(const Geo &g, dd x) { return dd_add(dd_of(g.c0), dd_mul_d(dd_sinpi(dd_ldexp(x, 2.0)), g.c1)); }
 
-__device__ __forceinline__ double frac_rint(double x) { return x - rint(x); }
+__device__ __forceinline__ double2 scaled(double2 e, double v) { return zc(e.x * v, e.y * v); }
 
-__device__ __forceinline__ double2 e2pi(double ph) {
-    double t = frac_rint(ph), s, c;
-    sincospi(2.0 * t, &s, &c);
-    return zc(c, s);
-}
-
-__device__ __forceinline__ double c_of(const Geo &g, double x) { return g.c0 + g.c1 * sinpi(2.0 * x); }
-
-// V[sigma][tau][j][s]
-__global__ void gen_V(Geo g, double2 *out) {
+// V[sigma][tau][j][s] = exp(2 pi i (y + sgn c(y)) (xi_s - gamma_j)) q_j(xi_s)   (|xi| = sgn xi on the box)
+__global__ void gen_V(Geo g, Nodes tn, double2 *out) {
     size_t n = (size_t)(1L << g.Lp) * g.nsl * g.q * g.b;
     size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     if (id >= n) return;
@@ -124,20 +110,18 @@ __global__ void gen_V(Geo g, double2 *out) {
     r /= g.q;
     int tau = r % g.nsl;
     long sigma = r / g.nsl;
-    double w = (double)g.b;                                   // frequency leaf width
-    double eta = -0.5 * g.N + (sigma + 0.5) * w;
-    double sgn = eta > 0 ? 1.0 : -1.0;
-    double tj = cheb_t(j, g.q);
-    double dxi = (s - 0.5 * w) - 0.5 * w * tj;                // xi_s - gamma_j
-    double y = (tau + 0.5) / g.nsl;
-    double ph = (y + sgn * c_of(g, y)) * dxi;
-    double qv = lagr((s - 0.5 * w) / (0.5 * w), j, g.q);
-    double2 e = e2pi(ph);
-    out[id] = zc(e.x * qv, e.y * qv);
+    const double w = (double)g.b, hw = 0.5 * w;                  // frequency leaf width (8) and half width
+    const double eta = -0.5 * g.N + (sigma + 0.5) * w;
+    const double sgn = eta > 0 ? 1.0 : -1.0;
+    const double y = (tau + 0.5) / g.nsl;
+    const dd kap = dd_add(dd_of(y), dd_mul_d(c_dd(g, dd_of(y)), sgn));
+    const dd dxi = dd_sub(dd_of(s - hw), dd_ldexp(tn.t(j), hw));  // xi_s - gamma_j
+    const double qv = dd_lagrange(dd_of((s - hw) / hw), j, tn);
+    out[id] = scaled(dd_expi2pi(dd_frac(dd_mul(kap, dxi))), qv);
 }
 
 // C^[l+1]: group (alpha at spatial level L-l-1, sigma at frequency level l)
-__global__ void gen_C(Geo g, int l, double2 *out) {
+__global__ void gen_C(Geo g, Nodes tn, int l, double2 *out) {
     const int q = g.q, q2 = 2 * q;
     size_t n = (size_t)(g.N / 2) * q2 * q2;
     size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -148,16 +132,15 @@ __global__ void gen_C(Geo g, int l, double2 *out) {
     long alpha = grp / G, sigma = grp % G;
     int cout = row / q, j = row % q, cin = col / q, t = col % q;
     long tau = 2 * alpha + cout;
-    double y = (tau + 0.5) / (double)(1L << (g.L - l));
-    double ws = (double)g.N / (double)(1L << l), wb = 0.5 * ws;
-    double eta_s = -0.5 * g.N + (sigma + 0.5) * ws;
-    double sgn = eta_s > 0 ? 1.0 : -1.0;
-    double tj = cheb_t(j, q), tt = cheb_t(t, q);
-    double dgam = (cin - 0.5) * wb + 0.5 * wb * tt - 0.5 * ws * tj;   // gamma_beta,t - gamma_sigma,j
-    double ph = (y + sgn * c_of(g, y)) * dgam;
-    double qv = lagr((cin - 0.5) + 0.5 * tt, j, q);
-    double2 e = e2pi(ph);
-    out[id] = zc(e.x * qv, e.y * qv);
+    const double y = (tau + 0.5) / (double)(1L << (g.L - l));
+    const double ws = (double)g.N / (double)(1L << l), wb = 0.5 * ws;
+    const double eta_s = -0.5 * g.N + (sigma + 0.5) * ws;
+    const double sgn = eta_s > 0 ? 1.0 : -1.0;
+    const dd kap = dd_add(dd_of(y), dd_mul_d(c_dd(g, dd_of(y)), sgn));
+    // gamma_beta,t - gamma_sigma,j
+    const dd dgam = dd_add(dd_of((cin - 0.5) * wb), dd_sub(dd_ldexp(tn.t(t), 0.5 * wb), dd_ldexp(tn.t(j), 0.5 * ws)));
+    const dd u = dd_add(dd_of(cin - 0.5), dd_ldexp(tn.t(t), 0.5));
+    out[id] = scaled(dd_expi2pi(dd_frac(dd_mul(kap, dgam))), dd_lagrange(u, j, tn));
 }
 
 // M[p][i][j] = k(z_tau,i, gamma_sigma,j), p = tau 2^h + sigma
@@ -172,7 +155,7 @@ __device__ double amp_at(const Amp &a, double z, double gam, double N) {
     return s;
 }
 
-__global__ void gen_M(Geo g, Amp am, double2 *out) {
+__global__ void gen_M(Geo g, Nodes tn, Amp am, double2 *out) {
     const int q = g.q;
     size_t n = (size_t)g.N * q * q;
     size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -181,35 +164,21 @@ __global__ void gen_M(Geo g, Amp am, double2 *out) {
     long p = id / ((size_t)q * q);
     long H = 1L << g.h;
     long tau = p / H, sigma = p % H;
-    double wsp = 1.0 / (double)H;
-    double y = (tau + 0.5) * wsp;
-    double dz = 0.5 * wsp * cheb_t(i, q);
-    double z = y + dz;
-    double wf = (double)g.N / (double)H;
-    long eta_i = -(g.N / 2) + (long)((sigma + 0.5) * wf);      // exact: wf is even
-    double eta = (double)eta_i;
-    double dg = 0.5 * wf * cheb_t(j, q);
-    double gam = eta + dg;
-    double sgn = eta > 0 ? 1.0 : -1.0;
-    double aeta = fabs(eta);
-    // x*xi part: y*eta exactly (y = (2 tau + 1) / 2^(h+1)), plus the small cross terms
-    long long P = (long long)(2 * tau + 1) * (long long)eta_i;
-    long long mod = 1LL << (g.h + 1);
-    long long Pr = P % mod;
-    double f_yeta = (double)Pr / (double)mod;
-    double ph = f_yeta + y * dg + dz * gam;
-    // c(z) |gamma| = (c0 + c1 sin 2 pi z)(|eta| + sgn dg), large products split exactly
-    double p0 = g.c0 * aeta, e0 = fma(g.c0, aeta, -p0);
-    double sz = g.c1 * sinpi(2.0 * z);
-    double p1 = sz * aeta, e1 = fma(sz, aeta, -p1);
-    ph += frac_rint(p0) + e0 + frac_rint(p1) + e1 + (g.c0 + sz) * sgn * dg;
-    const double2 e = e2pi(ph);
-    const double av = amp_at(am, z, gam, (double)g.N);
-    out[id] = zc(e.x * av, e.y * av);
+    const double wsp = 1.0 / (double)H, wf = (double)g.N / (double)H;
+    const dd z = dd_add(dd_of((tau + 0.5) * wsp), dd_ldexp(tn.t(i), 0.5 * wsp));
+    const double eta = -0.5 * g.N + (sigma + 0.5) * wf;           // an integer (wf is even)
+    const dd gam = dd_add(dd_of(eta), dd_ldexp(tn.t(j), 0.5 * wf));
+    const double sgn = eta > 0 ? 1.0 : -1.0;                       // no level-h box straddles 0
+    // Phi = z gamma + c(z) |gamma|, each product reduced modulo 1 before the sum
+    const dd lin = dd_frac(dd_mul(z, gam));
+    const dd nonlin = dd_frac(dd_mul(c_dd(g, z), dd_mul_d(gam, sgn)));
+    const double av = amp_at(am, dd_val(z), dd_val(gam), (double)g.N);
+    out[id] = scaled(dd_expi2pi(dd_add(lin, nonlin)), av);
 }
 
 // B^[l+1]: group (alpha at spatial level l, sigma at frequency level L-l-1)
-__global__ void gen_B(Geo g, int l, double2 *out) {
+//   exp(2 pi i ((z_tau,i - z_alpha,t) eta + (c(z_tau,i) - c(z_alpha,t)) |eta|)) p_t(u_i)
+__global__ void gen_B(Geo g, Nodes tn, int l, double2 *out) {
     const int q = g.q, q2 = 2 * q;
     size_t n = (size_t)(g.N / 2) * q2 * q2;
     size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -219,23 +188,21 @@ __global__ void gen_B(Geo g, int l, double2 *out) {
     long G = 1L << (g.L - l - 1);
     long alpha = grp / G, sigma = grp % G;
     int cout = row / q, i = row % q, cin = col / q, t = col % q;
-    double wa = 1.0 / (double)(1L << l), wt = 0.5 * wa;
-    double ya = (alpha + 0.5) * wa;
-    double ti = cheb_t(i, q), tt = cheb_t(t, q);
-    double dyt = (cout - 0.5) * wt;                              // y_tau - y_alpha
-    double dz = dyt + 0.5 * wt * ti - 0.5 * wa * tt;             // z_tau,i - z_alpha,t
-    double sz = 2.0 * ya + dyt + 0.5 * wt * ti + 0.5 * wa * tt;  // z_tau,i + z_alpha,t
-    long beta = 2 * sigma + cin;
-    double wf = (double)g.N / (double)(1L << (g.L - l));
-    double eta = -0.5 * g.N + (beta + 0.5) * wf;
-    double ph = dz * eta + 2.0 * g.c1 * cospi(sz) * sinpi(dz) * fabs(eta);
-    double pv = lagr((cout - 0.5) + 0.5 * ti, t, q);
-    double2 e = e2pi(ph);
-    out[id] = zc(e.x * pv, e.y * pv);
+    const double wa = 1.0 / (double)(1L << l), wt = 0.5 * wa;
+    const double ya = (alpha + 0.5) * wa;
+    const dd d1 = dd_add(dd_of((cout - 0.5) * wt), dd_ldexp(tn.t(i), 0.5 * wt));   // z_tau,i - y_alpha
+    const dd d2 = dd_ldexp(tn.t(t), 0.5 * wa);                                       // z_alpha,t - y_alpha
+    const long beta = 2 * sigma + cin;
+    const double wf = (double)g.N / (double)(1L << (g.L - l));
+    const double eta = -0.5 * g.N + (beta + 0.5) * wf;
+    const dd dc = dd_sub(c_dd(g, dd_add(dd_of(ya), d1)), c_dd(g, dd_add(dd_of(ya), d2)));
+    const dd ph = dd_add(dd_frac(dd_mul_d(dd_sub(d1, d2), eta)), dd_frac(dd_mul_d(dc, fabs(eta))));
+    const dd u = dd_add(dd_of(cout - 0.5), dd_ldexp(tn.t(i), 0.5));
+    out[id] = scaled(dd_expi2pi(ph), dd_lagrange(u, t, tn));
 }
 
-// U[tau][sigma][s][i]
-__global__ void gen_U(Geo g, double2 *out) {
+// U[tau][sigma][s][i] = exp(2 pi i ((x_s - z_tau,i) eta + (c(x_s) - c(z_tau,i)) |eta|)) p_i(x_s)
+__global__ void gen_U(Geo g, Nodes tn, double2 *out) {
     const int q = g.q;
     size_t n = (size_t)(1L << g.Lp) * g.nsl * g.b * q;
     size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -246,17 +213,15 @@ __global__ void gen_U(Geo g, double2 *out) {
     r /= g.b;
     int sigma = r % g.nsl;
     long tau = r / g.nsl;
-    double w = 1.0 / (double)(1L << g.Lp);
-    double y = (tau + 0.5) * w;
-    double dxy = (s - 0.5 * g.b) / (double)g.N;                  // x_s - y_tau
-    double ti = cheb_t(i, q);
-    double dx = dxy - 0.5 * w * ti;                              // x_s - z_tau,i
-    double sx = 2.0 * y + dxy + 0.5 * w * ti;                    // x_s + z_tau,i
-    double eta = -0.5 * g.N + (sigma + 0.5) * ((double)g.N / g.nsl);
-    double ph = dx * eta + 2.0 * g.c1 * cospi(sx) * sinpi(dx) * fabs(eta);
-    double pv = lagr((s - 0.5 * g.b) / (0.5 * g.b), i, q);
-    double2 e = e2pi(ph);
-    out[id] = zc(e.x * pv, e.y * pv);
+    const double w = 1.0 / (double)(1L << g.Lp), hb = 0.5 * g.b;
+    const double y = (tau + 0.5) * w;
+    const double x = (tau * g.b + s) / (double)g.N;                 // grid point, exact
+    const dd dzt = dd_ldexp(tn.t(i), 0.5 * w);                      // z_tau,i - y
+    const dd dx = dd_sub(dd_of((s - hb) / (double)g.N), dzt);     // x_s - z_tau,i
+    const double eta = -0.5 * g.N + (sigma + 0.5) * ((double)g.N / g.nsl);
+    const dd dc = dd_sub(c_dd(g, dd_of(x)), c_dd(g, dd_add(dd_of(y), dzt)));
+    const dd ph = dd_add(dd_frac(dd_mul_d(dx, eta)), dd_frac(dd_mul_d(dc, fabs(eta))));
+    out[id] = scaled(dd_expi2pi(ph), dd_lagrange(dd_of((s - hb) / hb), i, tn));
 }
 
 // Structured transfer factors: every 2q x 2q transfer block is, per (c_out, c_in) quadrant,
@@ -266,10 +231,9 @@ __global__ void gen_U(Geo g, double2 *out) {
 //   C side: a = exp(-2 pi i (Phi(y_tau, gamma_sigma,j) - Phi(y_tau, eta_sigma))),
 //           b = exp(2 pi i (Phi(y_tau, gamma_beta,t) - Phi(y_tau, eta_sigma))),   P = P_cin(t, j),
 // with P_c(i, t) = p_t((c - 1/2) + t_i / 2) on the reference grid.  The products a P b are the
-// entries of Section 2.2 (the common phase at the parent's center cancels); a and b are phase
-// differences between nearby points, so they are accurate at any N.
+// entries of Section 2.2 (the common phase at the parent's center cancels).
 // Layout per group: [c_out][4][q] = a(c_out, 0), a(c_out, 1), b(c_out, 0), b(c_out, 1).
-__global__ void gen_TW_B(Geo g, int l, double2 *out) {
+__global__ void gen_TW_B(Geo g, Nodes tn, int l, double2 *out) {
     const int q = g.q;
     size_t n = (size_t)(g.N / 2) * 8 * q;
     size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -284,20 +248,15 @@ __global__ void gen_TW_B(Geo g, int l, double2 *out) {
     const long beta = 2 * sigma + cin;
     const double wf = (double)g.N / (double)(1L << (g.L - l));
     const double eta = -0.5 * g.N + (beta + 0.5) * wf;
-    double dz, sz, sgn;
-    if (kind < 2) {        // a: z_tau,i - y_alpha
-        dz = (cout - 0.5) * wt + 0.5 * wt * cheb_t(i, q);
-        sgn = 1.0;
-    } else {               // b: z_alpha,i - y_alpha, conjugated
-        dz = 0.5 * wa * cheb_t(i, q);
-        sgn = -1.0;
-    }
-    sz = 2.0 * ya + dz;
-    const double ph = dz * eta + 2.0 * g.c1 * cospi(sz) * sinpi(dz) * fabs(eta);
-    out[id] = e2pi(sgn * ph);
+    // a: z_tau,i - y_alpha; b: z_alpha,i - y_alpha, conjugated
+    const dd dz = kind < 2 ? dd_add(dd_of((cout - 0.5) * wt), dd_ldexp(tn.t(i), 0.5 * wt))
+                           : dd_ldexp(tn.t(i), 0.5 * wa);
+    const dd dc = dd_sub(c_dd(g, dd_add(dd_of(ya), dz)), c_dd(g, dd_of(ya)));
+    const dd ph = dd_add(dd_frac(dd_mul_d(dz, eta)), dd_frac(dd_mul_d(dc, fabs(eta))));
+    out[id] = dd_expi2pi(kind < 2 ? ph : dd_neg(ph));
 }
 
-__global__ void gen_TW_C(Geo g, int l, double2 *out) {
+__global__ void gen_TW_C(Geo g, Nodes tn, int l, double2 *out) {
     const int q = g.q;
     size_t n = (size_t)(g.N / 2) * 8 * q;
     size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -312,21 +271,20 @@ __global__ void gen_TW_C(Geo g, int l, double2 *out) {
     const double ws = (double)g.N / (double)(1L << l), wb = 0.5 * ws;
     const double eta_s = -0.5 * g.N + (sigma + 0.5) * ws;
     const double sgn = eta_s > 0 ? 1.0 : -1.0;
-    const double kap = y + sgn * c_of(g, y);
-    double ph;
-    if (kind < 2)          // a: -(gamma_sigma,j - eta_sigma)
-        ph = -kap * (0.5 * ws * cheb_t(i, q));
-    else                   // b: gamma_beta,t - eta_sigma
-        ph = kap * ((cin - 0.5) * wb + 0.5 * wb * cheb_t(i, q));
-    out[id] = e2pi(ph);
+    const dd kap = dd_add(dd_of(y), dd_mul_d(c_dd(g, dd_of(y)), sgn));
+    // a: -(gamma_sigma,j - eta_sigma); b: gamma_beta,t - eta_sigma
+    const dd d = kind < 2 ? dd_neg(dd_ldexp(tn.t(i), 0.5 * ws))
+                          : dd_add(dd_of((cin - 0.5) * wb), dd_ldexp(tn.t(i), 0.5 * wb));
+    out[id] = dd_expi2pi(dd_frac(dd_mul(kap, d)));
 }
 
-__global__ void gen_Pchild(int q, double *out) {
+__global__ void gen_Pchild(Nodes tn, double *out) {
     // out[c][i][t] = P_c(i, t) = p_t((c - 1/2) + t_i / 2)
+    const int q = tn.q;
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= 2 * q * q) return;
     const int t = id % q, i = (id / q) % q, c = id / (q * q);
-    out[id] = lagr((c - 0.5) + 0.5 * cheb_t(i, q), t, q);
+    out[id] = dd_lagrange(dd_add(dd_of(c - 0.5), dd_ldexp(tn.t(i), 0.5)), t, tn);
 }
 
 __global__ void cvt_f64_f32(const double2 *in, float2 *out, size_t n) {
@@ -340,29 +298,30 @@ __global__ void cvt_f64_f32(const double2 *in, float2 *out, size_t n) {
 static void bf_generate(fio_bf_s *bf, hipStream_t s) {
     if (bf->dim == 2) return bf2d_generate(bf, s);
     Geo g = geo_of(bf);
+    const Nodes tn = make_nodes(bf->q);
     double2 *base = bf->f64.as<double2>();
     const unsigned T = 256;
     size_t nV = (size_t)(1L << bf->Lp) * bf->nsl * bf->q * bf->b;
-    gen_V<<<grid1d(nV, T), T, 0, s>>>(g, base + bf->offV);
+    gen_V<<<grid1d(nV, T), T, 0, s>>>(g, tn, base + bf->offV);
     size_t nT = (size_t)(bf->N / 2) * 4 * bf->q * bf->q;
     for (int lev = 0; lev < bf->nl; ++lev) {
-        gen_C<<<grid1d(nT, T), T, 0, s>>>(g, bf->h + lev, base + bf->offC[lev]);
-        gen_B<<<grid1d(nT, T), T, 0, s>>>(g, bf->h + lev, base + bf->offB[lev]);
+        gen_C<<<grid1d(nT, T), T, 0, s>>>(g, tn, bf->h + lev, base + bf->offC[lev]);
+        gen_B<<<grid1d(nT, T), T, 0, s>>>(g, tn, bf->h + lev, base + bf->offB[lev]);
     }
     size_t nM = (size_t)bf->N * bf->q * bf->q;
-    gen_M<<<grid1d(nM, T), T, 0, s>>>(g, bf->amp, base + bf->offM);
-    gen_U<<<grid1d(nV, T), T, 0, s>>>(g, base + bf->offU);
+    gen_M<<<grid1d(nM, T), T, 0, s>>>(g, tn, bf->amp, base + bf->offM);
+    gen_U<<<grid1d(nV, T), T, 0, s>>>(g, tn, base + bf->offU);
     FIO_HIP(hipGetLastError());
     // structured transfer twiddles and the shared Lagrange matrices
     if (bf->nl > 0) {
         const size_t ntw = (size_t)(bf->N / 2) * 8 * bf->q;
         bf->tw64.alloc(2 * bf->nl * ntw * sizeof(double2));
         for (int lev = 0; lev < bf->nl; ++lev) {
-            gen_TW_B<<<grid1d(ntw, T), T, 0, s>>>(g, bf->h + lev, bf->tw64.as<double2>() + bf_tw_off(bf, false, lev));
-            gen_TW_C<<<grid1d(ntw, T), T, 0, s>>>(g, bf->h + lev, bf->tw64.as<double2>() + bf_tw_off(bf, true, lev));
+            gen_TW_B<<<grid1d(ntw, T), T, 0, s>>>(g, tn, bf->h + lev, bf->tw64.as<double2>() + bf_tw_off(bf, false, lev));
+            gen_TW_C<<<grid1d(ntw, T), T, 0, s>>>(g, tn, bf->h + lev, bf->tw64.as<double2>() + bf_tw_off(bf, true, lev));
         }
         DevBuf pd(2 * bf->q * bf->q * sizeof(double));
-        gen_Pchild<<<1, 2 * bf->q * bf->q, 0, s>>>(bf->q, pd.as<double>());
+        gen_Pchild<<<1, 2 * bf->q * bf->q, 0, s>>>(tn, pd.as<double>());
         FIO_HIP(hipGetLastError());
         FIO_HIP(hipMemcpyAsync(bf->Pchild, pd.p, 2 * bf->q * bf->q * sizeof(double), hipMemcpyDeviceToHost, s));
         FIO_HIP(hipStreamSynchronize(s));

@@ -38,6 +38,7 @@
 #include <cmath>
 
 #include "bf.h"
+#include "ddmath.h"
 #include "timing.h"
 
 namespace fio {
@@ -90,30 +91,18 @@ __device__ __forceinline__ long lex_of(long m, int L, int n) {
     return (long)j1 * n + j2;
 }
 
-__device__ __forceinline__ double cheb_node(int i, int q) { return cospi((2.0 * i + 1.0) / (2.0 * q)); }
-
-// Lagrange basis of node t of the first-kind grid on [-1, 1], at u
-__device__ double lagr1(double u, int t, int q) {
-    const double tt = cheb_node(t, q);
-    double p = 1.0;
-    for (int k = 0; k < q; ++k) {
-        if (k == t) continue;
-        const double tk = cheb_node(k, q);
-        p *= (u - tk) / (tt - tk);
-    }
-    return p;
-}
-
-__device__ __forceinline__ double rho2(const G2 &g, double x1, double x2, double k1, double k2) {
-    const double c1 = g.a0 + g.a1 * sinpi(2.0 * x1) * sinpi(2.0 * x2);
-    const double c2 = g.iso ? c1 : g.a0 + g.a1 * cospi(2.0 * x1) * cospi(2.0 * x2);
-    return sqrt(c1 * c1 * k1 * k1 + c2 * c2 * k2 * k2);
-}
-
-__device__ __forceinline__ double2 e2pi(double ph) {
-    double s, c;
-    sincospi(2.0 * (ph - rint(ph)), &s, &c);
-    return zc(c, s);
+// Phases are formed in double-double arithmetic from exact points (ddmath.h; box corners and
+// grid points are binary fractions or integers, Chebyshev points are center + (w/2) t_i) and
+// reduced modulo 1 before the single rounding of an entry; Lagrange values are taken in the
+// reference coordinate of the point in its box.
+__device__ dd rho2_dd(const G2 &g, dd x1, dd x2, dd k1, dd k2) {
+    dd s1, co1, s2, co2;
+    dd_sincospi(dd_ldexp(x1, 2.0), s1, co1);
+    dd_sincospi(dd_ldexp(x2, 2.0), s2, co2);
+    const dd c1 = dd_add(dd_of(g.a0), dd_mul_d(dd_mul(s1, s2), g.a1));
+    const dd c2 = g.iso ? c1 : dd_add(dd_of(g.a0), dd_mul_d(dd_mul(co1, co2), g.a1));
+    const dd t1 = dd_mul(c1, k1), t2 = dd_mul(c2, k2);
+    return dd_sqrt(dd_add(dd_mul(t1, t1), dd_mul(t2, t2)));
 }
 
 // box geometry: spatial box j at level l is [j1 2^-l, (j1 + 1) 2^-l] x [..];
@@ -135,8 +124,9 @@ __device__ __forceinline__ void f_box(const G2 &g, int l, long box, double &lo1,
 }
 
 // --- factor generation ------------------------------------------------------------
-// V(i, s) of pair p = tau' * S + sigma
-__global__ void gen2_V(G2 g, double2 *out) {
+// V(i, s) of pair p = tau' * S + sigma:
+//   exp(2 pi i (y.(xi_s - gamma_i) + rho(y, xi_s) - rho(y, gamma_i))) q_i(xi_s)
+__global__ void gen2_V(G2 g, Nodes tn, double2 *out) {
     const size_t nV = (size_t)g.T * g.S * g.q2 * g.b2;
     const size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     if (id >= nV) return;
@@ -151,18 +141,19 @@ __global__ void gen2_V(G2 g, double2 *out) {
     f_box(g, g.h, sigma, f1, f2, wf);
     int a1, a2;
     demorton(s, g.hb, a1, a2);
-    const double k1 = f1 + a1, k2 = f2 + a2;                   // xi_s
+    const double k1 = f1 + a1, k2 = f2 + a2;                   // xi_s (integers)
     const int i1 = i / g.q, i2 = i % g.q;
     const double c1 = f1 + 0.5 * wf, c2 = f2 + 0.5 * wf, hw = 0.5 * wf;
-    const double g1 = c1 + hw * cheb_node(i1, g.q), g2 = c2 + hw * cheb_node(i2, g.q);   // gamma_i
-    const double ph = y1 * (k1 - g1) + y2 * (k2 - g2) + (rho2(g, y1, y2, k1, k2) - rho2(g, y1, y2, g1, g2));
-    const double lag = lagr1((k1 - c1) / hw, i1, g.q) * lagr1((k2 - c2) / hw, i2, g.q);
-    const double2 e = e2pi(ph);
+    const dd g1 = dd_add(dd_of(c1), dd_ldexp(tn.t(i1), hw)), g2 = dd_add(dd_of(c2), dd_ldexp(tn.t(i2), hw));
+    const dd lin = dd_add(dd_frac(dd_mul_d(dd_sub(dd_of(k1), g1), y1)), dd_frac(dd_mul_d(dd_sub(dd_of(k2), g2), y2)));
+    const dd nl = dd_sub(rho2_dd(g, dd_of(y1), dd_of(y2), dd_of(k1), dd_of(k2)), rho2_dd(g, dd_of(y1), dd_of(y2), g1, g2));
+    const double lag = dd_lagrange(dd_of((k1 - c1) / hw), i1, tn) * dd_lagrange(dd_of((k2 - c2) / hw), i2, tn);
+    const double2 e = dd_expi2pi(dd_add(lin, dd_frac(nl)));
     out[id] = zc(e.x * lag, e.y * lag);
 }
 
 // M(i, j) of block u * S + sigma: k(z_u,i, gamma_sigma,j)
-__global__ void gen2_M(G2 g, double2 *out) {
+__global__ void gen2_M(G2 g, Nodes tn, double2 *out) {
     const size_t nM = (size_t)g.S * g.S * g.q2 * g.q2;
     const size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     if (id >= nM) return;
@@ -174,24 +165,31 @@ __global__ void gen2_M(G2 g, double2 *out) {
     s_box(g.h, u, z1, z2, ws);
     f_box(g, g.h, sigma, f1, f2, wf);
     const double hs = 0.5 * ws, hf = 0.5 * wf;
-    const double x1 = z1 + hs + hs * cheb_node(i / g.q, g.q), x2 = z2 + hs + hs * cheb_node(i % g.q, g.q);
-    const double k1 = f1 + hf + hf * cheb_node(j / g.q, g.q), k2 = f2 + hf + hf * cheb_node(j % g.q, g.q);
-    const double r = rho2(g, x1, x2, k1, k2);
+    const dd x1 = dd_add(dd_of(z1 + hs), dd_ldexp(tn.t(i / g.q), hs));
+    const dd x2 = dd_add(dd_of(z2 + hs), dd_ldexp(tn.t(i % g.q), hs));
+    const dd k1 = dd_add(dd_of(f1 + hf), dd_ldexp(tn.t(j / g.q), hf));
+    const dd k2 = dd_add(dd_of(f2 + hf), dd_ldexp(tn.t(j % g.q), hf));
+    const dd r = rho2_dd(g, x1, x2, k1, k2);
+    const dd lin = dd_add(dd_frac(dd_mul(x1, k1)), dd_frac(dd_mul(x2, k2)));
+    const double2 e = dd_expi2pi(dd_add(lin, dd_frac(r)));
     if (!g.hankel) {
-        out[id] = e2pi(x1 * k1 + x2 * k2 + r);
+        out[id] = e;
         return;
     }
-    // a exp(2 pi i Phi) with a = H0^(1)(2 pi rho) exp(-2 pi i rho): the rho terms of the two
-    // exponentials cancel, leaving H0^(1)(2 pi rho) exp(2 pi i x.xi), H0^(1) = J0 + i Y0.
+    // a = H0^(1)(t) exp(-i t), t = 2 pi rho (H0^(1) = J0 + i Y0): a is smooth in t, so t is taken
+    // rounded once; the oscillation of H0^(1) cancels against exp(-i t) at the same t.
     // Chebyshev points never fall on xi = 0, so rho > 0 here.
-    const double z = 2.0 * M_PI * r;
-    const double hr = j0(z), hi = y0(z);
-    const double2 e = e2pi(x1 * k1 + x2 * k2);
-    out[id] = zc(hr * e.x - hi * e.y, hr * e.y + hi * e.x);
+    const double t = 2.0 * M_PI * dd_val(r);
+    double st, ct;
+    sincos(t, &st, &ct);
+    const double jr = j0(t), yi = y0(t);
+    const double ar = jr * ct + yi * st, ai = yi * ct - jr * st;    // (J0 + i Y0)(cos t - i sin t)
+    out[id] = zc(ar * e.x - ai * e.y, ar * e.y + ai * e.x);
 }
 
-// U(s, i) of pair p = tau * T + sigma'
-__global__ void gen2_U(G2 g, double2 *out) {
+// U(s, i) of pair p = tau * T + sigma':
+//   exp(2 pi i ((x_s - z_i).eta + rho(x_s, eta) - rho(z_i, eta))) p_i(x_s)
+__global__ void gen2_U(G2 g, Nodes tn, double2 *out) {
     const size_t nU = (size_t)g.S * g.T * g.q2 * g.b2;
     const size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     if (id >= nU) return;
@@ -207,12 +205,13 @@ __global__ void gen2_U(G2 g, double2 *out) {
     int a1, a2;
     demorton(s, g.hb, a1, a2);
     const double hs = 0.5 * ws, c1 = t1 + hs, c2 = t2 + hs;
-    const double x1 = t1 + a1 * (1.0 / g.n), x2 = t2 + a2 * (1.0 / g.n);
+    const double x1 = t1 + a1 * (1.0 / g.n), x2 = t2 + a2 * (1.0 / g.n);   // grid points, exact
     const int i1 = i / g.q, i2 = i % g.q;
-    const double z1 = c1 + hs * cheb_node(i1, g.q), z2 = c2 + hs * cheb_node(i2, g.q);
-    const double ph = (x1 - z1) * e1 + (x2 - z2) * e2 + (rho2(g, x1, x2, e1, e2) - rho2(g, z1, z2, e1, e2));
-    const double lag = lagr1((x1 - c1) / hs, i1, g.q) * lagr1((x2 - c2) / hs, i2, g.q);
-    const double2 e = e2pi(ph);
+    const dd z1 = dd_add(dd_of(c1), dd_ldexp(tn.t(i1), hs)), z2 = dd_add(dd_of(c2), dd_ldexp(tn.t(i2), hs));
+    const dd lin = dd_add(dd_frac(dd_mul_d(dd_sub(dd_of(x1), z1), e1)), dd_frac(dd_mul_d(dd_sub(dd_of(x2), z2), e2)));
+    const dd nl = dd_sub(rho2_dd(g, dd_of(x1), dd_of(x2), dd_of(e1), dd_of(e2)), rho2_dd(g, z1, z2, dd_of(e1), dd_of(e2)));
+    const double lag = dd_lagrange(dd_of((x1 - c1) / hs), i1, tn) * dd_lagrange(dd_of((x2 - c2) / hs), i2, tn);
+    const double2 e = dd_expi2pi(dd_add(lin, dd_frac(nl)));
     out[id] = zc(e.x * lag, e.y * lag);
 }
 
@@ -618,9 +617,10 @@ void bf2d_generate(fio_bf_s *bf, hipStream_t s) {
     const G2 g = g2_of(bf);
     double2 *base = bf->f64.as<double2>();
     const size_t nV = bf->offM - bf->offV, nM = bf->offU - bf->offM, nU = bf->total - bf->offU;
-    gen2_V<<<grid1d(nV, 256), 256, 0, s>>>(g, base + bf->offV);
-    gen2_M<<<grid1d(nM, 256), 256, 0, s>>>(g, base + bf->offM);
-    gen2_U<<<grid1d(nU, 256), 256, 0, s>>>(g, base + bf->offU);
+    const Nodes tn = make_nodes(bf->q);
+    gen2_V<<<grid1d(nV, 256), 256, 0, s>>>(g, tn, base + bf->offV);
+    gen2_M<<<grid1d(nM, 256), 256, 0, s>>>(g, tn, base + bf->offM);
+    gen2_U<<<grid1d(nU, 256), 256, 0, s>>>(g, tn, base + bf->offU);
     FIO_HIP(hipGetLastError());
 }
 

@@ -40,8 +40,29 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+def perr(a, b):
+    """Parity error of a against the reference b, element by element: the larger of the largest
+    per-column relative error ||a_c - b_c|| / ||b_c|| and max |a - b| / max |b| (vectors are one
+    column).  No whole-block norm: one bad column or entry is not averaged away."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    if a.ndim == 1:
+        a, b = a[:, None], b[:, None]
+    d = a - b
+    nd, nb = np.linalg.norm(d, axis=0), np.linalg.norm(b, axis=0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        col = np.where(nb > 0, nd / nb, np.where(nd > 0, np.inf, 0.0))
+    mb = np.abs(b).max()
+    ent = np.abs(d).max() / mb if mb > 0 else (np.inf if np.abs(d).max() > 0 else 0.0)
+    return float(max(col.max(), ent))
+
+
+def ecbf(a, b):
+    """Section 5's relative error estimator of an approximation (e_cBF): ||a - b||_2 / ||b||_2 over
+    the given (sampled) entries.  It measures the butterfly's interpolation error against the
+    dense K, a quantity of the method, not GPU-vs-oracle parity (that is perr)."""
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def step(msg):

@@ -6,7 +6,7 @@ import pytest
 
 import fio_inputs as fi
 from oracle import bf2d as obf2, fio2d as of2
-from gpu_common import fiohss, dev, host, rel, step, oracle_bf, gpu_bf
+from gpu_common import fiohss, dev, host, perr, step, oracle_bf, gpu_bf
 
 pytestmark = pytest.mark.gpu
 
@@ -24,8 +24,8 @@ def test_autotune_2d_candidates_match_oracle():
         for ns in (4, 8, 16):
             for adj in (False, True):
                 B.set_tile(k, adj=adj, kc=kc, nsplit=ns)
-            assert rel(host(B.apply(dev(x))), rf) < 1e-12
-            assert rel(host(B.apply_adj(dev(x))), ra) < 1e-12
+            assert perr(host(B.apply(dev(x))), rf) < 1e-12
+            assert perr(host(B.apply_adj(dev(x))), ra) < 1e-12
     with pytest.raises(F.FioError):
         B.set_tile(k, nsplit=32)       # more than the partner count / the workspace holds
     with pytest.raises(F.FioError):
@@ -35,8 +35,8 @@ def test_autotune_2d_candidates_match_oracle():
         assert "chosen fwd" in rep and "chosen adj" in rep
         step(rep)
         tol = 1e-12 if prec == F.FIO_PREC_FP64 else 1e-5
-        assert rel(host(B.apply(dev(x), prec=prec)), rf) < tol
-        assert rel(host(B.apply_adj(dev(x), prec=prec)), ra) < tol
+        assert perr(host(B.apply(dev(x), prec=prec)), rf) < tol
+        assert perr(host(B.apply_adj(dev(x), prec=prec)), ra) < tol
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])
@@ -54,7 +54,7 @@ def test_autotune_1d_levels_per_pass(prec):
         for adj in (False, True):
             B.set_tile(k, prec=prec, adj=adj, kmax=km)
         y, ya = host(B.apply(dev(x), prec=prec)), host(B.apply_adj(dev(x), prec=prec))
-        assert rel(y, rf) < tol and rel(ya, ra) < tol
+        assert perr(y, rf) < tol and perr(ya, ra) < tol
         outs.append((y, ya))
     if prec != 2:
         # FP64 / FP32 coefficients cross HBM unrounded between passes: identical results
@@ -63,5 +63,5 @@ def test_autotune_1d_levels_per_pass(prec):
     rep = B.autotune(dev(x), prec=prec, reps=3)
     step(rep)
     assert "chosen fwd" in rep and "chosen adj" in rep
-    assert rel(host(B.apply(dev(x), prec=prec)), rf) < tol
-    assert rel(host(B.apply_adj(dev(x), prec=prec)), ra) < tol
+    assert perr(host(B.apply(dev(x), prec=prec)), rf) < tol
+    assert perr(host(B.apply_adj(dev(x), prec=prec)), ra) < tol

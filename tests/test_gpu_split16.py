@@ -7,7 +7,7 @@ import pytest
 
 import fio_inputs as fi
 from oracle import bf as obf, fio as ofio
-from gpu_common import fiohss, dev, host, rel, step, oracle_bf, gpu_bf, PHASES
+from gpu_common import fiohss, dev, host, perr, ecbf, step, oracle_bf, gpu_bf, PHASES
 
 pytestmark = pytest.mark.gpu
 
@@ -37,10 +37,10 @@ def test_split16_apply_matches_oracle(n, k):
     y, ya = host(B.apply(dev(x), prec=SPLIT)), host(B.apply_adj(dev(x), prec=SPLIT))
     rf, ra = ob.apply(x), ob.apply_adj(x)
     for j in range(k):
-        assert rel(y[:, j], rf[:, j]) < TOL16
-        assert rel(ya[:, j], ra[:, j]) < TOL16
+        assert perr(y[:, j], rf[:, j]) < TOL16
+        assert perr(ya[:, j], ra[:, j]) < TOL16
     # half precision alone would give ~1e-3; FP64 rounding would give ~1e-15
-    assert 1e-9 < rel(y, rf) < 1e-5 and 1e-9 < rel(ya, ra) < 1e-5
+    assert 1e-9 < perr(y, rf) < 1e-5 and 1e-9 < perr(ya, ra) < 1e-5
 
 
 def test_split16_column_scaling():
@@ -60,7 +60,7 @@ def test_split16_column_scaling():
         y = host(fn(dev(x), prec=SPLIT))
         ref = ob.apply_adj(x) if adj else ob.apply(x)
         for j in range(3):
-            assert rel(y[:, j], ref[:, j]) < TOL16
+            assert perr(y[:, j], ref[:, j]) < TOL16
         assert np.all(y[:, 3] == 0)
         # an O(1) column shifted by 2^-40 / 2^40 (inside FP32 range through every factor)
         for sh in (-40, 40):
@@ -105,7 +105,7 @@ def test_full_size_sampled_rows_and_adjoint_identity(full_size):
     rows = np.sort(np.random.default_rng(5).choice(n, 64, replace=False))
     Kr = ofio.dense_K_rows(n, rows, PHASES["sin16"])
     cols = [0, 31, 63]
-    e = rel(yh[np.ix_(rows, cols)], Kr @ f[:, cols])
+    e = ecbf(yh[np.ix_(rows, cols)], Kr @ f[:, cols])
     assert 3e-7 < e < 2e-5
     step("full size adjoint identity")
     g = fi.complex_gaussian(24, fi.PURPOSE_PROBE, n, k)
@@ -115,8 +115,8 @@ def test_full_size_sampled_rows_and_adjoint_identity(full_size):
     assert np.max(np.abs(lhs - rhs) / np.abs(lhs)) < 1e-12
     step("full size FP32 / split vs FP64")
     for p in (F.FIO_PREC_FP32, SPLIT):
-        assert rel(host(B.apply(dev(f), prec=p)), yh) < TOL16
-        assert rel(host(B.apply_adj(dev(g), prec=p)), z) < TOL16
+        assert perr(host(B.apply(dev(f), prec=p)), yh) < TOL16
+        assert perr(host(B.apply_adj(dev(g), prec=p)), z) < TOL16
 
 
 def test_full_size_dft_closed_form():
@@ -128,10 +128,10 @@ def test_full_size_dft_closed_form():
     B = F.BF(n, 9, 0.0, 0.0, precs=precs3(F))
     f = fi.rhs(2, n, 2)
     ref, refa = ofio.dft_apply(f), ofio.dft_apply_adj(f)
-    assert rel(host(B.apply(dev(f))), ref) < 1e-6
-    assert rel(host(B.apply_adj(dev(f))), refa) < 1e-6
-    assert rel(host(B.apply(dev(f), prec=SPLIT)), ref) < 1e-6 + TOL16
-    assert rel(host(B.apply_adj(dev(f), prec=SPLIT)), refa) < 1e-6 + TOL16
+    assert perr(host(B.apply(dev(f))), ref) < 1e-6
+    assert perr(host(B.apply_adj(dev(f))), refa) < 1e-6
+    assert perr(host(B.apply(dev(f), prec=SPLIT)), ref) < 1e-6 + TOL16
+    assert perr(host(B.apply_adj(dev(f), prec=SPLIT)), refa) < 1e-6 + TOL16
 
 
 def test_full_size_refinement_all_precisions(full_size):
