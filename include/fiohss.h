@@ -377,23 +377,31 @@ const char *fio_status_str(fio_status s);
  * request (nrhs columns for one operator) and returns at once; a dispatcher
  * thread forms a batch whenever one of `streams` slots is free: the oldest
  * waiting request plus later requests for the same operator, in arrival order,
- * while the batch has at most max_batch_rhs columns and the bytes of all
- * batches in flight (solve workspace + batch input/output) stay within
- * mem_budget (0: no budget).  The batch runs as one fio_approx_solve on the
- * slot's stream (replayed from a captured hipGraph when use_graphs != 0);
+ * while the batch fits the slot's memory.  Each slot owns one device arena,
+ * allocated at the first submission and shared by all operators: mem_budget /
+ * streams bytes (0: the largest batch of any operator at max_batch_rhs
+ * columns).  A batch of w columns needs its input and output blocks (2 N w
+ * complex entries) plus the solve workspace for w columns; the widest w that
+ * fits the arena bounds every batch of that operator (memory-based admission),
+ * and the arenas take at most mem_budget bytes of device memory (captured
+ * graphs add the runtime's own bookkeeping, a few MB each).  A request wider than
+ * that returns FIO_ERR_ARG at submission, as does a budget too small for one
+ * column.  The batch runs as one fio_approx_solve on the slot's stream
+ * (replayed from a captured hipGraph when use_graphs != 0; the arena addresses
+ * depend only on the slot, operator and width, so the graphs stay valid).
  * U must be complete (the work producing it finished) when it is submitted;
  * batches on different slots overlap on the device.  Every column is solved
  * independently, so with a fixed refinement step count (solve mode DIRECT, or
  * IR with rel_res_tol <= 0, which add_operator requires) a request's result is
  * bitwise the same alone and in any batch.  U must stay valid and F untouched
  * until the request completes (fio_server_wait_all).  Times are seconds since
- * fio_server_create.
+ * fio_server_create.  add_operator is accepted only before the first submission.
  * ------------------------------------------------------------------------- */
 typedef struct fio_server_s *fio_server_t;
 typedef struct {
     int max_batch_rhs;     /* columns per batch */
     int streams;           /* concurrent batch slots (1..8) */
-    size_t mem_budget;     /* bytes of batches in flight; 0 = unlimited */
+    size_t mem_budget;     /* device bytes of all slot arenas; 0 = one widest batch per slot */
     int use_graphs;        /* replay captured hipGraphs per (operator, batch width) */
     int width_bucket;      /* > 1: batch widths rounded up to a multiple (zero columns appended), and
                               with use_graphs every (slot, operator, width) graph is captured when the

@@ -14,7 +14,7 @@ import numpy as np
 from . import _lib
 from ._lib import (FIO_PREC_FP64, FIO_PREC_FP32, FIO_PREC_SPLIT_FP16, FIO_SOLVE_DIRECT, FIO_SOLVE_IR,
                    FIO_SOLVE_PCG, FIO_AMP_ONE, FIO_AMP_GAUSSIAN_SUM, FIO_AMP_HANKEL, FIO_PHASE2_ANISO,
-                   FIO_PHASE2_ISO, FioError)
+                   FIO_PHASE2_ISO, FIO_WARN_RANK_CAP, FioError)
 
 __all__ = ["BF", "HSS", "ULV", "approx_solve", "colmajor", "empty", "FIO_PREC_FP64", "FIO_PREC_FP32",
            "FIO_PREC_SPLIT_FP16", "FIO_SOLVE_DIRECT", "FIO_SOLVE_IR", "FIO_SOLVE_PCG", "FIO_AMP_ONE",
@@ -49,6 +49,25 @@ def colmajor(x):
         x = x.t().contiguous().t()
     ld = x.stride(1) if k > 1 else n
     return x, ld
+
+
+def require_colmajor(x, n, what):
+    """Checks, without copying, that x is an (n, k) complex128 CUDA tensor in column-major layout
+    with leading dimension >= n, and returns (x, ld).  Used for buffers the library writes (out=)
+    or reads after the call returns (the server), where a silent copy would lose the data or free
+    it while the GPU still uses it."""
+    torch = _torch()
+    if not isinstance(x, torch.Tensor) or x.dtype != torch.complex128 or not x.is_cuda:
+        raise TypeError("%s: complex128 CUDA tensor required" % what)
+    if x.dim() == 1:
+        x = x.reshape(-1, 1)
+    if x.dim() != 2 or x.shape[0] != n:
+        raise TypeError("%s: shape (%d, k) required, got %s" % (what, n, tuple(x.shape)))
+    k = x.shape[1]
+    if not (x.stride(0) == 1 and (k == 1 or x.stride(1) >= n)):
+        raise TypeError("%s: column-major layout required (stride(0) == 1, stride(1) >= %d); "
+                        "use paper_2609_11520_amd.empty or colmajor()" % (what, n))
+    return x, (x.stride(1) if k > 1 else n)
 
 
 def empty(n, k, device="cuda"):
@@ -121,8 +140,9 @@ class BF:
     def _apply(self, fn, X, prec, out, ws):
         X, ldx = colmajor(X)
         k = X.shape[1]
-        Y = empty(self.n, k) if out is None else out
-        Y, ldy = colmajor(Y)
+        Y, ldy = require_colmajor(empty(self.n, k) if out is None else out, self.n, "out")
+        if Y.shape[1] != k:
+            raise TypeError("out: %d columns required" % k)
         if ws is None:
             ws = _workspace(self.workspace_size(k, prec))
         st = fn(self.h, _ptr(X), ldx, _ptr(Y), ldy, k, prec, _ptr(ws), ws.numel(), _stream())
@@ -166,8 +186,9 @@ def permute2d(n, X, to_internal=True, out=None):
     library's Morton order of an n x n grid."""
     X, ldx = colmajor(X)
     k = X.shape[1]
-    Y = empty(n * n, k) if out is None else out
-    Y, ldy = colmajor(Y)
+    Y, ldy = require_colmajor(empty(n * n, k) if out is None else out, n * n, "out")
+    if Y.shape[1] != k:
+        raise TypeError("out: %d columns required" % k)
     _lib.check(lib().fio_permute2d(n, 1 if to_internal else 0, _ptr(X), ldx, _ptr(Y), ldy, k, _stream()),
                "fio_permute2d")
     return Y
@@ -332,8 +353,9 @@ class ULV:
     def solve(self, Y, out=None, ws=None):
         Y, ldy = colmajor(Y)
         k = Y.shape[1]
-        Cm = empty(self.n, k) if out is None else out
-        Cm, ldc = colmajor(Cm)
+        Cm, ldc = require_colmajor(empty(self.n, k) if out is None else out, self.n, "out")
+        if Cm.shape[1] != k:
+            raise TypeError("out: %d columns required" % k)
         if ws is None:
             ws = _workspace(self.workspace_size(k))
         _lib.check(lib().hss_ulv_solve(self.h, _ptr(Y), ldy, _ptr(Cm), ldc, k, _ptr(ws), ws.numel(), _stream()),
@@ -359,8 +381,9 @@ def approx_solve(bf, ulv, U, mode=FIO_SOLVE_DIRECT, prec=FIO_PREC_FP64, rel_res_
     the normal equation (mode PCG, max_ir = iteration limit)."""
     U, ldu = colmajor(U)
     k = U.shape[1]
-    F = empty(bf.n, k) if out is None else out
-    F, ldf = colmajor(F)
+    F, ldf = require_colmajor(empty(bf.n, k) if out is None else out, bf.n, "out")
+    if F.shape[1] != k:
+        raise TypeError("out: %d columns required" % k)
     o = _lib.SolveOpts(mode, prec, rel_res_tol, max_ir)
     if ws is None:
         ws = _workspace(solve_workspace_size(bf, ulv, k, mode, prec, rel_res_tol, max_ir))
@@ -424,6 +447,7 @@ class Server:
         _lib.check(lib().fio_server_create(C.byref(o), C.byref(h)), "fio_server_create")
         self.h = h
         self._keep = []
+        self._n = {}
 
     def add_operator(self, bf, ulv, mode=FIO_SOLVE_IR, prec=FIO_PREC_FP32, max_ir=1):
         o = _lib.SolveOpts(mode, prec, 0.0, max_ir)
@@ -431,12 +455,20 @@ class Server:
         _lib.check(lib().fio_server_add_operator(self.h, bf.h, ulv.h, C.byref(o), C.byref(op)),
                    "fio_server_add_operator")
         self._keep.append((bf, ulv))
+        self._n[op.value] = bf.n
         return op.value
 
     def submit(self, op, U, F):
-        """Queues F <- solve(U); U and F are column-major (N, k) device tensors kept alive by the caller."""
-        U, ldu = colmajor(U)
-        F, ldf = colmajor(F)
+        """Queues F <- solve(U).  U and F must already be column-major (N, k) device tensors with
+        ld >= N (TypeError otherwise: the server reads U and writes F on its own streams after
+        submit returns, so no temporary copy may stand in for them).  The caller keeps both alive
+        until the request completes and makes U's contents ready first (the server's streams are
+        not ordered after torch's: synchronize after writing U)."""
+        n = self._n[op]
+        U, ldu = require_colmajor(U, n, "U")
+        F, ldf = require_colmajor(F, n, "F")
+        if F.shape[1] != U.shape[1]:
+            raise TypeError("U and F must have the same number of columns")
         rid = C.c_longlong()
         _lib.check(lib().fio_server_submit(self.h, op, _ptr(U), ldu, _ptr(F), ldf, U.shape[1], C.byref(rid)),
                    "fio_server_submit")

@@ -1,16 +1,26 @@
 // Continuous-batching solve server.  Several operators (BF + ULV factors) stay
 // resident; requests (a block of right-hand sides for one operator) arrive at
 // any time and are queued.  A dispatcher forms a batch whenever a stream slot
-// is free: it takes the oldest waiting request, adds later requests for the same
-// operator in arrival order while the batch stays within max_batch_rhs columns
-// and the in-flight memory budget, gathers their columns into the slot's batch
-// buffer, runs one fio_approx_solve on the batch (optionally replayed from a
-// captured hipGraph) and scatters the solutions back.  Batches on different
-// slots overlap on the device.  Every column of a batch is solved independently
+// is free: it takes the oldest waiting request and adds later requests for the
+// same operator in arrival order while the batch's memory (batch input and
+// output blocks plus the solve workspace for its width) fits the slot's arena,
+// gathers their columns into the arena, runs one fio_approx_solve on the batch
+// (optionally replayed from a captured hipGraph) and scatters the solutions
+// back.  Batches on different slots overlap on the device.
+//
+// Memory: each slot owns one device arena, shared by all operators (a slot runs
+// one batch at a time), allocated when serving starts: mem_budget / streams
+// bytes, or, with no budget, the largest batch of any operator.  A batch of
+// width w for operator op lays out U at offset 0, F next, the workspace last, so
+// the addresses depend only on (slot, op, w) and captured graphs stay valid.
+// The widest batch an operator can take is the widest that fits the arena:
+// that is the memory-based admission, and the device memory the server holds
+// never exceeds the budget.  Every column of a batch is solved independently
 // by the kernels, so with a fixed refinement step count a request's result does
 // not depend on the batch it travels in.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -36,7 +46,7 @@ struct Operator {
     hss_ulv_t ulv;
     fio_solve_opts opts;
     long n;
-    size_t ws_max;       // workspace for max_batch_rhs columns
+    int max_width;       // widest batch that fits a slot's arena (set when serving starts)
 };
 
 struct Request {
@@ -55,7 +65,7 @@ struct Request {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    std::vector<fio::DevBuf *> Ub, Fb, ws;   // per operator
+    fio::DevBuf *arena = nullptr;              // U, F and workspace of the running batch
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;   // (op, nrhs) -> captured solve
     bool busy = false;
     std::vector<long long> reqs;
@@ -71,6 +81,7 @@ struct fio_server_s {
     int max_batch = 64;
     int bucket = 1;                   // batch widths are rounded up to a multiple of this
     size_t budget = 0;
+    size_t slot_bytes = 0;            // arena bytes per slot
     bool graphs = false;
     clk::time_point t0;
     std::vector<Operator> ops;
@@ -98,18 +109,39 @@ struct fio_server_s {
 
 namespace {
 
-size_t batch_bytes(const Operator &op, int nrhs) {
-    size_t ws = 0;
-    fio_solve_workspace_size(op.bf, op.ulv, nrhs, &op.opts, &ws);
-    return ws + 2 * (size_t)op.n * nrhs * sizeof(double2);
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// arena layout of a batch of `nrhs` columns: U at 0, F at f_off, workspace at ws_off
+struct Layout {
+    size_t f_off, ws_off, ws, total;
+};
+
+Layout layout(const Operator &op, int nrhs) {
+    Layout l;
+    const size_t blk = align256((size_t)op.n * nrhs * sizeof(double2));
+    l.ws = 0;
+    fio_solve_workspace_size(op.bf, op.ulv, nrhs, &op.opts, &l.ws);
+    l.f_off = blk;
+    l.ws_off = 2 * blk;
+    l.total = 2 * blk + align256(l.ws);
+    return l;
+}
+
+size_t batch_bytes(const Operator &op, int nrhs) { return layout(op, nrhs).total; }
+
+double2 *u_of(Slot &s) { return s.arena->as<double2>(); }
+double2 *f_of(Slot &s, const Operator &o, int nrhs) {
+    return reinterpret_cast<double2 *>(static_cast<char *>(s.arena->p) + layout(o, nrhs).f_off);
 }
 
 // Runs (or replays) the batched solve of `s` on its stream.
 fio_status run_solve(fio_server_s *S, Slot &s, int op, int nrhs, bool capture_only = false) {
     Operator &o = S->ops[op];
+    const Layout l = layout(o, nrhs);
+    char *base = static_cast<char *>(s.arena->p);
     auto call = [&]() {
-        return fio_approx_solve(o.bf, o.ulv, s.Ub[op]->p, o.n, s.Fb[op]->p, o.n, nrhs, &o.opts, nullptr,
-                                s.ws[op]->p, s.ws[op]->bytes, s.stream);
+        return fio_approx_solve(o.bf, o.ulv, base, o.n, base + l.f_off, o.n, nrhs, &o.opts, nullptr,
+                                base + l.ws_off, l.ws, s.stream);
     };
     if (!S->graphs) return call();
     auto key = std::make_pair(op, nrhs);
@@ -153,21 +185,16 @@ void dispatcher_loop(fio_server_s *S) {
         const int op = S->reqs[head].op;
         std::vector<long long> take;
         int cols = 0;
+        // memory-based admission: the batch (rounded up to the width bucket) must fit the slot's
+        // arena, i.e. at most max_width columns; submit() rejects requests wider than that
+        const int wmax = S->ops[op].max_width;
         for (long long id : S->queue) {
             Request &r = S->reqs[id];
             if (r.op != op) continue;
-            if (cols + r.nrhs > S->max_batch) continue;
             const int w = ((cols + r.nrhs + S->bucket - 1) / S->bucket) * S->bucket;
-            size_t b = batch_bytes(S->ops[op], w);
-            if (S->budget && S->in_flight + b > S->budget && !take.empty()) continue;
-            if (S->budget && S->in_flight + b > S->budget && S->in_flight > 0) continue;
+            if (w > wmax) continue;
             take.push_back(id);
             cols += r.nrhs;
-        }
-        if (take.empty()) {
-            // the oldest request does not fit next to the batches in flight: wait for a completion
-            S->cv.wait(lk);
-            continue;
         }
         for (long long id : take)
             for (auto it = S->queue.begin(); it != S->queue.end(); ++it)
@@ -199,22 +226,23 @@ void dispatcher_loop(fio_server_s *S) {
         const long n = S->ops[op].n;
         fio_status st = FIO_OK;
         int c = 0;
+        double2 *Ub = u_of(s), *Fb = f_of(s, S->ops[op], width);
         for (auto &r : local) {
-            if (hipMemcpy2DAsync(s.Ub[op]->as<double2>() + (size_t)c * n, n * sizeof(double2), r.U,
+            if (hipMemcpy2DAsync(Ub + (size_t)c * n, n * sizeof(double2), r.U,
                                  r.ldu * sizeof(double2), n * sizeof(double2), r.nrhs, hipMemcpyDeviceToDevice,
                                  s.stream) != hipSuccess)
                 st = FIO_ERR_HIP;
             c += r.nrhs;
         }
         if (st == FIO_OK && width > cols &&
-            hipMemsetAsync(s.Ub[op]->as<double2>() + (size_t)cols * n, 0, (size_t)(width - cols) * n * sizeof(double2),
+            hipMemsetAsync(Ub + (size_t)cols * n, 0, (size_t)(width - cols) * n * sizeof(double2),
                            s.stream) != hipSuccess)
             st = FIO_ERR_HIP;
         if (st == FIO_OK) st = run_solve(S, s, op, width);
         c = 0;
         for (auto &r : local) {
             if (st == FIO_OK &&
-                hipMemcpy2DAsync(r.F, r.ldf * sizeof(double2), s.Fb[op]->as<double2>() + (size_t)c * n,
+                hipMemcpy2DAsync(r.F, r.ldf * sizeof(double2), Fb + (size_t)c * n,
                                  n * sizeof(double2), n * sizeof(double2), r.nrhs, hipMemcpyDeviceToDevice,
                                  s.stream) != hipSuccess)
                 st = FIO_ERR_HIP;
@@ -284,45 +312,59 @@ extern "C" fio_status fio_server_add_operator(fio_server_t S, fio_bf_t bf, hss_u
     FIO_CHECK_ARG(S && bf && ulv && opts && op_id && !S->started);
     FIO_CHECK_ARG(opts->mode == FIO_SOLVE_DIRECT || (opts->mode == FIO_SOLVE_IR && opts->rel_res_tol <= 0.0));
     Operator o{bf, ulv, *opts, bf->N, 0};
-    return guarded([&] {
-        o.ws_max = 0;
-        fio_status st = fio_solve_workspace_size(bf, ulv, S->max_batch, opts, &o.ws_max);
-        if (st != FIO_OK) return st;
-        const int id = (int)S->ops.size();
-        S->ops.push_back(o);
-        for (auto &s : S->slots) {
-            s.Ub.push_back(new DevBuf((size_t)o.n * S->max_batch * sizeof(double2)));
-            s.Fb.push_back(new DevBuf((size_t)o.n * S->max_batch * sizeof(double2)));
-            s.ws.push_back(new DevBuf(o.ws_max));
-        }
-        *op_id = id;
-        return FIO_OK;
-    });
+    size_t ws = 0;
+    fio_status st = fio_solve_workspace_size(bf, ulv, S->max_batch, opts, &ws);
+    if (st != FIO_OK) return st;
+    *op_id = (int)S->ops.size();
+    S->ops.push_back(o);
+    return FIO_OK;
 }
 
-static void start(fio_server_s *S) {
-    if (S->started) return;
+// Sizes and allocates the slot arenas and fixes each operator's widest batch (once, at the
+// first submission).  Returns FIO_ERR_ARG when the budget cannot hold a one-column batch of
+// some operator.
+static fio_status start(fio_server_s *S) {
+    if (S->started) return FIO_OK;
+    if (S->ops.empty()) return FIO_ERR_ARG;
+    const int step = S->bucket;
+    size_t widest = 0;
+    for (auto &o : S->ops) widest = std::max(widest, batch_bytes(o, S->max_batch));
+    S->slot_bytes = S->budget ? S->budget / S->slots.size() : widest;
+    for (auto &o : S->ops) {
+        o.max_width = 0;
+        for (int w = step; w <= S->max_batch; w += step)
+            if (batch_bytes(o, w) <= S->slot_bytes) o.max_width = w;
+        if (o.max_width == 0) return FIO_ERR_ARG;
+    }
+    fio_status st = guarded([&] {
+        for (auto &s : S->slots) s.arena = new DevBuf(S->slot_bytes);
+        return FIO_OK;
+    });
+    if (st != FIO_OK) return st;
     S->started = true;
     if (S->graphs && S->bucket > 1) {
         // capture every (slot, operator, bucketed width) up front: nothing is captured while serving
         for (auto &s : S->slots)
             for (int op = 0; op < (int)S->ops.size(); ++op)
-                for (int w = S->bucket; w <= S->max_batch; w += S->bucket)
+                for (int w = step; w <= S->ops[op].max_width; w += step)
                     if (run_solve(S, s, op, w, true) != FIO_OK) S->error = FIO_ERR_HIP;
     }
     S->slot_batches.assign(S->slots.size(), {});
     for (size_t i = 0; i < S->slots.size(); ++i) S->slot_cv.emplace_back(new std::condition_variable());
     S->dispatcher = std::thread(dispatcher_loop, S);
     for (size_t i = 0; i < S->slots.size(); ++i) S->completers.emplace_back(completer_loop, S, (int)i);
+    return FIO_OK;
 }
 
 extern "C" fio_status fio_server_submit(fio_server_t S, int op, const void *U, long ldu, void *F, long ldf, int nrhs,
                                         long long *req_id) {
     FIO_CHECK_ARG(S && U && F && req_id && op >= 0 && op < (int)S->ops.size());
     FIO_CHECK_ARG(nrhs >= 1 && nrhs <= S->max_batch && ldu >= S->ops[op].n && ldf >= S->ops[op].n);
-    if (S->budget) FIO_CHECK_ARG(batch_bytes(S->ops[op], nrhs) <= S->budget);
     std::lock_guard<std::mutex> lk(S->mu);
-    start(S);
+    const fio_status st = start(S);
+    if (st != FIO_OK) return st;
+    // a request wider than the widest batch that fits a slot's share of the budget
+    FIO_CHECK_ARG(((nrhs + S->bucket - 1) / S->bucket) * S->bucket <= S->ops[op].max_width);
     Request r;
     r.id = S->next_id++;
     r.op = op;
@@ -395,9 +437,7 @@ extern "C" void fio_server_destroy(fio_server_t S) {
     }
     for (auto &s : S->slots) {
         for (auto &kv : s.graphs) (void)hipGraphExecDestroy(kv.second);
-        for (auto *b : s.Ub) delete b;
-        for (auto *b : s.Fb) delete b;
-        for (auto *b : s.ws) delete b;
+        delete s.arena;
         if (s.done) (void)hipEventDestroy(s.done);
         if (s.stream) (void)hipStreamDestroy(s.stream);
     }

@@ -5,7 +5,7 @@ import pytest
 import fio_inputs as fi
 from oracle import hss as ohss
 from oracle import ulv as oulv
-from gpu_common import fiohss, dev, host, rel, step, oracle_bf, oracle_hss, gpu_bf, hss_generators, omega_np
+from gpu_common import fiohss, dev, host, perr, step, oracle_bf, oracle_hss, gpu_bf, hss_generators, omega_np
 
 pytestmark = pytest.mark.gpu
 
@@ -18,18 +18,18 @@ def test_imported_hss_matvec_and_ulv_solve_match_oracle():
     ranks, gen = hss_generators(h)
     H = F.HSS.from_generators(n, 64, ranks, gen)
     x = fi.complex_gaussian(5, fi.PURPOSE_PROBE, n, 7)
-    assert rel(host(H.matvec(dev(x))), ohss.matvec(h, x)) < 1e-13
+    assert perr(host(H.matvec(dev(x))), ohss.matvec(h, x)) < 1e-13
     r2, g2 = H.export()
     assert np.array_equal(r2, ranks) and np.array_equal(g2, gen)
     step("ULV on imported HSS")
     U = F.ULV(H)
     c = host(U.solve(dev(x)))
     ref = oulv.solve(fac, x)
-    assert rel(c, ref) < 1e-12
+    assert perr(c, ref) < 1e-12
     # in-place solve
     xd = dev(x)
     U.solve(xd, out=xd)
-    assert rel(host(xd), ref) < 1e-12
+    assert perr(host(xd), ref) < 1e-12
 
 
 def test_gpu_hss_build_matches_oracle_with_identical_inputs():
@@ -41,11 +41,11 @@ def test_gpu_hss_build_matches_oracle_with_identical_inputs():
     H = F.HSS.from_bf(B, tol=1e-3, p=10, omega=F.omega_from(omega_np(1000)))
     assert H.ranks() == {l: list(v) for l, v in h.rank.items()}
     x = fi.complex_gaussian(6, fi.PURPOSE_PROBE, n, 3)
-    assert rel(host(H.matvec(dev(x))), ohss.matvec(h, x)) < 1e-12
+    assert perr(host(H.matvec(dev(x))), ohss.matvec(h, x)) < 1e-12
     r, g = H.export()
     r0, g0 = hss_generators(h)
     assert np.array_equal(r, r0)
-    assert rel(g, g0) < 1e-11
+    assert perr(g, g0) < 1e-11
 
 
 def test_exact_recovery_with_dense_matvec_on_gpu():
@@ -58,13 +58,13 @@ def test_exact_recovery_with_dense_matvec_on_gpu():
     Hd = dev(Hm)
     H = F.HSS.from_samples(n, lambda X: Hd @ X, tol=1e-13, p=5, omega=F.omega_from(omega_np(21)))
     x = fi.complex_gaussian(3, fi.PURPOSE_PROBE, n, 2)
-    assert rel(host(H.matvec(dev(x))), Hm @ x) < 1e-11
+    assert perr(host(H.matvec(dev(x))), Hm @ x) < 1e-11
     # same answer as the oracle construction with the same test matrices
     ho = ohss.build(n, lambda X: Hm @ X, omega_np(21), tol=1e-13, p=5)
     assert H.ranks() == {l: list(v) for l, v in ho.rank.items()}
     U = F.ULV(H)
     y = host(U.solve(dev(x)))
-    assert rel(Hm @ y, x) < 1e-11
+    assert perr(Hm @ y, x) < 1e-11
 
 
 def test_rank_edge_cases_on_gpu():
@@ -77,12 +77,12 @@ def test_rank_edge_cases_on_gpu():
     H = F.HSS.from_samples(n, lambda X: Hd @ X, tol=1e-14, p=5, omega=F.omega_from(omega_np(24)))
     assert H.ranks()[2] == [64] * 4 and H.ranks()[1] == [128, 128]
     x = fi.complex_gaussian(9, fi.PURPOSE_PROBE, n, 2)
-    assert rel(Hm @ host(F.ULV(H).solve(dev(x))), x) < 1e-12
+    assert perr(Hm @ host(F.ULV(H).solve(dev(x))), x) < 1e-12
     Dm = np.diag(np.arange(1.0, n + 1)).astype(complex)
     Dd = dev(Dm)
     H0 = F.HSS.from_samples(n, lambda X: Dd @ X, tol=1e-3, p=5, omega=F.omega_from(omega_np(24)))
     assert all(max(v) == 0 for v in H0.ranks().values())
-    assert rel(Dm @ host(F.ULV(H0).solve(dev(x))), x) < 1e-13
+    assert perr(Dm @ host(F.ULV(H0).solve(dev(x))), x) < 1e-13
 
 
 def test_not_hpd_reported():
@@ -97,3 +97,25 @@ def test_not_hpd_reported():
     with pytest.raises(F.FioError) as e:
         F.ULV(H)
     assert e.value.status == -4
+
+
+def test_rank_cap_reports_warning():
+    # a full-rank Hermitian matrix (random A A^* + n I) at tolerance 1e-14 needs ranks m at every
+    # node; a cap of 8 truncates them, the build returns FIO_WARN_RANK_CAP and every rank is <= 8,
+    # and the capped HSS is still a valid (less accurate) Hermitian operator
+    F = fiohss()
+    n = 256
+    step("rank cap")
+    A = fi.complex_gaussian(5, fi.PURPOSE_DATA, n, n)
+    Hm = A @ A.conj().T + n * np.eye(n)
+    Hd = dev(Hm)
+    H = F.HSS.from_samples(n, lambda X: Hd @ X, tol=1e-14, p=5, rank_cap=8, omega=F.omega_from(omega_np(24)))
+    assert H.status == F.FIO_WARN_RANK_CAP
+    assert all(max(v) <= 8 for v in H.ranks().values())
+    assert max(max(v) for v in H.ranks().values()) == 8
+    x = fi.complex_gaussian(9, fi.PURPOSE_PROBE, n, 2)
+    y = host(H.matvec(dev(x)))
+    assert np.all(np.isfinite(y))
+    # uncapped: full ranks, no warning
+    H2 = F.HSS.from_samples(n, lambda X: Hd @ X, tol=1e-14, p=5, omega=F.omega_from(omega_np(24)))
+    assert H2.status == 0
