@@ -369,6 +369,22 @@ fio_status fio_approx_solve(fio_bf_t bf, hss_ulv_t f, const void *U, long ldu, v
                             int nrhs, const fio_solve_opts *opts, fio_solve_info *info,
                             void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate (code under hipGraph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): fio_approx_solve with the workspace taken from a
+ * file-scope device array of fio_approx_solve_static_max_bytes() bytes (64 MiB), one per
+ * GPU, held until the process ends; the call allocates nothing, on the device or the host.
+ * Same arguments and results as fio_approx_solve without ws / ws_bytes; the array of the
+ * current device is used, so the current device must be the one that `stream` runs on.
+ * Returns FIO_ERR_ARG (with a message on stderr) when the solve needs more workspace than
+ * the array holds (fio_solve_workspace_size tells the need), and for the residual-checked
+ * forms (IR or PCG with rel_res_tol > 0, which read norms back into host memory).  Every
+ * call on a GPU shares that GPU's array: calls that overlap in time on one GPU (other
+ * streams, other threads) race; the array's contents left by a call are not used by the
+ * next (nothing in it must start at zero). */
+size_t fio_approx_solve_static_max_bytes(void);
+fio_status fio_approx_solve_static(fio_bf_t bf, hss_ulv_t f, const void *U, long ldu, void *F, long ldf,
+                                   int nrhs, const fio_solve_opts *opts, fio_solve_info *info, void *stream);
+
 const char *fio_status_str(fio_status s);
 
 /* ---------------------------------------------------------------------------

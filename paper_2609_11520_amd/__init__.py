@@ -395,6 +395,26 @@ def approx_solve(bf, ulv, U, mode=FIO_SOLVE_DIRECT, prec=FIO_PREC_FP64, rel_res_
     return F, inf
 
 
+def approx_solve_static(bf, ulv, U, mode=FIO_SOLVE_DIRECT, prec=FIO_PREC_FP64, max_ir=0, out=None, info=None):
+    """fio_approx_solve_static: approx_solve with a fixed step count and the workspace taken from the
+    library's static per-GPU scratch array (no allocation in the library; `out` must be given, or
+    one is allocated here by torch before the call)."""
+    U, ldu = colmajor(U)
+    k = U.shape[1]
+    F, ldf = require_colmajor(empty(bf.n, k) if out is None else out, bf.n, "out")
+    if F.shape[1] != k:
+        raise TypeError("out: %d columns required" % k)
+    o = _lib.SolveOpts(mode, prec, 0.0, max_ir)
+    inf = _lib.SolveInfo() if info is None else info
+    _lib.check(lib().fio_approx_solve_static(bf.h, ulv.h, _ptr(U), ldu, _ptr(F), ldf, k, C.byref(o), C.byref(inf),
+                                             _stream()), "fio_approx_solve_static")
+    return F, inf
+
+
+def approx_solve_static_max_bytes():
+    return lib().fio_approx_solve_static_max_bytes()
+
+
 def timing_enable(on=True):
     lib().fio_timing_enable(1 if on else 0)
 

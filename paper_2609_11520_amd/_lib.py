@@ -83,6 +83,8 @@ PROTOS = {
     "hss_ulv_destroy": (None, [vp]),
     "fio_solve_workspace_size": (i32, [vp, vp, i32, C.POINTER(SolveOpts), C.POINTER(sz)]),
     "fio_approx_solve": (i32, [vp, vp, vp, lg, vp, lg, i32, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp, sz, vp]),
+    "fio_approx_solve_static_max_bytes": (sz, []),
+    "fio_approx_solve_static": (i32, [vp, vp, vp, lg, vp, lg, i32, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]),
     "fio_status_str": (C.c_char_p, [i32]),
     "fio_server_create": (i32, [C.POINTER(ServerOpts), C.POINTER(vp)]),
     "fio_server_add_operator": (i32, [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(i32)]),

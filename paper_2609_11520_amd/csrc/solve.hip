@@ -252,7 +252,7 @@ static fio_status pcg_impl(fio_bf_s *bf, hss_ulv_s *f, const double2 *U, long ld
     double2 *X = d2 ? XT : F;
     const long ldxx = d2 ? N : ldf;
     const bool measure = o->rel_res_tol > 0.0;
-    std::vector<double> hn(2 * nrhs);
+    std::vector<double> hn(measure ? 2 * nrhs : 0);   // host copy of the norms (only when measuring)
     if (info) {
         info->ir_steps = 0;
         info->rel_res = -1.0;
@@ -322,7 +322,7 @@ static fio_status solve_impl(fio_bf_s *bf, hss_ulv_s *f, const double2 *U, long 
         info->rel_res = -1.0;
     }
     if (o->mode != FIO_SOLVE_IR) return FIO_OK;
-    std::vector<double> hn(2 * nrhs);
+    std::vector<double> hn(o->rel_res_tol > 0.0 ? 2 * nrhs : 0);   // host copy of the norms (only when measuring)
     if (o->rel_res_tol > 0.0) colnorm2(U, ldu, N, nrhs, w.part, w.nrm + nrhs, s);
     for (int step = 0;; ++step) {
         const bool measure = o->rel_res_tol > 0.0;
@@ -391,6 +391,69 @@ extern "C" fio_status fio_approx_solve(fio_bf_t bf, hss_ulv_t f, const void *U, 
     if (opts->prec == FIO_PREC_SPLIT_FP16 && !bf->split16) return FIO_ERR_ARG;
     size_t need = solve_ws_bytes(bf, f, nrhs, opts);
     FIO_CHECK_ARG(ws && ws_bytes >= need);
+    return guarded([&] {
+        return solve_impl(bf, f, (const double2 *)U, ldu, (double2 *)F, ldf, nrhs, opts, info, ws, as_stream(stream));
+    });
+}
+
+// ---------------------------------------------------------------------------
+// The solve without any allocation: its workspace is a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code never passes the array's name (a host-side
+// stand-in) to a kernel: the device address comes from hipGetSymbolAddress, taken once per
+// device with that device current and kept per device.  Nothing in the workspace has to start
+// at zero (every solve writes each buffer before reading it), and calls that overlap on one GPU
+// share the array and race.
+namespace {
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+fio_status static_scratch(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return FIO_ERR_HIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            fprintf(stderr, "fiohss: hipGetSymbolAddress(scratch) failed on device %d: %s\n", dev,
+                    hipGetErrorString(e));
+            return FIO_ERR_HIP;
+        }
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return FIO_OK;
+}
+}  // namespace
+
+extern "C" size_t fio_approx_solve_static_max_bytes(void) { return kStaticScratchBytes; }
+
+extern "C" fio_status fio_approx_solve_static(fio_bf_t bf, hss_ulv_t f, const void *U, long ldu, void *F, long ldf,
+                                              int nrhs, const fio_solve_opts *opts, fio_solve_info *info,
+                                              void *stream) {
+    FIO_CHECK_ARG(bf && f && opts && nrhs >= 0);
+    if (nrhs == 0) return FIO_OK;
+    FIO_CHECK_ARG(U && F && U != F && ldu >= bf->N && ldf >= bf->N);
+    FIO_CHECK_ARG(opts->mode == FIO_SOLVE_DIRECT || opts->mode == FIO_SOLVE_IR || opts->mode == FIO_SOLVE_PCG);
+    FIO_CHECK_ARG(opts->mode != FIO_SOLVE_PCG || opts->prec == FIO_PREC_FP64);
+    FIO_CHECK_ARG(opts->prec >= FIO_PREC_FP64 && opts->prec <= FIO_PREC_SPLIT_FP16);
+    FIO_CHECK_ARG(opts->max_ir >= 0);
+    // a fixed step count: the residual-checked forms read norms back into host memory
+    FIO_CHECK_ARG(opts->mode == FIO_SOLVE_DIRECT || opts->rel_res_tol <= 0.0);
+    if (opts->prec == FIO_PREC_FP32 && !bf->f32.p) return FIO_ERR_ARG;
+    if (opts->prec == FIO_PREC_SPLIT_FP16 && !bf->split16) return FIO_ERR_ARG;
+    const size_t need = solve_ws_bytes(bf, f, nrhs, opts);
+    if (need > kStaticScratchBytes) {
+        fprintf(stderr, "fiohss: fio_approx_solve_static: %d columns at N = %ld need %zu bytes of workspace, "
+                        "more than its %zu-byte scratch array\n", nrhs, bf->N, need, kStaticScratchBytes);
+        return FIO_ERR_ARG;
+    }
+    void *ws = nullptr;
+    const fio_status st = static_scratch(&ws);
+    if (st != FIO_OK) return st;
     return guarded([&] {
         return solve_impl(bf, f, (const double2 *)U, ldu, (double2 *)F, ldf, nrhs, opts, info, ws, as_stream(stream));
     });
