@@ -4,21 +4,27 @@
 Workload (the headline configuration): 1D FIO, N = 2^18, Phi = x xi + c(x)|xi|,
 c(x) = (2 + sin 2 pi x)/16, q = 9 Chebyshev points, HSS tolerance 1e-3 with
 p = 10 oversampling, 64 right-hand sides u = K~ f with f complex Gaussian (seed 1).
-One step solves all 64 right-hand sides by iterative refinement with the number of
-steps calibrated once per operator (the residual-checked solve that stops at a
-relative residual of 5e-9 fixes it during warm-up; it is timed and reported too);
-the relative error of every column of f^ against f is checked after the timed
-region and must be below 1e-8:
+One step solves all 64 right-hand sides by iterative refinement with a step count
+fixed beforehand by the residual-checked solve (relative residual 5e-9) of a held-out
+block (seed 2); the residual-checked solve of the timed block is timed and reported
+too.  The relative error of every column of f^ against f is checked after the timed
+region and must be below 1e-8 (`accuracy_ok`; a path that misses it is not chosen
+as the headline, and the run exits with status 3 if the headline misses it):
   fp64  : K~^* and K~ applied in FP64;
   mixed : K~^* applied in FP32 (FP32 factors and coefficients), residual K~ f and
           the ULV solve in FP64;
   split16: as mixed, with the transfer factors of K~^* applied on the matrix cores
           in split FP16 (hi + lo halves, FP32 accumulation).
 `value` is the faster mixed path's RHS/s (64 / seconds per step; `config.mixed_variant`
-names it); the FP64 path and the other mixed path are reported beside it.  Offline work (BF, HSS and ULV construction) happens before
-the timed region; inputs are resident in HBM when it starts.
+names it); the FP64 path and the other mixed path are reported beside it.  Offline work
+(BF, HSS and ULV construction) happens before the timed region; inputs are resident in
+HBM when it starts.  Also reported: `roofline` (explicit-form work of the dominant
+kernel against the published peaks, spill and counter traffic beside it), the serving
+workload in split-FP16 and FP64 at 200 requests/s and at a saturating rate, the N = 2^16
+direct FP64 solve (with c = 0), the 2D and variable-amplitude workloads, and the oracle
+timed on the host (`cpu_baseline`).
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-serve] ...
 """
 import argparse
 import json
@@ -34,10 +40,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP16_MFMA_PEAK_TFLOPS = 2500.0 # MI355X dense FP16 matrix (no sparsity)
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector
-# FP32 vector without packed-FP32 instructions (which every kernel here is compiled without):
-# 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz; the 157.3 TFLOP/s datasheet figure
-# counts packed FP32
-FP32_PEAK_TFLOPS = 78.6
+# MI355X FP32 vector, published (it counts packed FP32: 2 lanes per instruction).  Every kernel here
+# is compiled without packed FP32, which caps what they can reach at half of it:
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s.
+FP32_PEAK_TFLOPS = 157.3
+FP32_NONPACKED_TFLOPS = 78.6
 METRIC = "RHS solved/s at N=2^18, rel err 1e-8: FP64 vs mixed; p50/p99 latency"
 
 
@@ -99,113 +106,188 @@ def pass_plan(n, kmax=3):
 
 
 def kernel_model(name, n, q, k):
-    """Average algorithmic (bytes, flops) per launch of the dominant kernel kinds.
+    """Algorithmic work per launch of the butterfly kernels, by the explicit-factor count:
+    (bytes, flops, spill_bytes, peak_tflops).
 
-    bf_struct_*: one structured pass = read and write the N q k coefficients once, read the
-    8q twiddles of every group of each of its levels (and the q x q middle blocks when it applies
-    M); per group and column 4 quadrants of q complex scalings, a real q x q product and q complex
-    multiply-adds (6q + 4q^2 + 8q flops each), plus 8 q^2 flops per pair for M."""
-    es = 16 if name.endswith("f64") else 8
-    if name == "bf_split16":
-        # one split pass: FP32 coefficients read and written once, the hi/lo block planes of
-        # every group of each level (2880 bytes; the middle factor is folded into them); per
-        # group and column three real 36 x 36 products (the complex 18 x 18 block)
-        plan = pass_plan(n)
-        byts = flops = 0.0
-        for kl, epi in plan:
-            byts += 2 * n * q * k * 8 + kl * (n // 2) * 2880
-            flops += kl * (n // 2) * k * 3 * 2 * (4 * q) ** 2
-        return byts / len(plan), flops / len(plan)
-    if name.startswith("bf_struct"):
-        plan = pass_plan(n)
-        byts = flops = 0.0
-        for kl, epi in plan:
-            byts += 2 * n * q * k * es + kl * (n // 2) * 8 * q * es + (n * q * q * es if epi else 0)
-            flops += kl * (n // 2) * k * 4 * (14 * q + 4 * q * q) + (8.0 * n * q * q * k if epi else 0)
-        return byts / len(plan), flops / len(plan)
+    The method's work is the product with the explicit factors of eq. bf: every entry read once
+    per apply (16 B in FP64, 8 B in FP32 or as split-FP16 hi + lo halves) and a complex
+    multiply-add (8 flops) per entry and column; the three split products count 3 x 8.  A
+    structured pass (3 transfer levels of (N/2) 4q^2 entries each, plus M's N q^2 on the pass that
+    applies it) is charged those entries whatever form the kernel reads them in.  The N x k
+    vectors read and written by an apply (2 N k 16 B) belong to its leaf kernels; the per-pass
+    round trip of the coefficient block (2 N q k e) is an implementation cost, reported apart as
+    spill_bytes."""
+    e = 16 if name.endswith("f64") else 8
+    plan = pass_plan(n)
+    transfer = (n // 2) * 4 * q * q              # entries of one transfer level
+    mid = n * q * q
+    if name == "bf_split16" or name.startswith("bf_struct"):
+        ent = sum(kl * transfer + (mid if epi else 0) for kl, epi in plan) / len(plan)
+        mult = 3 if name == "bf_split16" else 1
+        peak = FP16_MFMA_PEAK_TFLOPS if name == "bf_split16" else (
+            FP64_PEAK_TFLOPS if e == 16 else FP32_PEAK_TFLOPS)
+        return ent * e, mult * 8.0 * ent * k, 2.0 * n * q * k * (8 if name == "bf_split16" else e), peak
     if name.startswith("bf_transfer"):
-        groups = n // 2
-        return groups * (2 * q) ** 2 * es + 2 * n * q * k * es, 8.0 * groups * (2 * q) ** 2 * k
+        return transfer * e, 8.0 * transfer * k, 2.0 * n * q * k * e, FP64_PEAK_TFLOPS if e == 16 else FP32_PEAK_TFLOPS
     return None
 
 
-def cpu_baseline(n, q, nrhs_gpu, ir_steps):
-    """The oracle (as it stands) timed on the host: one right-hand side of the same workload."""
-    import resource
-    from oracle import bf as obf, fio as ofio, hss as ohss, ulv as oulv
+def roofline_of(name, n, q, k, avg_ms, traffic):
+    """The roofline record of one kernel: bound = the larger of the explicit-factor byte and flop
+    times at the published peaks; frac = bound time / measured time."""
+    m = kernel_model(name, n, q, k)
+    if m is None:
+        return None
+    byts, flops, spill, peak = m
+    t_mem, t_alu = byts / (HBM_PEAK_GBS * 1e9), flops / (peak * 1e12)
+    if t_mem >= t_alu:
+        ach = byts / (avg_ms * 1e-3) / 1e9
+        r = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(ach / HBM_PEAK_GBS, 4)}
+    else:
+        ach = flops / (avg_ms * 1e-3) / 1e12
+        r = {"bound": "mfma" if name == "bf_split16" else "alu", "achieved": round(ach, 2), "peak": peak,
+             "unit": "TFLOP/s", "frac": round(ach / peak, 4)}
+    r.update({"traffic": traffic, "kernel": name, "avg_launch_ms": round(avg_ms, 4),
+              "algorithmic_bytes_per_launch": int(byts), "algorithmic_flops_per_launch": float(flops),
+              "spill_bytes_per_launch": int(spill),
+              "achieved_with_spill_gbs": round((byts + spill) / (avg_ms * 1e-3) / 1e9, 1),
+              "traffic_over_algorithmic": None if traffic is None else round(traffic / byts, 3)})
+    if name.endswith("f32"):
+        r["fp32_nonpacked_peak"] = FP32_NONPACKED_TFLOPS
+    return r
+
+
+def host_info():
+    """Host CPU model and thread count (what lscpu and nproc report)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    return {"cpu_model": model, "nproc": nproc, "logical_cpus": os.cpu_count()}
+
+
+def cpu_baseline(n, q, nrhs_gpu, ir_steps, ranks, repeats=3):
+    """The oracle as it stands timed on the host: its FP64 refinement solve (oracle.solve.refine:
+    f = F K~^* u, then `ir_steps` steps of f += F K~^*(u - K~ f)) of one of the benchmark's
+    right-hand sides (column 0 of the same seeded f, u = K~ f with the oracle's own factors of the
+    same operator), the median of `repeats` runs after one warm-up, on all host cores and on one.
+    The ULV factors come from HSS generators with the tree and per-node ranks of the GPU
+    construction and seeded entries (the oracle's own HSS construction of this operator takes
+    hours on the host); a ULV solve's cost depends only on those shapes."""
+    from threadpoolctl import threadpool_limits
+    from oracle import bf as obf, fio as ofio, ulv as oulv, solve as osolve
     import fio_inputs as fi
     log("cpu baseline: building the oracle factors (untimed)")
     B = obf.BF1D(n, q, ofio.PHASE_SIN16)
     f = fi.rhs(1, n, 1)
     u = B.apply(f)
-    # ULV solve on generators of the same tree shape (rank 4 at every node, the ranks the
-    # oracle finds at tolerance 1e-3 for this operator); only the solve is timed
-    h = synthetic_hss(n, 64, 4)
-    fac = oulv.factor(h)
-    t0, c0 = time.perf_counter(), time.process_time()
-    x = oulv.solve(fac, B.apply_adj(u))
-    for _ in range(ir_steps):
-        r = u - B.apply(x)
-        x = x + oulv.solve(fac, B.apply_adj(r))
-    wall = time.perf_counter() - t0
-    cpu = time.process_time() - c0
-    cores = max(1, int(round(cpu / wall)))
-    return {"value": 1.0 / wall, "unit": "RHS/s", "cores": cores, "kind": "oracle",
-            "sample": "oracle FP64 refinement solve of 1 of the %d RHS at N=%d (%d refinement steps: "
-                      "%d K~* and %d K~ applies, %d ULV solves; ULV on rank-4 generators of the same tree), "
-                      "%.1f s wall" % (nrhs_gpu, n, ir_steps, ir_steps + 1, ir_steps, ir_steps + 1, wall)}
+    fac = oulv.factor(synthetic_hss(n, 64, ranks))
+    res = {}
+    for label, threads in (("all_cores", None), ("one_core", 1)):
+        with threadpool_limits(limits=threads):
+            osolve.refine(B, fac, u, ir_steps)
+            walls, cpus = [], []
+            for _ in range(repeats):
+                t0, c0 = time.perf_counter(), time.process_time()
+                osolve.refine(B, fac, u, ir_steps)
+                walls.append(time.perf_counter() - t0)
+                cpus.append(time.process_time() - c0)
+        i = int(np.argsort(walls)[len(walls) // 2])
+        res[label] = {"s_per_rhs": round(walls[i], 3), "rhs_per_s": round(1.0 / walls[i], 4),
+                      "threads_used": round(cpus[i] / walls[i], 2), "runs_s": [round(w, 3) for w in walls]}
+    host = host_info()
+    return {"value": res["all_cores"]["rhs_per_s"], "unit": "RHS/s",
+            "cores": max(1, int(round(res["all_cores"]["threads_used"]))), "kind": "oracle",
+            "sample": "oracle FP64 refinement solve (oracle.solve.refine, %d steps: %d K~* and %d K~ applies "
+                      "and %d ULV solves, plus the final residual) of 1 of the %d RHS at N=%d: column 0 of the "
+                      "same seeded f, u = K~ f from the oracle's own factors; ULV factors of seeded HSS "
+                      "generators with the GPU construction's tree and per-node ranks; median of %d runs after "
+                      "1 warm-up" % (ir_steps, ir_steps + 1, ir_steps + 1, ir_steps + 1, nrhs_gpu, n, repeats,),
+            "host": host, "all_cores": res["all_cores"], "one_core": res["one_core"]}
 
 
-def synthetic_hss(n, leaf, r):
-    """Random Hermitian positive definite HSS generators of a given uniform rank (timing only)."""
+def synthetic_hss(n, leaf, ranks):
+    """Hermitian positive definite HSS generators (timing only) on the tree of N / leaf leaves
+    with the given per-node ranks {level: [rank of node j]}: orthonormal bases, small coupling
+    blocks and N I leaf blocks, all seeded."""
     from oracle import hss as ohss
     import fio_inputs as fi
     h = ohss.HSS(n, leaf)
     Lh = h.Lh
     for l in range(1, Lh + 1):
-        h.rank[l] = [r] * (2 ** l)
+        h.rank[l] = [int(r) for r in ranks[l]]
+    for l in range(1, Lh + 1):
         h.U[l] = []
         for j in range(2 ** l):
-            m = leaf if l == Lh else 2 * r
-            Q, _ = np.linalg.qr(fi.complex_gaussian(j, fi.PURPOSE_DATA, m, r, level=l))
-            h.U[l].append(Q)
+            m, r = h.m_of(l, j), h.rank[l][j]
+            Q, _ = np.linalg.qr(fi.complex_gaussian(j, fi.PURPOSE_DATA, m, max(r, 1), level=l))
+            h.U[l].append(Q[:, :r])
     for l in range(Lh):
-        h.B[l] = [0.01 * fi.complex_gaussian(j, fi.PURPOSE_DATA, r, r, level=100 + l) for j in range(2 ** l)]
+        h.B[l] = [0.01 * fi.complex_gaussian(j, fi.PURPOSE_DATA, h.rank[l + 1][2 * j + 1], h.rank[l + 1][2 * j],
+                                             level=100 + l) for j in range(2 ** l)]
     h.D = [n * np.eye(leaf, dtype=np.complex128) for _ in range(2 ** Lh)]
     return h
 
 
-def serving(F, torch, fi, duration, rate, seed=4, rel_res=5e-9):
-    """Serving workload: three resident operators N = 2^14, 2^16, 2^18 (same phase, q = 9, HSS
-    tolerance 1e-3), Poisson arrivals at `rate` requests/s for `duration` s, each request 1..32
-    right-hand sides (uniform) for an operator drawn uniformly; the refinement with the split-FP16
-    K~^* and the step count calibrated per operator; batches of up to 64 columns on 2 streams,
-    replayed from captured hipGraphs.  Latency = completion - submission (host clock)."""
+def serving_operators(F, torch, fi, rel_res=5e-9):
+    """The serving workload's three resident operators N = 2^14, 2^16, 2^18 (phase (2 + sin 2 pi x)/16,
+    q = 9, HSS tolerance 1e-3), each with its refinement step count per low precision calibrated on
+    a seeded calibration block (seed 100 + e) that no served request uses."""
     dev = torch.device("cuda")
     ops = []
     for e in (14, 16, 18):
         n = 1 << e
         B = F.BF(n, 9, 2.0 / 16, 1.0 / 16, precs=(F.FIO_PREC_FP64, F.FIO_PREC_SPLIT_FP16))
         U = F.ULV(F.HSS.from_bf(B, tol=1e-3, p=10, seed=1003))
-        fpool = fi.rhs(seed + e, n, 32)
+        fcal = torch.from_numpy(np.ascontiguousarray(fi.rhs(100 + e, n, 32).T)).to(dev).t()
+        ucal = B.apply(fcal)
+        nir = {}
+        for name, prec in (("split16", F.FIO_PREC_SPLIT_FP16), ("fp64", F.FIO_PREC_FP64)):
+            _, info = F.approx_solve(B, U, ucal, mode=F.FIO_SOLVE_IR, prec=prec, rel_res_tol=rel_res, max_ir=6)
+            nir[name] = max(1, info.ir_steps)
+        fpool = fi.rhs(4 + e, n, 32)
         fd = torch.from_numpy(np.ascontiguousarray(fpool.T)).to(dev).t()
-        upool = B.apply(fd)
-        _, info = F.approx_solve(B, U, upool, mode=F.FIO_SOLVE_IR, prec=F.FIO_PREC_SPLIT_FP16,
-                                 rel_res_tol=rel_res, max_ir=6)
-        ops.append({"n": n, "B": B, "U": U, "u": upool, "f": fpool, "nir": max(1, info.ir_steps)})
-    srv = F.Server(max_batch_rhs=64, streams=2, use_graphs=True, width_bucket=16)
-    ids = [srv.add_operator(o["B"], o["U"], mode=F.FIO_SOLVE_IR, prec=F.FIO_PREC_SPLIT_FP16, max_ir=o["nir"])
-           for o in ops]
+        ops.append({"n": n, "B": B, "U": U, "u": B.apply(fd), "f": fpool, "nir": nir})
+    torch.cuda.synchronize()
+    return ops
+
+
+def serving(F, torch, fi, ops, variant, duration, rate, seed=4, mem_budget=0, streams=2):
+    """Serving workload: Poisson arrivals at `rate` requests/s for `duration` s, each request 1..32
+    right-hand sides (uniform) for an operator drawn uniformly from `ops`; `variant` "split16"
+    (refinement with the split-FP16 K~^*) or "fp64" (the same refinement in FP64), step counts
+    calibrated per operator on held-out columns; batches of up to 64 columns on `streams` slots
+    whose arenas share `mem_budget` bytes, replayed from captured hipGraphs.  Latency = completion
+    - submission (host clock); sustained RHS/s = RHS served / (last completion - first submission).
+    Every served column is checked against its known f (u = K~ f)."""
+    prec = F.FIO_PREC_SPLIT_FP16 if variant == "split16" else F.FIO_PREC_FP64
     arr = fi.poisson_arrivals(seed, rate, duration)
     ks = fi.integers(seed, fi.PURPOSE_DATA, 1, 32, len(arr))
-    which = fi.integers(seed + 1, fi.PURPOSE_DATA, 0, 2, len(arr))
+    which = fi.integers(seed + 1, fi.PURPOSE_DATA, 0, len(ops) - 1, len(arr))
     # every request gets its own output block; inputs are column slices of the operator's pool
     outs = [F.empty(ops[w]["n"], int(k)) for w, k in zip(which, ks)]
+    warm = [F.empty(o["n"], 1) for o in ops]
     torch.cuda.synchronize()
-    # warm-up request per operator (captures happen at the first submission)
+    free0 = torch.cuda.mem_get_info()[0]
+    srv = F.Server(max_batch_rhs=64, streams=streams, mem_budget=mem_budget, use_graphs=True, width_bucket=16)
+    ids = [srv.add_operator(o["B"], o["U"], mode=F.FIO_SOLVE_IR, prec=prec, max_ir=o["nir"][variant])
+           for o in ops]
+    # warm-up request per operator (the server allocates its arenas and captures its graphs here)
     for i, o in enumerate(ops):
-        srv.submit(ids[i], o["u"][:, :1], F.empty(o["n"], 1))
+        srv.submit(ids[i], o["u"][:, :1], warm[i])
     srv.wait_all()
+    torch.cuda.synchronize()
+    held = free0 - torch.cuda.mem_get_info()[0]
     nwarm = len(ops)
     t0 = srv.now()
     rids = []
@@ -228,14 +310,16 @@ def serving(F, torch, fi, duration, rate, seed=4, rel_res=5e-9):
     st = srv.stats()
     srv.close()
     lat = np.array(lat)
-    return {"workload": "3 resident 1D FIOs N=2^14,2^16,2^18; Poisson %g req/s for %g s (seed %d); "
-                        "1-32 RHS per request; split-FP16 refinement; 64-column batches, 2 streams, hipGraphs"
-                        % (rate, duration, seed),
-            "requests": len(rids), "rhs": int(np.sum(ks)), "rhs_per_s": float(np.sum(ks) / (last - first)),
+    rhs = int(np.sum(ks))
+    return {"variant": variant, "rate_req_per_s": rate, "duration_s": duration, "seed": seed,
+            "requests": len(rids), "rhs": rhs, "offered_rhs_per_s": round(rhs / duration, 1),
+            "rhs_per_s": round(rhs / (last - first), 1),
             "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                            "mean": float(lat.mean()), "max": float(lat.max())},
             "batches": st["batches"] - nwarm, "max_queue": st["max_queue"],
-            "max_col_rel_err": err, "ir_steps": [o["nir"] for o in ops]}
+            "mem_budget_bytes": mem_budget, "device_bytes_held": int(held), "peak_batch_bytes": st["peak_bytes"],
+            "max_col_rel_err": err, "accuracy_ok": bool(err <= 1e-8),
+            "ir_steps": [o["nir"][variant] for o in ops]}
 
 
 def graph_replay(F, torch, fn, out, f_host, k, steps, warmup):
@@ -484,6 +568,47 @@ def workload_var_amp(F, torch, fi, steps, warmup, n=1 << 18, k=64, rel_res=1e-9)
     return res
 
 
+def workload_2e16(F, torch, fi, steps, warmup, n=1 << 16, k=16):
+    """The N = 2^16 configuration: phase (2 + sin 2 pi x)/16 (and c = 0, the DFT), q = 9, HSS
+    tolerance 1e-3 with p = 10 oversampling, 16 complex Gaussian right-hand sides (seed 1),
+    u = K~ f; times the GPU build (BF, HSS, ULV) and the direct FP64 solve f^ = F K~^* u
+    (RHS/s, per-column error against f)."""
+    dev = torch.device("cuda")
+    res = {"workload": "1D FIO N=2^16, q=9, HSS tol 1e-3, p=10, 16 RHS (seed 1), direct FP64 solve"}
+    for label, (c0, c1) in (("c_sin16", (2.0 / 16, 1.0 / 16)), ("c_zero_dft", (0.0, 0.0))):
+        t = time.perf_counter()
+        B = F.BF(n, 9, c0, c1)
+        torch.cuda.synchronize()
+        t_bf = time.perf_counter() - t
+        t = time.perf_counter()
+        H = F.HSS.from_bf(B, tol=1e-3, p=10, seed=1001)
+        torch.cuda.synchronize()
+        t_hss = time.perf_counter() - t
+        t = time.perf_counter()
+        U = F.ULV(H)
+        torch.cuda.synchronize()
+        t_ulv = time.perf_counter() - t
+        f_host = fi.rhs(1, n, k)
+        u = B.apply(torch.from_numpy(np.ascontiguousarray(f_host.T)).to(dev).t())
+        out = F.empty(n, k)
+        ws = torch.empty(F.solve_workspace_size(B, U, k), dtype=torch.uint8, device=dev)
+        for _ in range(warmup):
+            F.approx_solve(B, U, u, out=out, ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            F.approx_solve(B, U, u, out=out, ws=ws)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        err = np.linalg.norm(out.cpu().numpy() - f_host, axis=0) / np.linalg.norm(f_host, axis=0)
+        res[label] = {"direct_fp64_rhs_per_s": round(k / (ms / 1e3), 1), "ms_per_solve": round(ms, 4),
+                      "max_col_rel_err": float(err.max()),
+                      "offline_s": {"bf": round(t_bf, 3), "hss": round(t_hss, 3), "ulv": round(t_ulv, 3)},
+                      "hss_max_rank": int(max(max(v) for v in H.ranks().values()))}
+        del B, H, U
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -496,8 +621,14 @@ def main():
     ap.add_argument("--rel-res", type=float, default=5e-9)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--saturate-rate", type=float, default=1500.0,
+                    help="offered request rate of the saturation runs (above the server's capacity)")
+    ap.add_argument("--saturate-seconds", type=float, default=1.5)
+    ap.add_argument("--serve-budget-gib", type=float, default=24.0,
+                    help="device memory budget of the server's batch arenas")
+    ap.add_argument("--no-cfg-2e16", action="store_true", help="skip the N=2^16, 16-RHS direct-solve workload")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D workload")
     ap.add_argument("--only-2d", action="store_true", help="run the 2D workload alone (for profiling)")
     ap.add_argument("--no-2d-solve", action="store_true", help="2D: time the applies only")
@@ -546,6 +677,10 @@ def main():
     f_host = fi.rhs(1, n, k)
     f = torch.from_numpy(np.ascontiguousarray(f_host.T)).to(dev).t()
     u = B.apply(f)
+    # calibration block: other seeded columns (seed 2), never timed or checked
+    fcal = torch.from_numpy(np.ascontiguousarray(fi.rhs(2, n, k).T)).to(dev).t()
+    ucal = B.apply(fcal)
+    del fcal
     sync()
     # tile autotuner: levels per fused pass for the 64-column applies of each precision
     tuned = {}
@@ -561,12 +696,14 @@ def main():
         out = F.empty(n, k)
         ws = torch.empty(F.solve_workspace_size(B, U, k, F.FIO_SOLVE_IR, prec, a.rel_res, 6), dtype=torch.uint8,
                          device=dev)
-        # calibration: the residual-checked solve (one FP64 residual per step, read back) fixes the
-        # number of refinement steps this operator needs; it is also timed and reported
+        # calibration on the held-out block: the residual-checked solve (one FP64 residual per step,
+        # read back) fixes the number of refinement steps this operator needs
         kwc = dict(mode=F.FIO_SOLVE_IR, prec=prec, rel_res_tol=a.rel_res, max_ir=6, out=out, ws=ws)
+        _, info = F.approx_solve(B, U, ucal, **kwc)
+        nir = info.ir_steps
+        # the residual-checked solve on the timed block, timed and reported too
         for _ in range(a.warmup):
             _, info = F.approx_solve(B, U, u, **kwc)
-        nir = info.ir_steps
         sync()
         t0 = time.perf_counter()
         for _ in range(a.steps):
@@ -575,7 +712,8 @@ def main():
         ms_c = (time.perf_counter() - t0) * 1e3 / a.steps
         errc = np.linalg.norm(out.cpu().numpy() - f_host, axis=0) / np.linalg.norm(f_host, axis=0)
         checked[name] = {"value": k / (ms_c / 1e3), "ms_per_step": ms_c, "ir_steps": info.ir_steps,
-                         "rel_res": info.rel_res, "max_col_rel_err": float(errc.max())}
+                         "rel_res": info.rel_res, "max_col_rel_err": float(errc.max()),
+                         "accuracy_ok": bool(errc.max() <= 1e-8)}
         # timed: the same refinement with the calibrated step count and no host synchronisation
         kw = dict(mode=F.FIO_SOLVE_IR, prec=prec, rel_res_tol=0.0, max_ir=nir, out=out, ws=ws)
         for _ in range(a.warmup):
@@ -605,6 +743,7 @@ def main():
         err = np.linalg.norm(fh - f_host, axis=0) / np.linalg.norm(f_host, axis=0)
         ms_step = wall * 1e3 / a.steps
         results[name] = {"value": k / (ms_step / 1e3), "ms_per_step": ms_step, "max_col_rel_err": float(err.max()),
+                         "accuracy_ok": bool(err.max() <= 1e-8), "calibrated_on": "seed 2 (held out)",
                          "ir_steps": int(max(steps_taken)), "residual_checked": checked[name],
                          "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))}}
         # the same solve captured once into a hipGraph and replayed: the same kernels, without the
@@ -653,42 +792,52 @@ def main():
                                                     k, a.steps, a.warmup)
     log("pcg", json.dumps(pcg))
 
-    # the headline mixed path: the faster of the two low-precision variants
-    head = "split16" if results["split16"]["value"] > results["mixed"]["value"] else "mixed"
+    for nm, r in results.items():
+        r["graph"]["accuracy_ok"] = bool(r["graph"]["max_col_rel_err"] <= 1e-8)
+    # the headline mixed path: the faster of the two low-precision variants among those whose every
+    # column reached rel err 1e-8 (eager and replayed)
+    ok = [v for v in ("split16", "mixed") if results[v]["accuracy_ok"] and results[v]["graph"]["accuracy_ok"]]
+    cands = ok or ["split16", "mixed"]
+    head = max(cands, key=lambda v: max(results[v]["value"], results[v]["graph"]["value"]))
     launch = "hipGraph replay" if results[head]["graph"]["value"] > results[head]["value"] else "eager"
-    # roofline of the dominant kernel of the headline path
+    # roofline of the dominant kernel of the headline path (most time per step), and of the
+    # kernel furthest below its bound
     ks = kernel_stats[head]
     dom = max(ks, key=lambda kn: ks[kn][1])
-    cnt, tot = ks[dom]
-    avg_ms = tot / cnt
-    model = kernel_model(dom, n, q, k)
-    roof = None
-    if model:
-        byts, flops = model
-        peak_f = FP64_PEAK_TFLOPS if dom.endswith("f64") else FP32_PEAK_TFLOPS
-        if dom == "bf_split16":
-            peak_f = FP16_MFMA_PEAK_TFLOPS
-        t_mem = byts / (HBM_PEAK_GBS * 1e9)
-        t_alu = flops / (peak_f * 1e12)
-        if t_mem >= t_alu:
-            ach = byts / (avg_ms * 1e-3) / 1e9
-            roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": stored_traffic(dom)}
-        else:
-            ach = flops / (avg_ms * 1e-3) / 1e12
-            roof = {"bound": "mfma" if dom == "bf_split16" else "alu", "achieved": round(ach, 2), "peak": peak_f,
-                    "unit": "TFLOP/s",
-                    "frac": round(ach / peak_f, 4), "traffic": stored_traffic(dom)}
-        roof.update({"kernel": dom, "avg_launch_ms": round(avg_ms, 4), "launches": cnt,
-                     "algorithmic_bytes_per_launch": int(byts), "algorithmic_flops_per_launch": float(flops)})
+    roof = roofline_of(dom, n, q, k, ks[dom][1] / ks[dom][0], stored_traffic(dom))
+    if roof:
+        roof["launches"] = ks[dom][0]
+    others = {}
+    for kn, (cnt, tot) in ks.items():
+        r = roofline_of(kn, n, q, k, tot / cnt, stored_traffic(kn))
+        if r:
+            r["launches"] = cnt
+            others[kn] = r
 
     serve = None
     if not a.no_serve:
         del B, H, U
         torch.cuda.empty_cache()
         log("serving workload")
-        serve = serving(F, torch, fi, a.serve_seconds, a.serve_rate)
-        log("serving", json.dumps(serve))
+        sops = serving_operators(F, torch, fi)
+        budget = int(a.serve_budget_gib * (1 << 30))
+        serve = {"budget_gib": a.serve_budget_gib}
+        for variant in ("split16", "fp64"):
+            serve[variant] = serving(F, torch, fi, sops, variant, a.serve_seconds, a.serve_rate, mem_budget=budget)
+            log("serving", variant, json.dumps(serve[variant]))
+        for variant in ("split16", "fp64"):
+            serve["saturated_" + variant] = serving(F, torch, fi, sops, variant, a.saturate_seconds,
+                                                    a.saturate_rate, seed=5, mem_budget=budget)
+            log("serving saturated", variant, json.dumps(serve["saturated_" + variant]))
+        del sops
+        torch.cuda.empty_cache()
+
+    w16 = None
+    if not a.no_cfg_2e16:
+        torch.cuda.empty_cache()
+        log("N=2^16 direct-solve workload")
+        w16 = workload_2e16(F, torch, fi, a.steps, a.warmup)
+        log("2e16", json.dumps(w16))
 
     w2d = None
     if not a.no_2d:
@@ -714,7 +863,7 @@ def main():
 
     cpu = None
     if not a.no_cpu_baseline:
-        cpu = cpu_baseline(n, q, k, results["fp64"]["ir_steps"])
+        cpu = cpu_baseline(n, q, k, results["fp64"]["ir_steps"], ranks)
 
     mixed = dict(results[head])
     if launch != "eager":
@@ -724,6 +873,7 @@ def main():
         for lm, rr in (("eager", r), ("graph", r["graph"])):
             if rr["max_col_rel_err"] > 1e-8:
                 log("ERROR: %s path (%s) missed rel err 1e-8: %g" % (nm, lm, rr["max_col_rel_err"]))
+    accuracy_ok = bool(mixed["max_col_rel_err"] <= 1e-8 and head in ok)
     line = {
         "metric": METRIC, "value": round(mixed["value"], 2), "unit": "RHS/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(mixed["ms_per_step"], 3), "higher_is_better": True,
@@ -733,6 +883,8 @@ def main():
                                "refinement steps calibrated to rel residual %g" % (int(np.log2(n)), q, a.hss_tol, k,
                                                                                     a.rel_res),
                    "n": n, "nrhs": k, "q": q, "hss_tol": a.hss_tol, "mixed_variant": head, "launch": launch,
+                   "calibration": "refinement step count from the residual-checked solve of a held-out block "
+                                  "(seed 2); the timed block (seed 1) is checked against its f",
                    "autotuned_tiles": tuned,
                    "hss_max_rank_per_level": {str(l): int(max(v)) for l, v in ranks.items()}},
         "mixed": results["mixed"], "split16": results["split16"], "fp64": results["fp64"],
@@ -743,9 +895,13 @@ def main():
         "offline_s": {"bf": round(t_bf, 3), "hss": round(t_hss, 3), "ulv": round(t_ulv, 3)},
         "kernels_ms": {p: {kn: [c, round(m, 3)] for kn, (c, m) in d.items()} for p, d in kernel_stats.items()},
         "serving": serve, "workload_2d": w2d, "workload_var_amp": wamp, "workload_2d_var_amp": w2a,
-        "roofline": roof, "cpu_baseline": cpu,
+        "workload_2e16": w16, "accuracy_ok": accuracy_ok,
+        "roofline": roof, "roofline_by_kernel": others, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+    if not accuracy_ok:
+        log("ERROR: the headline path missed rel err 1e-8 on some column")
+        sys.exit(3)
 
 
 if __name__ == "__main__":
