@@ -20,7 +20,9 @@ Readings of points the paper leaves open:
   * ranks are per node (Def. hss_matrix); the effective leaf size of a
     nonleaf node is m_tau = r_a1 + r_a2, and one s_l serves a whole level:
     s_l = max_tau m_tau + rhat + p with the rank guess rhat = max_tau m_tau
-    (a rank can never exceed m_tau), so no redraw is ever needed;
+    (a rank can never exceed m_tau), so no redraw is ever needed; or, adaptive,
+    rhat = the largest rank of the level below, checked against the ranks the
+    sample yields and raised to max_tau m_tau (one more draw) when one exceeds it;
   * truncation keeps QRCP column j while |R_jj| > tol * g, where
     g = ||Y^[L]||_F / ||Omega^[L]||_F is the gain of H on the leaf-level
     test matrix (or the caller's estimate when given);
@@ -104,31 +106,47 @@ def node_step(Om_t, Y_t, tol_abs):
     return U, Dr, r
 
 
-def build(n, matvec, omega, tol, p=5, leaf=64, norm_est=None, rhat=None):
-    """Black-box construction of Section 3 with matvec(X) = H X (X: N x k)."""
+def build(n, matvec, omega, tol, p=5, leaf=64, norm_est=None, rhat=None, adaptive=False):
+    """Black-box construction of Section 3 with matvec(X) = H X (X: N x k).
+
+    adaptive: the level's rank r_l in s_l = m_l + r_l + p is not known before the level is
+    built; level l < Lh guesses the largest rank found at level l + 1 (the leaf level guesses
+    rhat, or m_max), and the sample is kept only if no node's rank exceeds the guess, so that
+    at least p sample columns lie beyond every rank found; otherwise the level is sampled
+    again with the guess m_max, which always suffices."""
     hss = HSS(n, leaf)
     Lh = hss.Lh
     Dres = {}
     g = norm_est
-    hss.s = {}
+    hss.s, hss.drawn = {}, {}
     for l in range(Lh, 0, -1):
         ms = [hss.m_of(l, j) for j in range(2 ** l)]
         R, mmax = sum(ms), max(ms)
-        s = mmax + (mmax if rhat is None else rhat) + p
+        guess = rhat if rhat else mmax
+        if adaptive and l < Lh:
+            guess = min(mmax, max(hss.rank[l + 1]))
+        hss.drawn[l] = 0
+        while True:
+            s = mmax + guess + p
+            hss.drawn[l] += s
+            Om = omega(l, R, s)
+            Y = _project(hss, matvec(_lift(hss, Om, l)), l)
+            if norm_est is None and l == Lh:
+                g = np.linalg.norm(Y) / np.linalg.norm(Om)
+            Ul, Dl, rl = [], [], []
+            off = 0
+            for j in range(2 ** l):
+                m = ms[j]
+                U, Dr, r = node_step(Om[off:off + m], Y[off:off + m], tol * g)
+                Ul.append(U)
+                Dl.append(Dr)
+                rl.append(r)
+                off += m
+            if not adaptive or guess >= mmax or max(rl) <= guess:
+                break
+            guess = mmax
         hss.s[l] = s
-        Om = omega(l, R, s)
-        Y = _project(hss, matvec(_lift(hss, Om, l)), l)
-        if g is None:
-            g = np.linalg.norm(Y) / np.linalg.norm(Om)
-        hss.U[l], Dres[l], hss.rank[l] = [], [], []
-        off = 0
-        for j in range(2 ** l):
-            m = ms[j]
-            U, Dr, r = node_step(Om[off:off + m], Y[off:off + m], tol * g)
-            hss.U[l].append(U)
-            Dres[l].append(Dr)
-            hss.rank[l].append(r)
-            off += m
+        hss.U[l], Dres[l], hss.rank[l] = Ul, Dl, rl
     hss.gain = g
     # root
     m0 = hss.m_of(0, 0)

@@ -32,9 +32,10 @@ class MortonFrequencies:
         return self._out(self.bf.apply_adj(Y), self.n)
 
 
-def build_hss_for_bf2d(bf, omega, tol, p=5, leaf=64, norm_est=None, rhat=None):
+def build_hss_for_bf2d(bf, omega, tol, p=5, leaf=64, norm_est=None, rhat=None, adaptive=False):
     """HSS of G~ = K~^* K~ for a 2D K~, in the Morton order of the frequencies."""
-    return build_hss_for_bf(MortonFrequencies(bf), omega, tol, p=p, leaf=leaf, norm_est=norm_est, rhat=rhat)
+    return build_hss_for_bf(MortonFrequencies(bf), omega, tol, p=p, leaf=leaf, norm_est=norm_est, rhat=rhat,
+                            adaptive=adaptive)
 
 
 def direct_solve2d(bf, fac, u):
@@ -43,10 +44,10 @@ def direct_solve2d(bf, fac, u):
     return fio2d.to_user(direct_solve(MortonFrequencies(bf), fac, u), bf.n)
 
 
-def build_hss_for_bf(bf, omega, tol, p=5, leaf=64, norm_est=None, rhat=None):
+def build_hss_for_bf(bf, omega, tol, p=5, leaf=64, norm_est=None, rhat=None, adaptive=False):
     """Algorithm alg:fio_inv, step 2: HSS of G~ = K~^* K~ from BF applies."""
     return hss_mod.build(bf.N, lambda X: bf.apply_adj(bf.apply(X)), omega, tol,
-                         p=p, leaf=leaf, norm_est=norm_est, rhat=rhat)
+                         p=p, leaf=leaf, norm_est=norm_est, rhat=rhat, adaptive=adaptive)
 
 
 def direct_solve(bf, fac, u):
