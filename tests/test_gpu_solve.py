@@ -134,3 +134,33 @@ def test_refinement_step_equals_its_parts(n, prec):
     r = u - B.apply(f0)
     d, _ = F.approx_solve(B, U, r, prec=prec)
     assert np.array_equal(host(f1), host(f0 + d))
+
+
+def test_dense_rhs_error_is_the_butterfly_error():
+    """N = 1024, q = 9, HSS tolerance 1e-10, one right-hand side (seed 0): with u = K f from the
+    dense K (eq. fio_mat) instead of u = K~ f, the solve inverts K~, so f^ is off from f by about
+    the butterfly's own error times the conditioning (q = 9: e_cBF ~ 4e-6, kappa(K) ~ 1.5); with
+    u = K~ f the refined solve reaches f to rounding.  Both are reported."""
+    F = fiohss()
+    from oracle import fio as ofio
+    n = 1024
+    step("dense u = K f, n=%d" % n)
+    c0, c1 = ofio.PHASE_SIN16
+    B = F.BF(n, 9, c0, c1)
+    U = F.ULV(F.HSS.from_bf(B, tol=1e-10, p=10, seed=3))
+    f = fi.rhs(0, n, 1)
+    K = ofio.dense_K(n, ofio.PHASE_SIN16)
+    u_dense = K @ f
+    fd, _ = F.approx_solve(B, U, dev(u_dense))
+    fr, info = F.approx_solve(B, U, dev(u_dense), mode=F.FIO_SOLVE_IR, rel_res_tol=1e-13, max_ir=8)
+    e_direct = osolve.col_rel_err(host(fd), f)
+    e_refined = osolve.col_rel_err(host(fr), f)
+    ut = host(B.apply(dev(f)))
+    ft, info2 = F.approx_solve(B, U, dev(ut), mode=F.FIO_SOLVE_IR, rel_res_tol=1e-13, max_ir=8)
+    e_tilde = osolve.col_rel_err(host(ft), f)
+    step("u = K f: direct %.2e, refined %.2e (%d steps); u = K~ f refined %.2e"
+         % (e_direct, e_refined, info.ir_steps, e_tilde))
+    # K~^{-1} K f - f = K~^{-1} (K - K~) f: the butterfly error, not the solver's
+    assert 1e-7 < e_refined < 1e-4
+    assert 1e-7 < e_direct < 1e-4
+    assert e_tilde < 1e-11
