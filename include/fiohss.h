@@ -270,6 +270,11 @@ typedef struct {
                            (0, default) or FIO_PREC_FP32 (needs the handle's FP32 copy, else FIO_ERR_ARG;
                            its ~1e-6 relative rounding sits far below the truncation tolerances the
                            construction is used with); ignored by hss_build_from_samples */
+    int adaptive;       /* 0: s_l = m_max + rhat + p at every level.  1: Section 3.1's s_l = m_l + r_l + p
+                           with the rank r_l guessed as the largest rank of level l + 1 (rhat, or m_max,
+                           at the leaf level); a level where some node's rank exceeds the guess is
+                           sampled again with the guess m_max, which always suffices (a second call of
+                           omega for that level, with more columns) */
 } hss_opts;
 
 /* Y = H X for ncols columns (device, column-major).  Return 0 on success. */

@@ -254,17 +254,18 @@ class HSS:
         self.levels, self.leaf, self.n = lv.value, leaf.value, n.value
 
     @staticmethod
-    def _opts(tol, p, leaf, rhat, norm_est, rank_cap):
-        return _lib.HssOpts(leaf, tol, p, rhat, norm_est, rank_cap)
+    def _opts(tol, p, leaf, rhat, norm_est, rank_cap, adaptive=False):
+        return _lib.HssOpts(leaf, tol, p, rhat, norm_est, rank_cap, 0, 1 if adaptive else 0)
 
     @classmethod
     def from_bf(cls, bf, tol, p=10, leaf=64, omega=None, seed=1000, rhat=0, norm_est=0.0, rank_cap=0,
-                sample_prec=FIO_PREC_FP64):
+                sample_prec=FIO_PREC_FP64, adaptive=False):
         """Algorithm alg:fio_inv step 2 with K~^* K~ applied by the library's BF kernels, in
-        sample_prec (FP64, or FP32 when the handle holds the FP32 copy)."""
+        sample_prec (FP64, or FP32 when the handle holds the FP32 copy).  adaptive: Section 3.1's
+        s_l = m_l + r_l + p with the rank guessed from the level below (hss_opts.adaptive)."""
         cb = omega if omega is not None else omega_torch(seed)
         h = C.c_void_p()
-        o = cls._opts(tol, p, leaf, rhat, norm_est, rank_cap)
+        o = cls._opts(tol, p, leaf, rhat, norm_est, rank_cap, adaptive)
         o.sample_prec = sample_prec
         st = lib().fio_hss_build(bf.h, C.byref(o), cb, None, _stream(), C.byref(h))
         _lib.check(st, "fio_hss_build", allow_warn=True)
@@ -274,7 +275,8 @@ class HSS:
         return obj
 
     @classmethod
-    def from_samples(cls, n, matvec, tol, p=10, leaf=64, omega=None, seed=1000, rhat=0, norm_est=0.0, rank_cap=0):
+    def from_samples(cls, n, matvec, tol, p=10, leaf=64, omega=None, seed=1000, rhat=0, norm_est=0.0, rank_cap=0,
+                     adaptive=False):
         """hss_build_from_samples with matvec(X: (n, k) device tensor) -> (n, k) device tensor."""
         def mv(ctx, X, ldx, Y, ldy, ncols, stream):
             try:
@@ -288,7 +290,7 @@ class HSS:
         mcb = _lib.MATVEC_FN(mv)
         cb = omega if omega is not None else omega_torch(seed)
         h = C.c_void_p()
-        o = cls._opts(tol, p, leaf, rhat, norm_est, rank_cap)
+        o = cls._opts(tol, p, leaf, rhat, norm_est, rank_cap, adaptive)
         st = lib().hss_build_from_samples(n, C.byref(o), mcb, None, cb, None, _stream(), C.byref(h))
         _lib.check(st, "hss_build_from_samples", allow_warn=True)
         obj = cls(h)

@@ -31,7 +31,8 @@ class BfDesc(C.Structure):
 
 class HssOpts(C.Structure):
     _fields_ = [("leaf", C.c_int), ("tol", C.c_double), ("p", C.c_int), ("rhat", C.c_int),
-                ("norm_est", C.c_double), ("rank_cap", C.c_int), ("sample_prec", C.c_int)]
+                ("norm_est", C.c_double), ("rank_cap", C.c_int), ("sample_prec", C.c_int),
+                ("adaptive", C.c_int)]
 
 
 class SolveOpts(C.Structure):

@@ -17,7 +17,8 @@ struct hss_s {
     // leaf diagonal blocks, leaf x leaf each, contiguous
     fio::DevBuf Dbuf;
     double gain = 0.0;
-    std::vector<int> samples;   // s_l used by the construction
+    std::vector<int> samples;   // s_l used by the construction (the last draw of a level)
+    std::vector<int> drawn;     // sample columns drawn per level (more than s_l after a redraw)
     bool rank_capped = false;
     ~hss_s() {
         for (auto *b : Ubuf) delete b;

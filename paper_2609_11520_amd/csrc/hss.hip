@@ -793,6 +793,7 @@ static fio_status build_impl(long n, const hss_opts *o, const Sampler &sm, hipSt
     h->uoff.assign(Lh + 1, {});
     h->Ubuf.assign(Lh + 1, nullptr);
     h->samples.assign(Lh + 1, 0);
+    h->drawn.assign(Lh + 1, 0);
     std::vector<DevBuf *> Dres(Lh + 1, nullptr);
     std::vector<std::vector<size_t>> doff(Lh + 1);
     fio_status st = guarded([&] {
@@ -825,8 +826,18 @@ static fio_status build_impl(long n, const hss_opts *o, const Sampler &sm, hipSt
                 continue;
             }
             if (mmax > kMaxM) throw Err{FIO_ERR_UNSUPPORTED};
-            const int rh = root ? 0 : (o->rhat > 0 ? o->rhat : mmax);
-            const int sl = mmax + rh + o->p;
+            // Section 3.1: s_l = m_l + r_l + p.  The level's rank is not known before it is built:
+            // the guess is rhat (or m_max); adaptive, a nonleaf level guesses the largest rank of
+            // the level below and is sampled again with the guess m_max (always sufficient) when a
+            // node's rank exceeds the guess
+            int guess = root ? 0 : (o->rhat > 0 ? o->rhat : mmax);
+            if (o->adaptive && !root && l < Lh) {
+                int rb = 0;
+                for (int v : h->rank[l + 1]) rb = v > rb ? v : rb;
+                guess = rb < mmax ? rb : mmax;
+            }
+            for (;;) {
+            const int sl = mmax + guess + o->p;
             // the one-workgroup node kernel keeps the norms of all s - m sample columns in LDS
             int mmin = mmax;
             for (int v : ms)
@@ -844,7 +855,7 @@ static fio_status build_impl(long n, const hss_opts *o, const Sampler &sm, hipSt
             lift_all(h, l, Om.as<double2>(), R, t0.as<double2>(), t1.as<double2>(), Ob.as<double2>(), sl, s);
             if (sm.matvec(sm.mctx, Ob.p, n, Yb.p, n, sl, s) != 0) throw Err{FIO_ERR_CALLBACK};
             project_all(h, l, Yb.as<double2>(), t0.as<double2>(), t1.as<double2>(), Y.as<double2>(), R, sl, s);
-            if (l == Lh && !(g > 0.0)) {
+            if (l == Lh && !(o->norm_est > 0.0)) {
                 double ny = sumsq(Y.as<double2>(), (size_t)R * sl, s);
                 double no = sumsq(Om.as<double2>(), (size_t)R * sl, s);
                 g = sqrt(ny) / sqrt(no);
@@ -919,6 +930,13 @@ static fio_status build_impl(long n, const hss_opts *o, const Sampler &sm, hipSt
             delete dms;
             delete duo;
             delete ddo;
+            h->drawn[l] += sl;
+            if (root || !o->adaptive || guess >= mmax) break;
+            int rl = 0;
+            for (int v : h->rank[l]) rl = v > rl ? v : rl;
+            if (rl <= guess) break;
+            guess = mmax;
+            }
             if (!root && o->rank_cap > 0)
                 for (int v : h->rank[l])
                     if (v >= o->rank_cap) h->rank_capped = true;

@@ -119,3 +119,58 @@ def test_rank_cap_reports_warning():
     # uncapped: full ranks, no warning
     H2 = F.HSS.from_samples(n, lambda X: Hd @ X, tol=1e-14, p=5, omega=F.omega_from(omega_np(24)))
     assert H2.status == 0
+
+
+def _recorded(seed, calls):
+    """omega_np(seed) that also records every (level, rows, cols) it is asked for."""
+    f = omega_np(seed)
+
+    def g(l, r, c):
+        calls.append((l, r, c))
+        return f(l, r, c)
+    return g
+
+
+def test_gpu_adaptive_sample_count_matches_oracle():
+    # Section 3.1's s_l = m_l + r_l + p with the rank guessed from the level below: the GPU
+    # construction asks for the same test matrices as the oracle (same levels, shapes and order)
+    # and finds the same ranks and generators, with fewer samples than the non-adaptive count
+    F = fiohss()
+    from oracle import solve as osolve
+    n = 1024
+    step("adaptive HSS build n=%d" % n)
+    co, cg = [], []
+    h = osolve.build_hss_for_bf(oracle_bf(n, 9, "sin16"), _recorded(1000, co), 1e-3, p=10, rhat=16, adaptive=True)
+    B = gpu_bf(F, n, 9, "sin16", imported=True)
+    H = F.HSS.from_bf(B, tol=1e-3, p=10, rhat=16, adaptive=True, omega=F.omega_from(_recorded(1000, cg)))
+    assert cg == co
+    assert H.ranks() == {l: list(v) for l, v in h.rank.items()}
+    r, g = H.export()
+    r0, g0 = hss_generators(h)
+    assert np.array_equal(r, r0)
+    assert perr(g, g0) < 1e-11
+    x = fi.complex_gaussian(6, fi.PURPOSE_PROBE, n, 3)
+    assert perr(host(H.matvec(dev(x))), ohss.matvec(h, x)) < 1e-12
+    cn = []
+    F.HSS.from_bf(B, tol=1e-3, p=10, omega=F.omega_from(_recorded(1000, cn)))
+    assert sum(c for _, _, c in cg) < 0.8 * sum(c for _, _, c in cn)
+
+
+def test_gpu_adaptive_sample_count_redraws_like_the_oracle():
+    # a leaf guess (rhat = 1) below the leaf rank 9 forces a second draw of the leaf level with
+    # m_max: both sides ask for the same draws and recover the matrix exactly
+    F = fiohss()
+    from test_oracle_hss import block_structured_hermitian
+    n = 512
+    step("adaptive HSS redraw n=%d" % n)
+    Hm = block_structured_hermitian(n, 64, 3, seed=11)
+    co, cg = [], []
+    ho = ohss.build(n, lambda X: Hm @ X, _recorded(21, co), tol=1e-13, p=5, rhat=1, adaptive=True)
+    Hd = dev(Hm)
+    H = F.HSS.from_samples(n, lambda X: Hd @ X, tol=1e-13, p=5, rhat=1, adaptive=True,
+                           omega=F.omega_from(_recorded(21, cg)))
+    assert cg == co
+    assert [c for l, _, c in cg if l == 3] == [64 + 1 + 5, 64 + 64 + 5]
+    assert H.ranks() == {l: list(v) for l, v in ho.rank.items()}
+    x = fi.complex_gaussian(3, fi.PURPOSE_PROBE, n, 2)
+    assert perr(host(H.matvec(dev(x))), Hm @ x) < 1e-11
