@@ -563,6 +563,10 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_stru
                 if (lane + 64 * k2 < Q * Q) mpf[k2] = msrc[lane + 64 * k2];
         }
         const C *tw = TWL ? stw + grp * 8 * Q : a.TW[j] + (size_t)g * 8 * Q;
+        // The output-side twiddle does not depend on the child summed over when the forward pass
+        // runs C factors (a depends on c_out only) or the adjoint runs B factors (b depends on
+        // c_in only): the two quadrant products are then summed first and scaled once.
+        constexpr bool FACT = ADJ != CS;
         C acc[Q];
 #pragma unroll
         for (int r = 0; r < Q; ++r) acc[r] = czero<C>();
@@ -573,41 +577,47 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_stru
             const int srcp = ADJ ? (o ? lout0 + Gl : lout0) : lin0 + o;
             const C *ta = tw + cout * 4 * Q + cin * Q;          // a(c_out, c_in, .)
             const C *tb = tw + cout * 4 * Q + (2 + cin) * Q;    // b(c_out, c_in, .)
-            // Element (r, t) of the quadrant matrix is read in one pattern per precision in every
-            // variant: Pm[t * Q + r] (double) or Pm[r * Q + t] (single), from P or its transpose
-            // as the variant needs.  In double precision, when both input children use the same
-            // matrix, an opaque zero offset makes each child load it for itself (otherwise the
-            // compiler keeps all 2 q^2 scalar registers of the matrix live across both and spills
-            // them into vector lanes).
+            // Element (r, t) of the quadrant matrix is read as Pm[t * Q + r], from P or its transpose
+            // as the variant needs, one column t at a time: the products run with the input index
+            // outermost (v_r += M(r, t) w_t for every r), so one scaled input and one column of the
+            // matrix are live at a time; each v_r still sums its terms in the order t = 0 .. Q-1.
+            // In double precision, when both input children use the same matrix, an opaque zero
+            // offset makes each child load it for itself (otherwise the compiler keeps all 2 q^2
+            // scalar registers of the matrix live across both and spills them into vector lanes).
             constexpr bool D = sizeof(T) == 8;
             int opaque0 = 0;
             if constexpr (D) asm volatile("s_mov_b32 %0, 0" : "=s"(opaque0));
-            const T *Pm = ((D ? !TRANS : TRANS) ? &a.PT[0][0][0] : &a.P[0][0][0]) + (CS ? cin : cout) * Q * Q + opaque0;
-            C w[Q];
+            const T *Pm = (!TRANS ? &a.PT[0][0][0] : &a.P[0][0][0]) + (CS ? cin : cout) * Q * Q + opaque0;
+            C v[Q];
+#pragma unroll
+            for (int r = 0; r < Q; ++r) v[r] = FACT ? acc[r] : czero<C>();
 #pragma unroll
             for (int t = 0; t < Q; ++t) {
                 const C x = lds[(srcp * Q + t) * 64 + lane];
-                if (ADJ) {
-                    C aa = ta[t];
-                    w[t] = cmul(cconj(aa), x);
-                } else {
-                    w[t] = cmul(tb[t], x);
+                const C wt = ADJ ? cmul(cconj(ta[t]), x) : cmul(tb[t], x);
+#pragma unroll
+                for (int r = 0; r < Q; ++r) {
+                    const T m = Pm[t * Q + r];
+                    v[r].x = fma(m, wt.x, v[r].x);
+                    v[r].y = fma(m, wt.y, v[r].y);
                 }
             }
 #pragma unroll
             for (int r = 0; r < Q; ++r) {
-                C v = czero<C>();
-#pragma unroll
-                for (int t = 0; t < Q; ++t) {
-                    const T m = D ? Pm[t * Q + r] : Pm[r * Q + t];
-                    v.x = fma(m, w[t].x, v.x);
-                    v.y = fma(m, w[t].y, v.y);
-                }
-                if (ADJ)
-                    cfmac(acc[r], tb[r], v);
+                if (FACT)
+                    acc[r] = v[r];
+                else if (ADJ)
+                    cfmac(acc[r], tb[r], v[r]);
                 else
-                    cfma(acc[r], ta[r], v);
+                    cfma(acc[r], ta[r], v[r]);
             }
+        }
+        if (FACT) {
+            // forward C side: a(c_out, .) of either input child; adjoint B side: b(., c_in)
+            // of either output child (the two stored copies are equal)
+            const C *ts = ADJ ? tw + (2 + h) * Q : tw + h * 4 * Q;
+#pragma unroll
+            for (int r = 0; r < Q; ++r) acc[r] = ADJ ? cmul(cconj(ts[r]), acc[r]) : cmul(ts[r], acc[r]);
         }
         __syncthreads();
         const int dst = ADJ ? lin0 + h : (h ? lout0 + Gl : lout0);
