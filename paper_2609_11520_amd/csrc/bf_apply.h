@@ -439,6 +439,109 @@ template <typename T, int Q> struct StructArgs {
     T PT[2][Q][Q];           // P_c(t, i): the transposes, so that every variant reads one pattern
 };
 
+// One transfer factor of a structured pass for the calling wave: group grp of forward step j,
+// output child h (forward) or input child h (adjoint), for the lane's column, from the tile in
+// LDS (pair p, coefficient i at row p q + i, 64 columns per row) and the group's 8q twiddles
+// at tw.  The result goes to acc; returns the local pair it belongs to.
+template <typename T, int Q, int KL, bool ADJ, bool CS>
+__device__ __forceinline__ int struct_step(const StructArgs<T, Q> &a, const cpx<T> *lds, const cpx<T> *tw, int grp,
+                                           int h, int j, int lane, cpx<T> (&acc)[Q]) {
+    using C = cpx<T>;
+    constexpr int P = 1 << KL;
+    // quadrant matrix M(r, t) = P_pc(r, t) (B side) or P_pc(t, r) (C side); the adjoint uses
+    // M^T, so the stored matrix is read transposed when ADJ != CS
+    constexpr bool TRANS = ADJ != CS;
+    const int Gl = P >> (j + 1);
+    const int aj = grp / Gl, sj = grp % Gl;
+    const int lin0 = aj * 2 * Gl + 2 * sj, lout0 = 2 * aj * Gl + sj;
+    // The output-side twiddle does not depend on the child summed over when the forward pass
+    // runs C factors (a depends on c_out only) or the adjoint runs B factors (b depends on
+    // c_in only): the two quadrant products are then summed first and scaled once.
+    constexpr bool FACT = ADJ != CS;
+#pragma unroll
+    for (int r = 0; r < Q; ++r) acc[r] = czero<C>();
+    // Element (r, t) of the quadrant matrix is read as Pm[t * Q + r], from P or its transpose as
+    // the variant needs, one column t at a time: the products run with the input index outermost
+    // (v_r += M(r, t) w_t for every r), so one scaled input and one column of the matrix are
+    // live at a time; each v_r sums its terms in the order t = 0 .. Q-1.
+    constexpr bool D = sizeof(T) == 8;
+    if constexpr (!FACT) {
+        // forward B side / adjoint C side: both quadrants use the same matrix (P_{c_out},
+        // resp. P_{c_in}, c = h), so one pass over its columns serves both children
+        const int s0 = ADJ ? lout0 : lin0, s1 = ADJ ? lout0 + Gl : lin0 + 1;
+        const C *t0 = tw + (ADJ ? h * Q : h * 4 * Q);                  // quadrant o = 0
+        const C *t1 = tw + (ADJ ? 4 * Q + h * Q : h * 4 * Q + Q);      // quadrant o = 1
+        // a(c_out, c_in, .) at t_o, b(c_out, c_in, .) at t_o + 2 Q
+        const T *Pm = (!TRANS ? &a.PT[0][0][0] : &a.P[0][0][0]) + h * Q * Q;
+        C v0[Q], v1[Q];
+#pragma unroll
+        for (int r = 0; r < Q; ++r) v0[r] = v1[r] = czero<C>();
+#pragma unroll
+        for (int t = 0; t < Q; ++t) {
+            // in double precision the column offset is opaque, so that each column's scalar
+            // loads are issued with the column (the whole matrix at once would not fit the
+            // scalar registers and would be spilled into vector lanes)
+            int ot = t * Q;
+            if constexpr (D) asm volatile("" : "+s"(ot));
+            const C x0 = lds[(s0 * Q + t) * 64 + lane], x1 = lds[(s1 * Q + t) * 64 + lane];
+            const C w0 = ADJ ? cmul(cconj(t0[t]), x0) : cmul(t0[2 * Q + t], x0);
+            const C w1 = ADJ ? cmul(cconj(t1[t]), x1) : cmul(t1[2 * Q + t], x1);
+#pragma unroll
+            for (int r = 0; r < Q; ++r) {
+                const T m = Pm[ot + r];
+                v0[r].x = fma(m, w0.x, v0[r].x);
+                v0[r].y = fma(m, w0.y, v0[r].y);
+                v1[r].x = fma(m, w1.x, v1[r].x);
+                v1[r].y = fma(m, w1.y, v1[r].y);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < Q; ++r) {
+            if (ADJ) {
+                cfmac(acc[r], t0[2 * Q + r], v0[r]);
+                cfmac(acc[r], t1[2 * Q + r], v1[r]);
+            } else {
+                cfma(acc[r], t0[r], v0[r]);
+                cfma(acc[r], t1[r], v1[r]);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int o = 0; o < 2; ++o) {
+            // FWD: o = c_in, output child c_out = h.  ADJ: o = c_out, input child c_in = h.
+            const int cout = ADJ ? o : h, cin = ADJ ? h : o;
+            const int srcp = ADJ ? (o ? lout0 + Gl : lout0) : lin0 + o;
+            const C *ta = tw + cout * 4 * Q + cin * Q;          // a(c_out, c_in, .)
+            const C *tb = tw + cout * 4 * Q + (2 + cin) * Q;    // b(c_out, c_in, .)
+            // In double precision an opaque zero offset makes each child load its matrix for
+            // itself (otherwise the compiler keeps all 2 q^2 scalar registers of both matrices
+            // live and spills them into vector lanes).
+            int opaque0 = 0;
+            if constexpr (D) asm volatile("s_mov_b32 %0, 0" : "=s"(opaque0));
+            const T *Pm = (!TRANS ? &a.PT[0][0][0] : &a.P[0][0][0]) + (CS ? cin : cout) * Q * Q + opaque0;
+#pragma unroll
+            for (int t = 0; t < Q; ++t) {
+                const C x = lds[(srcp * Q + t) * 64 + lane];
+                const C wt = ADJ ? cmul(cconj(ta[t]), x) : cmul(tb[t], x);
+#pragma unroll
+                for (int r = 0; r < Q; ++r) {
+                    const T m = Pm[t * Q + r];
+                    acc[r].x = fma(m, wt.x, acc[r].x);
+                    acc[r].y = fma(m, wt.y, acc[r].y);
+                }
+            }
+        }
+    }
+    if (FACT) {
+        // forward C side: a(c_out, .) of either input child; adjoint B side: b(., c_in) of
+        // either output child (the two stored copies are equal)
+        const C *ts = ADJ ? tw + (2 + h) * Q : tw + h * 4 * Q;
+#pragma unroll
+        for (int r = 0; r < Q; ++r) acc[r] = ADJ ? cmul(cconj(ts[r]), acc[r]) : cmul(ts[r], acc[r]);
+    }
+    return ADJ ? lin0 + h : (h ? lout0 + Gl : lout0);
+}
+
 // Register budget: single precision keeps 8 waves per SIMD (four 37 KB workgroups per CU at
 // KL = 3, <= 64 VGPRs), double precision 4 (two 74 KB workgroups, LDS-bound anyway).
 // LEAF (first pass of 3 levels: forward C side or adjoint B side): the pass also applies the
@@ -523,13 +626,17 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_stru
         const C *blk = a.V + ((size_t)box * kLeafPts + partner) * (Q * kLeafPts);   // nsl = 8 partners
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
+            // double precision: an opaque row offset keeps the block's scalar loads with their
+            // row (the whole 8 x q block does not fit the scalar registers)
+            int oi = i;
+            if constexpr (sizeof(T) == 8) asm volatile("" : "+s"(oi));
             C acc = czero<C>();
 #pragma unroll
             for (int t = 0; t < kLeafPts; ++t) {
                 if constexpr (ADJ)
-                    cfmac(acc, blk[t * Q + i], x[t]);
+                    cfmac(acc, blk[t * Q + oi], x[t]);
                 else
-                    cfma(acc, blk[i * kLeafPts + t], x[t]);
+                    cfma(acc, blk[oi * kLeafPts + t], x[t]);
             }
             lds[(wave * Q + i) * 64 + lane] = acc;
         }
@@ -542,17 +649,9 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_stru
     }
     __syncthreads();
     const int grp = wave >> 1, h = wave & 1;
-    // quadrant matrix M(r, t) = P_pc(r, t) (B side) or P_pc(t, r) (C side); the adjoint uses
-    // M^T, so the stored matrix is read transposed when ADJ != CS
-    constexpr bool TRANS = ADJ != CS;
 #pragma unroll
     for (int st = 0; st < KL; ++st) {
         const int j = ADJ ? KL - 1 - st : st;
-        const int Gl = P >> (j + 1);
-        const long Gj = a.G0 >> j;
-        const int aj = grp / Gl, sj = grp % Gl;
-        const long g = (A * (1L << j) + aj) * Gj + (S * Gl + sj);
-        const int lin0 = aj * 2 * Gl + 2 * sj, lout0 = 2 * aj * Gl + sj;
         if (TWL && st + 1 < KL && tid < NTW) twn = tw_src(ADJ ? j - 1 : j + 1, tid);
         if (EPI_M && st == KL - 1) {
             // the middle block of this wave's output pair, for the store phase
@@ -562,65 +661,9 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_stru
             for (int k2 = 0; k2 < NMP; ++k2)
                 if (lane + 64 * k2 < Q * Q) mpf[k2] = msrc[lane + 64 * k2];
         }
-        const C *tw = TWL ? stw + grp * 8 * Q : a.TW[j] + (size_t)g * 8 * Q;
-        // The output-side twiddle does not depend on the child summed over when the forward pass
-        // runs C factors (a depends on c_out only) or the adjoint runs B factors (b depends on
-        // c_in only): the two quadrant products are then summed first and scaled once.
-        constexpr bool FACT = ADJ != CS;
         C acc[Q];
-#pragma unroll
-        for (int r = 0; r < Q; ++r) acc[r] = czero<C>();
-#pragma unroll
-        for (int o = 0; o < 2; ++o) {
-            // FWD: o = c_in, output child c_out = h.  ADJ: o = c_out, input child c_in = h.
-            const int cout = ADJ ? o : h, cin = ADJ ? h : o;
-            const int srcp = ADJ ? (o ? lout0 + Gl : lout0) : lin0 + o;
-            const C *ta = tw + cout * 4 * Q + cin * Q;          // a(c_out, c_in, .)
-            const C *tb = tw + cout * 4 * Q + (2 + cin) * Q;    // b(c_out, c_in, .)
-            // Element (r, t) of the quadrant matrix is read as Pm[t * Q + r], from P or its transpose
-            // as the variant needs, one column t at a time: the products run with the input index
-            // outermost (v_r += M(r, t) w_t for every r), so one scaled input and one column of the
-            // matrix are live at a time; each v_r still sums its terms in the order t = 0 .. Q-1.
-            // In double precision, when both input children use the same matrix, an opaque zero
-            // offset makes each child load it for itself (otherwise the compiler keeps all 2 q^2
-            // scalar registers of the matrix live across both and spills them into vector lanes).
-            constexpr bool D = sizeof(T) == 8;
-            int opaque0 = 0;
-            if constexpr (D) asm volatile("s_mov_b32 %0, 0" : "=s"(opaque0));
-            const T *Pm = (!TRANS ? &a.PT[0][0][0] : &a.P[0][0][0]) + (CS ? cin : cout) * Q * Q + opaque0;
-            C v[Q];
-#pragma unroll
-            for (int r = 0; r < Q; ++r) v[r] = FACT ? acc[r] : czero<C>();
-#pragma unroll
-            for (int t = 0; t < Q; ++t) {
-                const C x = lds[(srcp * Q + t) * 64 + lane];
-                const C wt = ADJ ? cmul(cconj(ta[t]), x) : cmul(tb[t], x);
-#pragma unroll
-                for (int r = 0; r < Q; ++r) {
-                    const T m = Pm[t * Q + r];
-                    v[r].x = fma(m, wt.x, v[r].x);
-                    v[r].y = fma(m, wt.y, v[r].y);
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < Q; ++r) {
-                if (FACT)
-                    acc[r] = v[r];
-                else if (ADJ)
-                    cfmac(acc[r], tb[r], v[r]);
-                else
-                    cfma(acc[r], ta[r], v[r]);
-            }
-        }
-        if (FACT) {
-            // forward C side: a(c_out, .) of either input child; adjoint B side: b(., c_in)
-            // of either output child (the two stored copies are equal)
-            const C *ts = ADJ ? tw + (2 + h) * Q : tw + h * 4 * Q;
-#pragma unroll
-            for (int r = 0; r < Q; ++r) acc[r] = ADJ ? cmul(cconj(ts[r]), acc[r]) : cmul(ts[r], acc[r]);
-        }
+        const int dst = struct_step<T, Q, KL, ADJ, CS>(a, lds, stw + grp * 8 * Q, grp, h, j, lane, acc);
         __syncthreads();
-        const int dst = ADJ ? lin0 + h : (h ? lout0 + Gl : lout0);
 #pragma unroll
         for (int r = 0; r < Q; ++r) lds[(dst * Q + r) * 64 + lane] = acc[r];
         if (TWL && st + 1 < KL && tid < NTW) stw[tid] = twn;
