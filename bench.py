@@ -633,6 +633,8 @@ def main():
     ap.add_argument("--only-2d", action="store_true", help="run the 2D workload alone (for profiling)")
     ap.add_argument("--no-2d-solve", action="store_true", help="2D: time the applies only")
     ap.add_argument("--no-amp", action="store_true", help="skip the variable-amplitude workload")
+    ap.add_argument("--tune-file", default=None,
+                    help="tile table of the headline operator: loaded when the file exists, else tuned and written")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path; run with --gpus 1",
@@ -682,11 +684,24 @@ def main():
     ucal = B.apply(fcal)
     del fcal
     sync()
-    # tile autotuner: levels per fused pass for the 64-column applies of each precision
+    # tile autotuner: levels per fused pass, leaf fold and (split precision) engine for the
+    # 64-column applies of each precision; --tune-file reuses a table written by an earlier run
     tuned = {}
-    for prec, pn in ((F.FIO_PREC_FP64, "fp64"), (F.FIO_PREC_FP32, "fp32"), (F.FIO_PREC_SPLIT_FP16, "split16")):
-        tuned[pn] = chosen(B.autotune(u, prec=prec, reps=3))
-    log("autotuned tiles", json.dumps(tuned))
+    tune_source = "tuned in this run"
+    if a.tune_file and os.path.exists(a.tune_file):
+        with open(a.tune_file) as fh:
+            B.tune_import(fh.read())
+        tune_source = "loaded from " + a.tune_file
+        for prec, pn in ((F.FIO_PREC_FP64, "fp64"), (F.FIO_PREC_FP32, "fp32"), (F.FIO_PREC_SPLIT_FP16, "split16")):
+            tuned[pn] = [("%s " % d) + " ".join("%s=%d" % kv for kv in B.get_tile(k, prec=prec, adj=d == "adj").items())
+                         for d in ("fwd", "adj")]
+    else:
+        for prec, pn in ((F.FIO_PREC_FP64, "fp64"), (F.FIO_PREC_FP32, "fp32"), (F.FIO_PREC_SPLIT_FP16, "split16")):
+            tuned[pn] = chosen(B.autotune(u, prec=prec, reps=3))
+        if a.tune_file:
+            with open(a.tune_file, "w") as fh:
+                fh.write(B.tune_export())
+    log("autotuned tiles (%s)" % tune_source, json.dumps(tuned))
 
     results = {}
     kernel_stats = {}
@@ -885,7 +900,7 @@ def main():
                    "n": n, "nrhs": k, "q": q, "hss_tol": a.hss_tol, "mixed_variant": head, "launch": launch,
                    "calibration": "refinement step count from the residual-checked solve of a held-out block "
                                   "(seed 2); the timed block (seed 1) is checked against its f",
-                   "autotuned_tiles": tuned,
+                   "autotuned_tiles": tuned, "tune_source": tune_source,
                    "hss_max_rank_per_level": {str(l): int(max(v)) for l, v in ranks.items()}},
         "mixed": results["mixed"], "split16": results["split16"], "fp64": results["fp64"],
         "direct_fp64": {"ms_per_step": round(ms_direct, 3), "value": k / (ms_direct / 1e3),

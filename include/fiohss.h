@@ -194,8 +194,12 @@ fio_status fio_bf_apply_adj(fio_bf_t bf, const void *X, long ldx, void *Y, long 
  * two of nrhs, all counts >= 64 in one bucket) and precision use it.  Candidates: for dim = 2
  * the column chunk of the workgroups (8 or 16) times the reduction split of the U and V^*
  * steps (4, 8, 16 dividing the partner count); for dim = 1 (q = 9) the number of transfer
- * levels per fused pass (1, 2, 3); the built-in default is always a candidate.  Every
- * candidate applies the same operator (results differ at most by rounding order).  Y (ldy >= N)
+ * levels per fused pass (1, 2, 3), with 3 levels the first leaf factor folded into the first pass
+ * or run as its own kernel, and for FIO_PREC_SPLIT_FP16 each of these with the transfer passes
+ * on the matrix cores (split FP16) or on the vector units (FP32); the built-in default is always
+ * a candidate (fio_tile describes a candidate).  Every candidate applies the same operator
+ * (results differ at most by rounding order, and the FP32 engine is the more accurate one of a
+ * split-precision request).  Y (ldy >= N)
  * receives the last apply; `ws` as for fio_bf_apply (NULL: the handle's workspace).  When
  * `report` is not NULL, a NUL-terminated summary of the timings and the choices is written to
  * it (at most report_len bytes).  Synchronous.  Must not run concurrently with applies on the
@@ -211,6 +215,39 @@ fio_status fio_bf_autotune(fio_bf_t bf, const void *X, long ldx, void *Y, long l
  * ignored.  FIO_ERR_ARG for other values.  Host-side only; must not run concurrently with
  * applies on the same handle. */
 fio_status fio_bf_set_tile(fio_bf_t bf, int adj, fio_prec prec, int nrhs, int kc, int nsplit, int kmax);
+
+/* One tile configuration of an apply (fio_bf_autotune's candidates).  0 everywhere is the
+ * built-in default. */
+typedef struct {
+    int kc;        /* dim 2: column chunk of the workgroups, 0, 8 or 16 */
+    int nsplit;    /* dim 2: reduction split of the U and V^* steps, 0 or a power of two dividing the
+                      partner count, at most 16 */
+    int kmax;      /* dim 1: transfer levels per fused pass, 0 (as many as the LDS tile holds) or 1..3 */
+    int leaf_sep;  /* dim 1: 1 runs the first leaf factor as its own kernel instead of folding it into a
+                      first pass of 3 levels */
+    int valu;      /* dim 1, FIO_PREC_SPLIT_FP16 only: 1 runs the transfer passes as FP32 structured
+                      passes on the vector units instead of split FP16 on the matrix cores */
+} fio_tile;
+
+/* fio_bf_set_tile with every field of fio_tile; FIO_ERR_ARG for values outside the ranges above
+ * (valu = 1 with another precision included).  Host-side only, as fio_bf_set_tile. */
+fio_status fio_bf_set_tile_cfg(fio_bf_t bf, int adj, fio_prec prec, int nrhs, const fio_tile *t);
+
+/* The configuration later applies of that direction, precision and column bucket use (all zero:
+ * the built-in default). */
+fio_status fio_bf_get_tile_cfg(fio_bf_t bf, int adj, fio_prec prec, int nrhs, fio_tile *t);
+
+/* The handle's tuned table as NUL-terminated text, so that a tuning can be kept and reused by
+ * another process: a header line "fiohss-tune 1 dim=<d> n=<n> q=<q> level_offset=<o>", then one
+ * line "adj=<0|1> prec=<p> cols=<bucket> kc=.. nsplit=.. kmax=.. leaf_sep=.. valu=.." per tuned
+ * (direction, precision, column bucket).  *needed (if not NULL) receives the size including the
+ * NUL; buf == NULL only queries it; FIO_ERR_ARG when len is smaller. */
+fio_status fio_bf_tune_export(fio_bf_t bf, char *buf, size_t len, size_t *needed);
+
+/* Loads a table written by fio_bf_tune_export into the handle (entries it names replace the
+ * handle's; others are kept).  FIO_ERR_ARG, with the handle unchanged, for malformed text, a
+ * header of another operator shape (dim, n, q, level_offset) or an invalid configuration. */
+fio_status fio_bf_tune_import(fio_bf_t bf, const char *text);
 
 void fio_bf_destroy(fio_bf_t bf);
 

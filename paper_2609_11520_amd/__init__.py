@@ -171,9 +171,28 @@ class BF:
         _lib.check(st, "fio_bf_autotune")
         return rep.value.decode()
 
-    def set_tile(self, nrhs, prec=FIO_PREC_FP64, adj=False, kc=0, nsplit=0, kmax=0):
-        """Pins the tile configuration of one direction / precision / column bucket (fio_bf_set_tile)."""
-        _lib.check(lib().fio_bf_set_tile(self.h, int(adj), prec, nrhs, kc, nsplit, kmax), "fio_bf_set_tile")
+    def set_tile(self, nrhs, prec=FIO_PREC_FP64, adj=False, kc=0, nsplit=0, kmax=0, leaf_sep=0, valu=0):
+        """Pins the tile configuration of one direction / precision / column bucket (fio_bf_set_tile_cfg)."""
+        t = _lib.Tile(kc, nsplit, kmax, leaf_sep, valu)
+        _lib.check(lib().fio_bf_set_tile_cfg(self.h, int(adj), prec, nrhs, C.byref(t)), "fio_bf_set_tile_cfg")
+
+    def get_tile(self, nrhs, prec=FIO_PREC_FP64, adj=False):
+        """The configuration used for that direction / precision / column bucket, as a dict."""
+        t = _lib.Tile()
+        _lib.check(lib().fio_bf_get_tile_cfg(self.h, int(adj), prec, nrhs, C.byref(t)), "fio_bf_get_tile_cfg")
+        return {f: getattr(t, f) for f, _ in _lib.Tile._fields_}
+
+    def tune_export(self):
+        """The tuned table as text (fio_bf_tune_export)."""
+        need = C.c_size_t()
+        _lib.check(lib().fio_bf_tune_export(self.h, None, 0, C.byref(need)), "fio_bf_tune_export")
+        buf = C.create_string_buffer(need.value)
+        _lib.check(lib().fio_bf_tune_export(self.h, buf, need.value, None), "fio_bf_tune_export")
+        return buf.value.decode()
+
+    def tune_import(self, text):
+        """Loads a table written by tune_export (fio_bf_tune_import)."""
+        _lib.check(lib().fio_bf_tune_import(self.h, text.encode()), "fio_bf_tune_import")
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None and _lib._lib is not None:

@@ -35,6 +35,10 @@ class HssOpts(C.Structure):
                 ("adaptive", C.c_int)]
 
 
+class Tile(C.Structure):
+    _fields_ = [("kc", C.c_int), ("nsplit", C.c_int), ("kmax", C.c_int), ("leaf_sep", C.c_int), ("valu", C.c_int)]
+
+
 class SolveOpts(C.Structure):
     _fields_ = [("mode", C.c_int), ("prec", C.c_int), ("rel_res_tol", C.c_double), ("max_ir", C.c_int)]
 
@@ -64,6 +68,10 @@ PROTOS = {
     "fio_bf_apply_adj": (i32, [vp, vp, lg, vp, lg, i32, i32, vp, sz, vp]),
     "fio_bf_autotune": (i32, [vp, vp, lg, vp, lg, i32, i32, i32, vp, sz, vp, C.c_char_p, sz]),
     "fio_bf_set_tile": (i32, [vp, i32, i32, i32, i32, i32, i32]),
+    "fio_bf_set_tile_cfg": (i32, [vp, i32, i32, i32, C.POINTER(Tile)]),
+    "fio_bf_get_tile_cfg": (i32, [vp, i32, i32, i32, C.POINTER(Tile)]),
+    "fio_bf_tune_export": (i32, [vp, C.c_char_p, sz, C.POINTER(sz)]),
+    "fio_bf_tune_import": (i32, [vp, C.c_char_p]),
     "fio_bf_destroy": (None, [vp]),
     "fio_set_fused": (None, [i32]),
     "fio_set_leaf_fused": (None, [i32]),

@@ -10,6 +10,8 @@ namespace fio {
 // steps; kmax: 1D levels per fused pass.
 struct TileCfg {
     int kc = 0, nsplit = 0, kmax = 0;
+    int leaf_sep = 0;   // 1D: run the first leaf factor as its own kernel (no fold into the first pass)
+    int valu = 0;       // 1D split FP16: run the transfer passes as FP32 structured passes (vector units)
 };
 // Section 5.1's Gaussian-sum amplitude (m = 0: a = 1), passed to the factor generation by value
 constexpr int kMaxAmpTerms = 16;

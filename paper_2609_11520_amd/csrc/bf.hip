@@ -12,6 +12,7 @@
 #include "ddmath.h"
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -393,10 +394,23 @@ static std::vector<TileCfg> tile_candidates(const fio_bf_s *bf, fio_prec prec) {
             for (int ns : {4, 8, 16})
                 if (ns <= nmax && T % ns == 0) c.push_back(TileCfg{kc, ns, 0});
     } else if (bf->nl > 0 && bf->q == 9) {
-        for (int km : {1, 2, 3}) c.push_back(TileCfg{0, 0, km});
+        // levels per fused pass; with 3, the first leaf factor folded in or run on its own; in
+        // split precision, each of these with the transfer passes on the matrix cores (split
+        // FP16) or on the vector units (FP32, the more accurate of the two)
+        for (int valu : {0, 1}) {
+            if (valu && prec != FIO_PREC_SPLIT_FP16) continue;
+            for (int km : {1, 2, 3}) c.push_back(TileCfg{0, 0, km, 0, valu});
+            c.push_back(TileCfg{0, 0, 3, 1, valu});
+        }
     }
-    (void)prec;
     return c;
+}
+
+static std::string tile_str(const TileCfg &c) {
+    char buf[96];
+    snprintf(buf, sizeof buf, "kc=%d nsplit=%d kmax=%d leaf_sep=%d valu=%d", c.kc, c.nsplit, c.kmax, c.leaf_sep,
+             c.valu);
+    return buf;
 }
 
 void bf_apply_impl(fio_bf_s *bf, bool adjoint, const double2 *X, long ldx, double2 *Y, long ldy, int nrhs,
@@ -552,16 +566,122 @@ extern "C" fio_status fio_bf_apply_adj(fio_bf_t bf, const void *X, long ldx, voi
     return bf_apply_api(bf, true, X, ldx, Y, ldy, nrhs, prec, ws, ws_bytes, stream);
 }
 
-extern "C" fio_status fio_bf_set_tile(fio_bf_t bf, int adj, fio_prec prec, int nrhs, int kc, int nsplit, int kmax) {
-    FIO_CHECK_ARG(bf && nrhs > 0 && prec >= FIO_PREC_FP64 && prec <= FIO_PREC_SPLIT_FP16);
-    FIO_CHECK_ARG(kc == 0 || kc == 8 || kc == 16);
-    FIO_CHECK_ARG(kmax >= 0 && kmax <= 3 && nsplit >= 0);
-    if (bf->dim == 2 && nsplit > 0) {
+static bool tile_valid(const fio_bf_s *bf, const TileCfg &c) {
+    if (!(c.kc == 0 || c.kc == 8 || c.kc == 16)) return false;
+    if (!(c.kmax >= 0 && c.kmax <= 3 && c.nsplit >= 0)) return false;
+    if (!(c.leaf_sep == 0 || c.leaf_sep == 1) || !(c.valu == 0 || c.valu == 1)) return false;
+    if (bf->dim == 2 && c.nsplit > 0) {
         const long T = 1L << (2 * bf->lc);
-        FIO_CHECK_ARG(nsplit <= (T < 16 ? T : 16) && T % nsplit == 0);
+        if (!(c.nsplit <= (T < 16 ? T : 16) && T % c.nsplit == 0)) return false;
+    }
+    return true;
+}
+
+extern "C" fio_status fio_bf_set_tile(fio_bf_t bf, int adj, fio_prec prec, int nrhs, int kc, int nsplit, int kmax) {
+    fio_tile t{kc, nsplit, kmax, 0, 0};
+    return fio_bf_set_tile_cfg(bf, adj, prec, nrhs, &t);
+}
+
+extern "C" fio_status fio_bf_set_tile_cfg(fio_bf_t bf, int adj, fio_prec prec, int nrhs, const fio_tile *t) {
+    FIO_CHECK_ARG(bf && t && nrhs > 0 && prec >= FIO_PREC_FP64 && prec <= FIO_PREC_SPLIT_FP16);
+    const TileCfg c{t->kc, t->nsplit, t->kmax, t->leaf_sep, t->valu};
+    FIO_CHECK_ARG(tile_valid(bf, c));
+    FIO_CHECK_ARG(c.valu == 0 || prec == FIO_PREC_SPLIT_FP16);
+    std::lock_guard<std::mutex> lk(bf->tune_mu);
+    bf->tuned[tile_key(adj != 0, prec, nrhs)] = c;
+    return FIO_OK;
+}
+
+extern "C" fio_status fio_bf_get_tile_cfg(fio_bf_t bf, int adj, fio_prec prec, int nrhs, fio_tile *t) {
+    FIO_CHECK_ARG(bf && t && nrhs > 0 && prec >= FIO_PREC_FP64 && prec <= FIO_PREC_SPLIT_FP16);
+    const TileCfg c = bf_tile(bf, adj != 0, prec, nrhs);
+    *t = fio_tile{c.kc, c.nsplit, c.kmax, c.leaf_sep, c.valu};
+    return FIO_OK;
+}
+
+// The tuned table as text: one header line naming the operator shape, then one line per entry,
+//   fiohss-tune 1 dim=<d> n=<n> q=<q> level_offset=<o>
+//   adj=<0|1> prec=<p> cols=<bucket> kc=<kc> nsplit=<s> kmax=<k> leaf_sep=<0|1> valu=<0|1>
+static std::string tune_text(const fio_bf_s *bf) {
+    std::string out;
+    char buf[256];
+    snprintf(buf, sizeof buf, "fiohss-tune 1 dim=%d n=%ld q=%d level_offset=%d\n", bf->dim, (long)bf->desc.n,
+             bf->q, bf->desc.level_offset);
+    out += buf;
+    for (const auto &kv : bf->tuned) {
+        const int key = kv.first;
+        const TileCfg &c = kv.second;
+        snprintf(buf, sizeof buf, "adj=%d prec=%d cols=%d %s\n", key & 1, (key >> 1) & 3, 1 << (key >> 3),
+                 tile_str(c).c_str());
+        out += buf;
+    }
+    return out;
+}
+
+extern "C" fio_status fio_bf_tune_export(fio_bf_t bf, char *buf, size_t len, size_t *needed) {
+    FIO_CHECK_ARG(bf);
+    std::string t;
+    {
+        std::lock_guard<std::mutex> lk(bf->tune_mu);
+        t = tune_text(bf);
+    }
+    if (needed) *needed = t.size() + 1;
+    if (!buf) return FIO_OK;
+    FIO_CHECK_ARG(len >= t.size() + 1);
+    memcpy(buf, t.c_str(), t.size() + 1);
+    return FIO_OK;
+}
+
+// value of "name=<int>" in a line (false when absent or malformed)
+static bool field(const std::string &line, const char *name, long *v) {
+    const std::string key = std::string(" ") + name + "=";
+    const std::string l = " " + line;
+    const size_t at = l.find(key);
+    if (at == std::string::npos) return false;
+    const char *p = l.c_str() + at + key.size();
+    char *end = nullptr;
+    const long x = strtol(p, &end, 10);
+    if (end == p || (*end != 0 && *end != ' ' && *end != '\r')) return false;
+    *v = x;
+    return true;
+}
+
+extern "C" fio_status fio_bf_tune_import(fio_bf_t bf, const char *text) {
+    FIO_CHECK_ARG(bf && text);
+    std::vector<std::string> lines;
+    {
+        std::string cur;
+        for (const char *p = text; *p; ++p) {
+            if (*p == '\n') {
+                lines.push_back(cur);
+                cur.clear();
+            } else {
+                cur += *p;
+            }
+        }
+        if (!cur.empty()) lines.push_back(cur);
+    }
+    FIO_CHECK_ARG(!lines.empty() && lines[0].rfind("fiohss-tune 1 ", 0) == 0);
+    long d = 0, n = 0, q = 0, o = 0;
+    FIO_CHECK_ARG(field(lines[0], "dim", &d) && field(lines[0], "n", &n) && field(lines[0], "q", &q) &&
+                  field(lines[0], "level_offset", &o));
+    // a table tuned for another operator shape is refused
+    FIO_CHECK_ARG(d == bf->dim && n == (long)bf->desc.n && q == bf->q && o == bf->desc.level_offset);
+    std::map<int, TileCfg> tab;
+    for (size_t i = 1; i < lines.size(); ++i) {
+        if (lines[i].empty()) continue;
+        long adj, prec, cols, kc, ns, km, ls, va;
+        FIO_CHECK_ARG(field(lines[i], "adj", &adj) && field(lines[i], "prec", &prec) && field(lines[i], "cols", &cols) &&
+                      field(lines[i], "kc", &kc) && field(lines[i], "nsplit", &ns) && field(lines[i], "kmax", &km) &&
+                      field(lines[i], "leaf_sep", &ls) && field(lines[i], "valu", &va));
+        FIO_CHECK_ARG((adj == 0 || adj == 1) && prec >= FIO_PREC_FP64 && prec <= FIO_PREC_SPLIT_FP16);
+        FIO_CHECK_ARG(cols >= 1 && cols <= 64 && (cols & (cols - 1)) == 0);
+        const TileCfg c{(int)kc, (int)ns, (int)km, (int)ls, (int)va};
+        FIO_CHECK_ARG(tile_valid(bf, c) && (c.valu == 0 || prec == FIO_PREC_SPLIT_FP16));
+        tab[tile_key(adj != 0, (fio_prec)prec, (int)cols)] = c;
     }
     std::lock_guard<std::mutex> lk(bf->tune_mu);
-    bf->tuned[tile_key(adj != 0, prec, nrhs)] = TileCfg{kc, nsplit, kmax};
+    for (const auto &kv : tab) bf->tuned[kv.first] = kv.second;
     return FIO_OK;
 }
 
@@ -608,9 +728,8 @@ extern "C" fio_status fio_bf_autotune(fio_bf_t bf, const void *X, long ldx, void
                 float ms = 0.f;
                 FIO_HIP(hipEventElapsedTime(&ms, e0, e1));
                 ms /= (float)reps;
-                char buf[128];
-                snprintf(buf, sizeof buf, "%s kc=%d nsplit=%d kmax=%d %.4f ms; ", adj ? "adj" : "fwd", c.kc, c.nsplit,
-                         c.kmax, ms);
+                char buf[160];
+                snprintf(buf, sizeof buf, "%s %s %.4f ms; ", adj ? "adj" : "fwd", tile_str(c).c_str(), ms);
                 rep += buf;
                 if (best < 0.f || ms < best) {
                     best = ms;
@@ -619,9 +738,8 @@ extern "C" fio_status fio_bf_autotune(fio_bf_t bf, const void *X, long ldx, void
             }
             std::lock_guard<std::mutex> lk(bf->tune_mu);
             bf->tuned[key] = bc;
-            char buf[128];
-            snprintf(buf, sizeof buf, "chosen %s kc=%d nsplit=%d kmax=%d; ", adj ? "adj" : "fwd", bc.kc, bc.nsplit,
-                     bc.kmax);
+            char buf[160];
+            snprintf(buf, sizeof buf, "chosen %s %s; ", adj ? "adj" : "fwd", tile_str(bc).c_str());
             rep += buf;
         }
         (void)hipEventDestroy(e0);

@@ -938,13 +938,18 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
     // run C^[h+hi] .. C^[h+lo+1], forward B passes run B^[h+lo+1] .. B^[h+hi]
     bool fused = false;
     int kmax = 1;
+    bool leaf_sep = false;
     if constexpr (fused_q<Q>()) {
         fused = bf->nl > 0 && (split || !fused_disabled());
         kmax = fused_max_kl<T, Q>();
-        // levels per pass: tuned (fio_bf_autotune) or the most the LDS tile holds
+        // levels per pass: tuned (fio_bf_autotune) or the most the LDS tile holds; the tuned
+        // configuration may also keep the first leaf factor separate and, in split precision,
+        // run the transfer passes on the vector units in FP32
         const fio_prec pr = f64 ? FIO_PREC_FP64 : (split ? FIO_PREC_SPLIT_FP16 : FIO_PREC_FP32);
-        const int tk = bf_tile(bf, adj, pr, nrhs).kmax;
-        if (tk > 0 && tk < kmax) kmax = tk;
+        const TileCfg tc = bf_tile(bf, adj, pr, nrhs);
+        if (tc.kmax > 0 && tc.kmax < kmax) kmax = tc.kmax;
+        leaf_sep = tc.leaf_sep != 0;
+        if (split && tc.valu) split = false;
     }
     auto pass = [&](bool a, bool cside, int lo, int hi, bool epi, bool leaf = false) {
         if constexpr (fused_q<Q>()) {
@@ -1039,7 +1044,8 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
         // V^[L'] folds into the first C pass when that pass is a structured one of 3 levels (one
         // leaf box per wave) and its workgroups can be grouped by 8 per XCD (2^L' / 8 % 8 == 0)
         const bool leaf_fused = leaf_foldable<T, Q>() && fused && bf->structured &&
-                                !leaf_fused_disabled() && (kmax < bf->nl ? kmax : bf->nl) == 3 && bf->Lp >= 6;
+                                !leaf_fused_disabled() && !leaf_sep && (kmax < bf->nl ? kmax : bf->nl) == 3 &&
+                                bf->Lp >= 6;
         if (!leaf_fused) {
             FIO_TIMED(f64 ? "bf_leaf_in_f64" : "bf_leaf_in_f32", s);
             if (tiled)
@@ -1075,7 +1081,8 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
     } else {
         // U^[L']* folds into the first B* pass under the same conditions as V^[L'] forward
         const bool leaf_fused = leaf_foldable<T, Q>() && fused && bf->structured &&
-                                !leaf_fused_disabled() && (kmax < bf->nl ? kmax : bf->nl) == 3 && bf->Lp >= 6;
+                                !leaf_fused_disabled() && !leaf_sep && (kmax < bf->nl ? kmax : bf->nl) == 3 &&
+                                bf->Lp >= 6;
         if (!leaf_fused) {
             FIO_TIMED(f64 ? "bf_leaf_in_f64" : "bf_leaf_in_f32", s);
             if (tiled)

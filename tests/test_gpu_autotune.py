@@ -65,3 +65,66 @@ def test_autotune_1d_levels_per_pass(prec):
     assert "chosen fwd" in rep and "chosen adj" in rep
     assert perr(host(B.apply(dev(x), prec=prec)), rf) < tol
     assert perr(host(B.apply_adj(dev(x), prec=prec)), ra) < tol
+
+
+def test_autotune_1d_leaf_and_engine_candidates():
+    # the first leaf factor kept separate (leaf_sep) gives bitwise the same FP64 and FP32 results
+    # as folded; split precision on the vector units (valu) is the FP32 apply, bitwise
+    F = fiohss()
+    n, k = 4096, 64
+    step("1D leaf / engine candidates")
+    B = gpu_bf(F, n, 9, "sin16", imported=False, precs=(0, 1, 2))
+    ob = oracle_bf(n, 9, "sin16")
+    x = fi.complex_gaussian(33, fi.PURPOSE_PROBE, n, k)
+    rf, ra = ob.apply(x), ob.apply_adj(x)
+    for prec, tol in ((0, 1e-12), (1, 1e-5), (2, 2e-5)):
+        base = (host(B.apply(dev(x), prec=prec)), host(B.apply_adj(dev(x), prec=prec)))
+        for adj in (False, True):
+            B.set_tile(k, prec=prec, adj=adj, kmax=3, leaf_sep=1)
+        sep = (host(B.apply(dev(x), prec=prec)), host(B.apply_adj(dev(x), prec=prec)))
+        assert perr(sep[0], rf) < tol and perr(sep[1], ra) < tol
+        if prec != 2:
+            # (in split precision the folded first pass runs in FP32, the separate one split)
+            assert np.array_equal(sep[0], base[0]) and np.array_equal(sep[1], base[1])
+        for adj in (False, True):
+            B.set_tile(k, prec=prec, adj=adj)
+    f32 = (host(B.apply(dev(x), prec=1)), host(B.apply_adj(dev(x), prec=1)))
+    for adj in (False, True):
+        B.set_tile(k, prec=2, adj=adj, valu=1)
+    assert B.get_tile(k, prec=2) == {"kc": 0, "nsplit": 0, "kmax": 0, "leaf_sep": 0, "valu": 1}
+    v = (host(B.apply(dev(x), prec=2)), host(B.apply_adj(dev(x), prec=2)))
+    assert np.array_equal(v[0], f32[0]) and np.array_equal(v[1], f32[1])
+    with pytest.raises(F.FioError):
+        B.set_tile(k, prec=0, valu=1)
+    with pytest.raises(F.FioError):
+        B.set_tile(k, prec=2, leaf_sep=2)
+
+
+def test_tuned_table_export_and_import():
+    # a tuned table written by one handle and loaded into another of the same operator gives the
+    # same configurations and bitwise the same applies; other shapes and bad text are refused
+    F = fiohss()
+    n, k = 4096, 64
+    step("tune export / import")
+    B = gpu_bf(F, n, 9, "sin16", imported=False, precs=(0, 1, 2))
+    x = dev(fi.complex_gaussian(34, fi.PURPOSE_PROBE, n, k))
+    rep = B.autotune(x, prec=2, reps=2)
+    assert "valu=1" in rep and "leaf_sep=1" in rep
+    B.set_tile(8, prec=0, adj=True, kmax=2)
+    text = B.tune_export()
+    assert text.startswith("fiohss-tune 1 dim=1 n=4096 q=9 level_offset=3\n")
+    B2 = gpu_bf(F, n, 9, "sin16", imported=False, precs=(0, 1, 2))
+    B2.tune_import(text)
+    assert B2.tune_export() == text
+    for prec, cols in ((2, k), (0, 8)):
+        for adj in (False, True):
+            assert B2.get_tile(cols, prec=prec, adj=adj) == B.get_tile(cols, prec=prec, adj=adj)
+    assert B2.get_tile(8, prec=0, adj=True)["kmax"] == 2
+    y1, y2 = host(B.apply(x, prec=2)), host(B2.apply(x, prec=2))
+    assert np.array_equal(y1, y2)
+    B3 = gpu_bf(F, 1024, 9, "sin16", imported=False)
+    with pytest.raises(F.FioError):
+        B3.tune_import(text)
+    with pytest.raises(F.FioError):
+        B2.tune_import("fiohss-tune 1 dim=1 n=4096 q=9 level_offset=3\nadj=0 prec=0 cols=64 kc=0 kmax=9\n")
+    assert B2.tune_export() == text
