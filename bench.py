@@ -87,6 +87,81 @@ def copy_calibration(torch, nbytes=1 << 30):
     del src, dst
 
 
+def traffic_from(fetch_dir, write_dir, n=1 << 18, k=64, q=9):
+    """Writes profiles/traffic.json from two rocprofv3 counter runs of this benchmark (--pmc
+    FETCH_SIZE, then --pmc WRITE_SIZE, csv output) and prints a markdown summary.  The counters
+    (KiB per dispatch) are scaled by what they read for the 1 GiB device copy of
+    copy_calibration; per kernel label, the average over the run's dispatches at N = n with k
+    columns (one column tile)."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not f:
+            raise SystemExit("no counter_collection.csv under " + d)
+        per = {}
+        for r in csv.DictReader(open(f[0])):
+            if r["Counter_Name"] != counter:
+                continue
+            key = int(r["Dispatch_Id"])
+            name, grid, v = r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])
+            old = per.get(key)
+            per[key] = (name, grid, v + (old[2] if old else 0.0))
+        return per
+
+    fetch, write = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    one_gib_kib = float(1 << 20)
+    cf = [v for (_, _, v) in write.values() if abs(v - one_gib_kib) < 0.01 * one_gib_kib]
+    copies = [fetch[d][2] for d, (_, _, v) in write.items()
+              if abs(v - one_gib_kib) < 0.01 * one_gib_kib and d in fetch and fetch[d][2] > 0.25 * one_gib_kib]
+    if not copies or not cf:
+        raise SystemExit("the 1 GiB calibration copy was not found in the counter runs")
+    fs, ws = one_gib_kib / max(copies), one_gib_kib / max(cf)
+    tiles = n >> 3
+    labels = {
+        "bf_split16": (lambda nm: nm.startswith("void fio::(anonymous namespace)::k_split_fused<3,")
+                       or "k_split_fused<3," in nm, tiles * 512),
+        "bf_struct_f64": (lambda nm: "k_struct_fused<double, 9, 3," in nm and nm.split(">")[0].endswith("false"), tiles * 512),
+        "bf_struct_f32": (lambda nm: "k_struct_fused<float, 9, 3," in nm and nm.split(">")[0].endswith("false"), tiles * 512),
+        "bf_struct_leaf_f64": (lambda nm: "k_struct_fused<double, 9, 3," in nm and nm.split(">")[0].endswith("true"), tiles * 512),
+        "bf_struct_leaf_f32": (lambda nm: "k_struct_fused<float, 9, 3," in nm and nm.split(">")[0].endswith("true"), tiles * 512),
+        "bf_leaf_out_f64": (lambda nm: "k_leaf_io<double, 9, false," in nm, (n >> 3) // 4 * 256),
+        "bf_leaf_out_f32": (lambda nm: "k_leaf_io<float, 9, false," in nm, (n >> 3) // 4 * 256),
+    }
+    out = {"source_hash": kernel_source_hash(), "fetch_scale": fs, "write_scale": ws, "kernels": {},
+           "note": "hbm_bytes_per_launch: FETCH_SIZE x fetch_scale + WRITE_SIZE x write_scale per launch "
+                   "(KiB -> bytes), N=2^%d, %d RHS; algorithmic and spill bytes per launch by the explicit-form "
+                   "model of bench.kernel_model" % (int(np.log2(n)), k)}
+    rows = []
+    for lab, (match, grid) in labels.items():
+        ds = [d for d, (nm, g, _) in write.items() if match(nm) and g == grid and d in fetch]
+        if not ds:
+            continue
+        b = [(fetch[d][2] * fs + write[d][2] * ws) * 1024.0 for d in ds]
+        avg = sum(b) / len(b)
+        rec = {"hbm_bytes_per_launch": avg, "dispatches": len(ds),
+               "fetch_kib_per_launch": sum(fetch[d][2] for d in ds) / len(ds),
+               "write_kib_per_launch": sum(write[d][2] for d in ds) / len(ds)}
+        m = kernel_model(lab, n, q, k)
+        if m is not None:
+            rec["algorithmic_bytes_per_launch"] = m[0]
+            rec["spill_bytes_per_launch"] = m[2]
+        out["kernels"][lab] = rec
+        rows.append((lab, len(ds), rec["fetch_kib_per_launch"], rec["write_kib_per_launch"], avg,
+                     rec.get("algorithmic_bytes_per_launch"), rec.get("spill_bytes_per_launch")))
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print("calibration: FETCH_SIZE x %.4f, WRITE_SIZE x %.4f (1 GiB copy)" % (fs, ws))
+    print()
+    print("| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes | explicit-form bytes | ratio | spill bytes |")
+    print("|---|---|---|---|---|---|---|---|")
+    for lab, nd, fk, wk, hb, ab, sb in rows:
+        print("| %s | %d | %.0f | %.0f | %.3e | %s | %s | %s |" % (
+            lab, nd, fk, wk, hb, "-" if ab is None else "%.3e" % ab, "-" if ab is None else "%.2f" % (hb / ab),
+            "-" if sb is None else "%.3e" % sb))
+
+
 def pass_plan(n, kmax=3):
     """Structured butterfly passes of one apply: (levels, applies M) per launch."""
     L = int(np.log2(n))
@@ -633,9 +708,14 @@ def main():
     ap.add_argument("--only-2d", action="store_true", help="run the 2D workload alone (for profiling)")
     ap.add_argument("--no-2d-solve", action="store_true", help="2D: time the applies only")
     ap.add_argument("--no-amp", action="store_true", help="skip the variable-amplitude workload")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
+                    help="write profiles/traffic.json from two rocprofv3 counter runs of this benchmark and exit")
     ap.add_argument("--tune-file", default=None,
                     help="tile table of the headline operator: loaded when the file exists, else tuned and written")
     a = ap.parse_args()
+    if a.traffic_from:
+        traffic_from(*a.traffic_from, n=a.n, k=a.nrhs, q=a.q)
+        return
     if a.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path; run with --gpus 1",
               file=sys.stderr)
