@@ -568,8 +568,34 @@ def workload_2d(F, torch, fi, steps, warmup, rel_res=5e-9, solve=True, var_amp=F
         err32 = np.linalg.norm(fd.cpu().numpy() - f_host, axis=0) / np.linalg.norm(f_host, axis=0)
         sol["mixed_on_fp32_sampled_hss"] = {"ir_steps": int(info32.ir_steps), "max_col_rel_err": float(err32.max())}
         del H32, U32
+        # Section 3.1's sample count s_l = m_l + r_l + p with the rank guessed from the level below
+        # (hss_opts.adaptive); the test-matrix columns drawn are counted through the callback
+        drawn = {"adaptive": 0, "default": 0}
+
+        def counting(key):
+            inner = F.omega_torch(1003)
+
+            def cb(ctx, level, rows, cols, out, stream):
+                drawn[key] += int(cols)
+                return inner(ctx, level, rows, cols, out, stream)
+            return F._lib.OMEGA_FN(cb), inner
+        cb_def = counting("default")
+        F.HSS.from_bf(B, tol=1e-3, p=10, omega=cb_def[0])
+        torch.cuda.synchronize()
+        cb_ad = counting("adaptive")
+        t = time.perf_counter()
+        Had = F.HSS.from_bf(B, tol=1e-3, p=10, omega=cb_ad[0], adaptive=True)
+        torch.cuda.synchronize()
+        t_hss_ad = time.perf_counter() - t
+        Uad = F.ULV(Had)
+        _, info_ad = F.approx_solve(B, Uad, u, mode=F.FIO_SOLVE_IR, prec=F.FIO_PREC_FP32, rel_res_tol=rel_res,
+                                    max_ir=10, out=fd)
+        err_ad = np.linalg.norm(fd.cpu().numpy() - f_host, axis=0) / np.linalg.norm(f_host, axis=0)
+        sol["mixed_on_adaptive_hss"] = {"ir_steps": int(info_ad.ir_steps), "max_col_rel_err": float(err_ad.max())}
+        del Had, Uad
         res.update({"offline_s": {"hss": round(t_hss, 2), "ulv": round(t_ulv, 2),
-                                  "hss_fp32_samples": round(t_hss32, 2)},
+                                  "hss_fp32_samples": round(t_hss32, 2), "hss_adaptive_samples": round(t_hss_ad, 2)},
+                    "hss_sample_columns": drawn,
                     "hss_max_rank_per_level": {str(l): int(max(v)) for l, v in H.ranks().items()},
                     "solve": sol})
     return res
@@ -755,6 +781,14 @@ def main():
     t_ulv = time.perf_counter() - t
     log("offline: BF %.2fs, HSS %.2fs, ULV %.2fs; max ranks per level %s" %
         (t_bf, t_hss, t_ulv, {l: int(max(v)) for l, v in ranks.items()}))
+    # the same construction with Section 3.1's adaptive sample count (leaf rank guess 16, then the
+    # largest rank of the level below); timed for the offline figures only
+    t = time.perf_counter()
+    Had = F.HSS.from_bf(B, tol=a.hss_tol, p=10, seed=1003, rhat=16, adaptive=True)
+    sync()
+    t_hss_ad = time.perf_counter() - t
+    ranks_ad = {str(l): int(max(v)) for l, v in Had.ranks().items()}
+    del Had
 
     f_host = fi.rhs(1, n, k)
     f = torch.from_numpy(np.ascontiguousarray(f_host.T)).to(dev).t()
@@ -987,7 +1021,8 @@ def main():
                         "max_col_rel_err": err_d},
         "pcg_fp64": pcg,
         "latency_ms": mixed["latency_ms"],
-        "offline_s": {"bf": round(t_bf, 3), "hss": round(t_hss, 3), "ulv": round(t_ulv, 3)},
+        "offline_s": {"bf": round(t_bf, 3), "hss": round(t_hss, 3), "ulv": round(t_ulv, 3),
+                      "hss_adaptive_rhat16": round(t_hss_ad, 3), "hss_adaptive_max_rank_per_level": ranks_ad},
         "kernels_ms": {p: {kn: [c, round(m, 3)] for kn, (c, m) in d.items()} for p, d in kernel_stats.items()},
         "serving": serve, "workload_2d": w2d, "workload_var_amp": wamp, "workload_2d_var_amp": w2a,
         "workload_2e16": w16, "accuracy_ok": accuracy_ok,
