@@ -87,7 +87,7 @@ def copy_calibration(torch, nbytes=1 << 30):
     del src, dst
 
 
-def traffic_from(fetch_dir, write_dir, n=1 << 18, k=64, q=9):
+def traffic_from(fetch_dir, write_dir, n=1 << 18, k=64, q=9, out_path=None):
     """Writes profiles/traffic.json from two rocprofv3 counter runs of this benchmark (--pmc
     FETCH_SIZE, then --pmc WRITE_SIZE, csv output) and prints a markdown summary.  The counters
     (KiB per dispatch) are scaled by what they read for the 1 GiB device copy of
@@ -150,7 +150,7 @@ def traffic_from(fetch_dir, write_dir, n=1 << 18, k=64, q=9):
         out["kernels"][lab] = rec
         rows.append((lab, len(ds), rec["fetch_kib_per_launch"], rec["write_kib_per_launch"], avg,
                      rec.get("algorithmic_bytes_per_launch"), rec.get("spill_bytes_per_launch")))
-    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+    with open(out_path or os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
         json.dump(out, fh, indent=1)
     print("calibration: FETCH_SIZE x %.4f, WRITE_SIZE x %.4f (1 GiB copy)" % (fs, ws))
     print()
@@ -893,6 +893,16 @@ def main():
     sync()
     ms_direct = (time.perf_counter() - t0) * 1e3 / a.steps
     err_d = float((np.linalg.norm(out.cpu().numpy() - f_host, axis=0) / np.linalg.norm(f_host, axis=0)).max())
+    # the same direct solve with K~^* in split FP16: its error is the HSS approximation's either way
+    for _ in range(a.warmup):
+        F.approx_solve(B, U, u, prec=F.FIO_PREC_SPLIT_FP16, out=out)
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        F.approx_solve(B, U, u, prec=F.FIO_PREC_SPLIT_FP16, out=out)
+    sync()
+    ms_direct16 = (time.perf_counter() - t0) * 1e3 / a.steps
+    err_d16 = float((np.linalg.norm(out.cpu().numpy() - f_host, axis=0) / np.linalg.norm(f_host, axis=0)).max())
 
     # the paper's iterative solver (Sec. 4.1, Sec. 5): CG on the normal equation preconditioned by F,
     # to a relative residual of 1e-12; residual-checked, then with the iteration count fixed
@@ -1019,6 +1029,8 @@ def main():
         "mixed": results["mixed"], "split16": results["split16"], "fp64": results["fp64"],
         "direct_fp64": {"ms_per_step": round(ms_direct, 3), "value": k / (ms_direct / 1e3),
                         "max_col_rel_err": err_d},
+        "direct_split16": {"ms_per_step": round(ms_direct16, 3), "value": k / (ms_direct16 / 1e3),
+                           "max_col_rel_err": err_d16},
         "pcg_fp64": pcg,
         "latency_ms": mixed["latency_ms"],
         "offline_s": {"bf": round(t_bf, 3), "hss": round(t_hss, 3), "ulv": round(t_ulv, 3),
