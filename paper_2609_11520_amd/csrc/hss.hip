@@ -837,105 +837,105 @@ static fio_status build_impl(long n, const hss_opts *o, const Sampler &sm, hipSt
                 guess = rb < mmax ? rb : mmax;
             }
             for (;;) {
-            const int sl = mmax + guess + o->p;
-            // the one-workgroup node kernel keeps the norms of all s - m sample columns in LDS
-            int mmin = mmax;
-            for (int v : ms)
-                if (v > 0) mmin = v < mmin ? v : mmin;
-            if (!root && mmax < g_big_node && sl - mmin > kMaxNW) throw Err{FIO_ERR_UNSUPPORTED};
-            h->samples[l] = sl;
-            Om.ensure((size_t)R * sl * sizeof(double2));
-            if (sm.omega(sm.octx, l, R, sl, Om.p, s) != 0) throw Err{FIO_ERR_CALLBACK};
-            const size_t big = (size_t)n * sl * sizeof(double2);
-            Ob.ensure(big);
-            Yb.ensure(big);
-            t0.ensure(big);
-            t1.ensure(big);
-            Y.ensure((size_t)R * sl * sizeof(double2));
-            lift_all(h, l, Om.as<double2>(), R, t0.as<double2>(), t1.as<double2>(), Ob.as<double2>(), sl, s);
-            if (sm.matvec(sm.mctx, Ob.p, n, Yb.p, n, sl, s) != 0) throw Err{FIO_ERR_CALLBACK};
-            project_all(h, l, Yb.as<double2>(), t0.as<double2>(), t1.as<double2>(), Y.as<double2>(), R, sl, s);
-            if (l == Lh && !(o->norm_est > 0.0)) {
-                double ny = sumsq(Y.as<double2>(), (size_t)R * sl, s);
-                double no = sumsq(Om.as<double2>(), (size_t)R * sl, s);
-                g = sqrt(ny) / sqrt(no);
-            }
-            // per-node algebra
-            size_t stride = (size_t)2 * sl * mmax + (size_t)3 * mmax * mmax;
-            scratch.ensure(stride * nn * sizeof(double2));
-            std::vector<size_t> uo(nn, 0);
-            if (!root) uo = h->uoff[l];
-            DevBuf *dmo = upload(mo, s), *dms = upload(ms, s), *duo = upload(uo, s), *ddo = upload(doff[l], s);
-            DevBuf rk(nn * sizeof(int));
-            NodeArgs na;
-            na.Om = Om.as<double2>();
-            na.Y = Y.as<double2>();
-            na.ldR = R;
-            na.moff = dmo->as<long>();
-            na.msz = dms->as<int>();
-            na.s = sl;
-            na.tol_abs = o->tol * g;
-            na.cap = o->rank_cap;
-            na.scratch = scratch.as<double2>();
-            na.stride = stride;
-            na.rank_out = rk.as<int>();
-            na.Uslot = root ? nullptr : h->Ubuf[l]->as<double2>();
-            na.uoff = duo->as<size_t>();
-            na.Dres = Dres[l]->as<double2>();
-            na.doff = ddo->as<size_t>();
-            na.root = root ? 1 : 0;
-            if (mmax < g_big_node) {
-                k_node_basis<<<nn, node_threads(mmax), 0, s>>>(na);
-                FIO_HIP(hipGetLastError());
-            } else {
-                basis_big(na, ms, nn, mmax, sl, root, s);
-            }
-            if (!root) {
-                h->rank[l].assign(nn, 0);
-                FIO_HIP(hipMemcpyAsync(h->rank[l].data(), rk.p, nn * sizeof(int), hipMemcpyDeviceToHost, s));
+                const int sl = mmax + guess + o->p;
+                // the one-workgroup node kernel keeps the norms of all s - m sample columns in LDS
+                int mmin = mmax;
+                for (int v : ms)
+                    if (v > 0) mmin = v < mmin ? v : mmin;
+                if (!root && mmax < g_big_node && sl - mmin > kMaxNW) throw Err{FIO_ERR_UNSUPPORTED};
+                h->samples[l] = sl;
+                Om.ensure((size_t)R * sl * sizeof(double2));
+                if (sm.omega(sm.octx, l, R, sl, Om.p, s) != 0) throw Err{FIO_ERR_CALLBACK};
+                const size_t big = (size_t)n * sl * sizeof(double2);
+                Ob.ensure(big);
+                Yb.ensure(big);
+                t0.ensure(big);
+                t1.ensure(big);
+                Y.ensure((size_t)R * sl * sizeof(double2));
+                lift_all(h, l, Om.as<double2>(), R, t0.as<double2>(), t1.as<double2>(), Ob.as<double2>(), sl, s);
+                if (sm.matvec(sm.mctx, Ob.p, n, Yb.p, n, sl, s) != 0) throw Err{FIO_ERR_CALLBACK};
+                project_all(h, l, Yb.as<double2>(), t0.as<double2>(), t1.as<double2>(), Y.as<double2>(), R, sl, s);
+                if (l == Lh && !(o->norm_est > 0.0)) {
+                    double ny = sumsq(Y.as<double2>(), (size_t)R * sl, s);
+                    double no = sumsq(Om.as<double2>(), (size_t)R * sl, s);
+                    g = sqrt(ny) / sqrt(no);
+                }
+                // per-node algebra
+                size_t stride = (size_t)2 * sl * mmax + (size_t)3 * mmax * mmax;
+                scratch.ensure(stride * nn * sizeof(double2));
+                std::vector<size_t> uo(nn, 0);
+                if (!root) uo = h->uoff[l];
+                DevBuf *dmo = upload(mo, s), *dms = upload(ms, s), *duo = upload(uo, s), *ddo = upload(doff[l], s);
+                DevBuf rk(nn * sizeof(int));
+                NodeArgs na;
+                na.Om = Om.as<double2>();
+                na.Y = Y.as<double2>();
+                na.ldR = R;
+                na.moff = dmo->as<long>();
+                na.msz = dms->as<int>();
+                na.s = sl;
+                na.tol_abs = o->tol * g;
+                na.cap = o->rank_cap;
+                na.scratch = scratch.as<double2>();
+                na.stride = stride;
+                na.rank_out = rk.as<int>();
+                na.Uslot = root ? nullptr : h->Ubuf[l]->as<double2>();
+                na.uoff = duo->as<size_t>();
+                na.Dres = Dres[l]->as<double2>();
+                na.doff = ddo->as<size_t>();
+                na.root = root ? 1 : 0;
+                if (mmax < g_big_node) {
+                    k_node_basis<<<nn, node_threads(mmax), 0, s>>>(na);
+                    FIO_HIP(hipGetLastError());
+                } else {
+                    basis_big(na, ms, nn, mmax, sl, root, s);
+                }
+                if (!root) {
+                    h->rank[l].assign(nn, 0);
+                    FIO_HIP(hipMemcpyAsync(h->rank[l].data(), rk.p, nn * sizeof(int), hipMemcpyDeviceToHost, s));
+                    FIO_HIP(hipStreamSynchronize(s));
+                    // D-breve = X + U (X U)^*, X = T - U (U^* T), for all nodes of the level
+                    ZgemmBatch g1, g2, g3, g4;
+                    double2 *sc = scratch.as<double2>();
+                    int rmax = 0;
+                    for (int j = 0; j < nn; ++j) {
+                        const int m = ms[j], r = h->rank[l][j];
+                        if (m == 0) continue;
+                        rmax = r > rmax ? r : rmax;
+                        double2 *T = sc + stride * j + (size_t)sl * m;
+                        double2 *U = T + (size_t)m * sl, *P = U + (size_t)m * m, *X = P + (size_t)m * m;
+                        g1.add(U, m, T, m, P, m, r, m, m);        // P = U^* T      (r x m)
+                        g2.add(U, m, P, m, T, m, m, m, r);        // T -= U P       (X, m x m)
+                        g3.add(T, m, U, m, X, m, m, r, m);        // X slot = X U   (m x r)
+                        g4.add(U, m, P, m, T, m, m, m, r);        // T += U (X U)^* (D-breve)
+                    }
+                    g1.upload(s);
+                    g2.upload(s);
+                    g3.upload(s);
+                    g4.upload(s);
+                    g1.run(true, zc(1.0, 0.0), zc(0.0, 0.0), s);
+                    g2.run(false, zc(-1.0, 0.0), zc(1.0, 0.0), s);
+                    g3.run(false, zc(1.0, 0.0), zc(0.0, 0.0), s);
+                    if (rmax > 0) {
+                        dim3 gct((unsigned)((rmax * (size_t)mmax + 255) / 256), (unsigned)nn);
+                        k_node_conj_transpose<<<gct, 256, 0, s>>>(na);
+                    }
+                    g4.run(false, zc(1.0, 0.0), zc(1.0, 0.0), s);
+                    k_node_finish<<<nn, node_threads(mmax), 0, s>>>(na);
+                    FIO_HIP(hipGetLastError());
+                    FIO_HIP(hipStreamSynchronize(s));   // the descriptor lists are released here
+                }
                 FIO_HIP(hipStreamSynchronize(s));
-                // D-breve = X + U (X U)^*, X = T - U (U^* T), for all nodes of the level
-                ZgemmBatch g1, g2, g3, g4;
-                double2 *sc = scratch.as<double2>();
-                int rmax = 0;
-                for (int j = 0; j < nn; ++j) {
-                    const int m = ms[j], r = h->rank[l][j];
-                    if (m == 0) continue;
-                    rmax = r > rmax ? r : rmax;
-                    double2 *T = sc + stride * j + (size_t)sl * m;
-                    double2 *U = T + (size_t)m * sl, *P = U + (size_t)m * m, *X = P + (size_t)m * m;
-                    g1.add(U, m, T, m, P, m, r, m, m);        // P = U^* T      (r x m)
-                    g2.add(U, m, P, m, T, m, m, m, r);        // T -= U P       (X, m x m)
-                    g3.add(T, m, U, m, X, m, m, r, m);        // X slot = X U   (m x r)
-                    g4.add(U, m, P, m, T, m, m, m, r);        // T += U (X U)^* (D-breve)
-                }
-                g1.upload(s);
-                g2.upload(s);
-                g3.upload(s);
-                g4.upload(s);
-                g1.run(true, zc(1.0, 0.0), zc(0.0, 0.0), s);
-                g2.run(false, zc(-1.0, 0.0), zc(1.0, 0.0), s);
-                g3.run(false, zc(1.0, 0.0), zc(0.0, 0.0), s);
-                if (rmax > 0) {
-                    dim3 gct((unsigned)((rmax * (size_t)mmax + 255) / 256), (unsigned)nn);
-                    k_node_conj_transpose<<<gct, 256, 0, s>>>(na);
-                }
-                g4.run(false, zc(1.0, 0.0), zc(1.0, 0.0), s);
-                k_node_finish<<<nn, node_threads(mmax), 0, s>>>(na);
-                FIO_HIP(hipGetLastError());
-                FIO_HIP(hipStreamSynchronize(s));   // the descriptor lists are released here
-            }
-            FIO_HIP(hipStreamSynchronize(s));
-            delete dmo;
-            delete dms;
-            delete duo;
-            delete ddo;
-            h->drawn[l] += sl;
-            if (root || !o->adaptive || guess >= mmax) break;
-            int rl = 0;
-            for (int v : h->rank[l]) rl = v > rl ? v : rl;
-            if (rl <= guess) break;
-            guess = mmax;
+                delete dmo;
+                delete dms;
+                delete duo;
+                delete ddo;
+                h->drawn[l] += sl;
+                if (root || !o->adaptive || guess >= mmax) break;
+                int rl = 0;
+                for (int v : h->rank[l]) rl = v > rl ? v : rl;
+                if (rl <= guess) break;
+                guess = mmax;
             }
             if (!root && o->rank_cap > 0)
                 for (int v : h->rank[l])
