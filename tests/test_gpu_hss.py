@@ -32,6 +32,21 @@ def test_imported_hss_matvec_and_ulv_solve_match_oracle():
     assert perr(host(xd), ref) < 1e-12
 
 
+def test_ulv_solve_two_column_blocks_matches_oracle():
+    # 70 right-hand sides: a full 64-column block and a ragged one in every level product
+    # (the leaf level of 64-row nodes runs on the FP64 matrix cores)
+    F = fiohss()
+    n = 1024
+    step("ULV solve n=%d, 70 columns" % n)
+    h, fac = oracle_hss(n, 9, "sin16", 1e-3, 10, 1000)
+    ranks, gen = hss_generators(h)
+    U = F.ULV(F.HSS.from_generators(n, 64, ranks, gen))
+    x = fi.complex_gaussian(7, fi.PURPOSE_PROBE, n, 70)
+    c = host(U.solve(dev(x)))
+    ref = oulv.solve(fac, x)
+    assert perr(c, ref) < 1e-12
+
+
 def test_gpu_hss_build_matches_oracle_with_identical_inputs():
     F = fiohss()
     n = 1024
