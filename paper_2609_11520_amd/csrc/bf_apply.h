@@ -667,7 +667,9 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_stru
 #pragma unroll
         for (int r = 0; r < Q; ++r) lds[(dst * Q + r) * 64 + lane] = acc[r];
         if (TWL && st + 1 < KL && tid < NTW) stw[tid] = twn;
-        __syncthreads();
+        // After the last factor every wave touches only its own pair's rows (its output pair is
+        // its store pair: 2g + h), and LDS runs one wave's accesses in order: no barrier there.
+        if (st + 1 < KL) __syncthreads();
     }
     {
         const int lp = wave;

@@ -339,16 +339,21 @@ __global__ void __launch_bounds__((1 << KL) * 64, 4) k_split_fused(SplitArgsK a)
                     sA[SAF + e] = odd_form(pf[r]);
                 }
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
     {
-        const int lp = wave;
+        // The last factor of wave 2 g + h wrote output pairs 2 g and 2 g + 1 (both directions) for
+        // columns [32 h, 32 h + 32); the wave stores exactly these (lanes 0-31 the first pair,
+        // 32-63 the second), reading back only its own writes, so no barrier precedes the store.
+        const int lp = 2 * grp + (lane >> 5), n = nh * 32 + (lane & 31);
+        const float invn = __shfl(inv, n);
         const long gp = ADJ ? A * 2 * a.G0 + S * P + lp : (A * P + lp) * Glast + S;
-        C *dstp = a.out + (size_t)gp * Q * ld + col;
+        C *dstp = a.out + (size_t)gp * Q * ld + (size_t)blockIdx.y * 64 + n;
+        const bool actn = (int)(blockIdx.y * 64 + n) < a.nrhs;
 #pragma unroll
         for (int i = 0; i < Q; ++i)
-            if (act) dstp[i * ld] = cscale(ftile[pidx(lp * Q + i, lane)], inv);
+            if (actn) dstp[i * ld] = cscale(ftile[pidx(lp * Q + i, n)], invn);
     }
 }
 
