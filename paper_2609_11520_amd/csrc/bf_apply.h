@@ -607,9 +607,19 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_stru
         // put them.  Same operations, in the same order, as the leaf kernel followed by the load.
         constexpr int XP = 65;                                   // padded column stride of the staged rows
         static_assert(64 * XP <= P * Q * 64, "the staged rows fit the tile");
+        constexpr int VB = Q * kLeafPts, NVB = (VB + 63) / 64;   // entries of one leaf block, per lane
         const int cb = blockIdx.y * 64;
         const int ncol = a.nrhs - cb < 64 ? a.nrhs - cb : 64;
         const long box0 = ADJ ? A * P : S * P;                   // first leaf box of the workgroup
+        const long box = box0 + wave;
+        const long partner = ADJ ? S : A;
+        // the wave's leaf block (nsl = 8 partners), fetched with vector loads while the rows are
+        // staged, so that its latency overlaps theirs
+        const C *blk = a.V + ((size_t)box * kLeafPts + partner) * VB;
+        C vpf[NVB];
+#pragma unroll
+        for (int k2 = 0; k2 < NVB; ++k2)
+            if (lane + 64 * k2 < VB) vpf[k2] = blk[lane + 64 * k2];
         const double2 *xs = a.X + (size_t)box0 * kLeafPts;
         for (int e = tid; e < 64 * 64; e += P * 64) {
             const int r = e & 63, cc = e >> 6;
@@ -621,25 +631,30 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_stru
 #pragma unroll
         for (int t = 0; t < kLeafPts; ++t) x[t] = lds[lane * XP + wave * kLeafPts + t];
         __syncthreads();
-        const long box = box0 + wave;
-        const long partner = ADJ ? S : A;
-        const C *blk = a.V + ((size_t)box * kLeafPts + partner) * (Q * kLeafPts);   // nsl = 8 partners
+        // The staged rows are consumed: the block goes to the wave's own pair rows and is read
+        // back as broadcasts; the q outputs stay in registers until every read is done, then
+        // overwrite those rows (LDS runs one wave's accesses in order).
+        C *vs = lds + (size_t)wave * Q * 64;
+#pragma unroll
+        for (int k2 = 0; k2 < NVB; ++k2)
+            if (lane + 64 * k2 < VB) vs[lane + 64 * k2] = vpf[k2];
+        __builtin_amdgcn_wave_barrier();
+        C lacc[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            // double precision: an opaque row offset keeps the block's scalar loads with their
-            // row (the whole 8 x q block does not fit the scalar registers)
-            int oi = i;
-            if constexpr (sizeof(T) == 8) asm volatile("" : "+s"(oi));
             C acc = czero<C>();
 #pragma unroll
             for (int t = 0; t < kLeafPts; ++t) {
                 if constexpr (ADJ)
-                    cfmac(acc, blk[t * Q + oi], x[t]);
+                    cfmac(acc, vs[t * Q + i], x[t]);
                 else
-                    cfma(acc, blk[oi * kLeafPts + t], x[t]);
+                    cfma(acc, vs[i * kLeafPts + t], x[t]);
             }
-            lds[(wave * Q + i) * 64 + lane] = acc;
+            lacc[i] = acc;
         }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int i = 0; i < Q; ++i) lds[(wave * Q + i) * 64 + lane] = lacc[i];
     } else {
         const int lp = wave;
         const long gp = ADJ ? (A * P + lp) * Glast + S : A * 2 * a.G0 + S * P + lp;
