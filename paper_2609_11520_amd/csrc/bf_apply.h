@@ -810,10 +810,10 @@ __global__ void __launch_bounds__(256, 4) k_leaf_io(Geo g, const cpx<T> *__restr
     constexpr int NCH = BLK * (int)sizeof(C) / 16;  // its 16-byte chunks
     constexpr int NPF = (NCH + 63) / 64;
     __shared__ C tile[64][R + 1];                   // [column][row]
-    // IN: one factor block per wave; the block of the wave's next unit is fetched into
-    // registers (vector loads) while the current one is applied, then written here and read
-    // back as broadcasts
-    __shared__ __attribute__((aligned(16))) C wblk[IN ? 4 : 1][IN ? BLK : 1];
+    // one factor block per wave; the block of the wave's next unit (IN) or next coarse partner
+    // (out) is fetched into registers (vector loads) while the current one is applied, then
+    // written here and read back as broadcasts
+    __shared__ __attribute__((aligned(16))) C wblk[4][BLK];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const long box0 = (long)blockIdx.x * NB;        // first leaf box of the workgroup
@@ -831,7 +831,7 @@ __global__ void __launch_bounds__(256, 4) k_leaf_io(Geo g, const cpx<T> *__restr
             if (lane + 64 * k < NCH) pf[k] = src[lane + 64 * k];
     };
     auto stage = [&]() {
-        uint4 *dst = reinterpret_cast<uint4 *>(&wblk[IN ? wave : 0][0]);
+        uint4 *dst = reinterpret_cast<uint4 *>(&wblk[wave][0]);
 #pragma unroll
         for (int k = 0; k < NPF; ++k)
             if (lane + 64 * k < NCH) dst[lane + 64 * k] = pf[k];
@@ -878,35 +878,63 @@ __global__ void __launch_bounds__(256, 4) k_leaf_io(Geo g, const cpx<T> *__restr
             __builtin_amdgcn_wave_barrier();
         }
     } else {
-        // each wave produces one box's rows for its lane's column
-        for (int b = wave; b < NB; b += 4) {
-            const long box = box0 + b;
-            C acc[kLeafPts];
+        // each wave produces one box's rows for its lane's column (NB = 4 boxes, 4 waves)
+        static_assert(NB == 4, "one leaf box per wave");
+        const int b = wave;
+        const long box = box0 + b;
+        const C *blk = &wblk[wave][0];
+        C acc[kLeafPts];
 #pragma unroll
-            for (int s = 0; s < kLeafPts; ++s) acc[s] = czero<C>();
-            for (int c = 0; c < g.nsl; ++c) {
-                // V^*: block V[sigma = box][tau = c], pair c 2^L' + box; U: block U[tau = box][sigma = c],
-                // pair box nsl + c.  The block is read through the scalar cache here (as LDS values
-                // the compiler would hold all of it in vector registers).
-                const size_t p = VSIDE ? (size_t)c * Lp2 + box : (size_t)box * g.nsl + c;
-                const C *blk = Fblk + ((size_t)box * g.nsl + c) * BLK;
-                C d[Q];
-                const C *ip = cin + p * Q * (size_t)nrhs + col;
+        for (int s = 0; s < kLeafPts; ++s) acc[s] = czero<C>();
+        // blocks of partners c = 0 .. nsl - 1 of the box follow one another in memory
+        const uint4 *bsrc = reinterpret_cast<const uint4 *>(Fblk + (size_t)box * g.nsl * BLK);
+        uint4 *bdst = reinterpret_cast<uint4 *>(&wblk[wave][0]);
 #pragma unroll
-                for (int i = 0; i < Q; ++i) d[i] = act ? ip[(size_t)i * nrhs] : czero<C>();
+        for (int k = 0; k < NPF; ++k)
+            if (lane + 64 * k < NCH) bdst[lane + 64 * k] = bsrc[lane + 64 * k];
+        __builtin_amdgcn_wave_barrier();
+        for (int c = 0; c < g.nsl; ++c) {
+            // V^*: block V[sigma = box][tau = c], pair c 2^L' + box; U: block U[tau = box][sigma = c],
+            // pair box nsl + c.  The next partner's block is on its way while this one is applied.
+            const size_t p = VSIDE ? (size_t)c * Lp2 + box : (size_t)box * g.nsl + c;
+            uint4 nb[NPF];
+            const bool more = c + 1 < g.nsl;
 #pragma unroll
-                for (int s = 0; s < kLeafPts; ++s)
+            for (int k = 0; k < NPF; ++k)
+                if (more && lane + 64 * k < NCH) nb[k] = bsrc[(size_t)(c + 1) * NCH + lane + 64 * k];
+            // inactive lanes (columns beyond nrhs) read column c0 and use zeros: no branches
+            C d[Q];
+            const C *ip = cin + p * Q * (size_t)nrhs + (act ? col : c0);
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) {
-                        if (VSIDE)
-                            cfmac(acc[s], blk[i * kLeafPts + s], d[i]);
-                        else
-                            cfma(acc[s], blk[s * Q + i], d[i]);
-                    }
+            for (int i = 0; i < Q; ++i) {
+                const C v = ip[(size_t)i * nrhs];
+                d[i] = act ? v : czero<C>();
             }
+            // input index outermost (each acc[s] still sums over i in order): one column of the
+            // block is live at a time
 #pragma unroll
-            for (int s = 0; s < kLeafPts; ++s) tile[lane][b * kLeafPts + s] = acc[s];
+            for (int i = 0; i < Q; ++i) {
+#pragma unroll
+                for (int s = 0; s < kLeafPts; ++s) {
+                    if (VSIDE)
+                        cfmac(acc[s], blk[i * kLeafPts + s], d[i]);
+                    else
+                        cfma(acc[s], blk[s * Q + i], d[i]);
+                }
+            }
+            // The products are finished before the next block overwrites this one (else the
+            // compiler would read the whole block ahead, hold it in vector registers and sink the
+            // products below the overwrite); LDS runs a wave's accesses in order.
+#pragma unroll
+            for (int s = 0; s < kLeafPts; ++s) asm volatile("" : "+v"(acc[s].x), "+v"(acc[s].y)::"memory");
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int k = 0; k < NPF; ++k)
+                if (more && lane + 64 * k < NCH) bdst[lane + 64 * k] = nb[k];
+            __builtin_amdgcn_wave_barrier();
         }
+#pragma unroll
+        for (int s = 0; s < kLeafPts; ++s) tile[lane][b * kLeafPts + s] = acc[s];
         __syncthreads();
         for (int e = tid; e < R * 64; e += 256) {
             const int r = e % R, cc = e / R;
