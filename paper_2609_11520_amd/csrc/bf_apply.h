@@ -597,6 +597,19 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_stru
     constexpr int NMP = (Q * Q + 63) / 64;
     C mpf[NMP];
     if (TWL && tid < NTW) stw[tid] = tw_src(ADJ ? KL - 1 : 0, tid);
+    // When the pass applies M, the middle block of this wave's output pair is fetched into
+    // registers for the store phase: in double precision before the load phase, so that its
+    // latency overlaps the coefficients' (measured faster); in single precision during the last
+    // factor (the registers held through the pass cost more there than the latency).
+    auto fetch_m = [&]() {
+        const long gpo = ADJ ? A * 2 * a.G0 + S * P + wave : (A * P + wave) * Glast + S;
+        const C *msrc = a.M + (size_t)gpo * Q * Q;
+#pragma unroll
+        for (int k2 = 0; k2 < NMP; ++k2)
+            if (lane + 64 * k2 < Q * Q) mpf[k2] = msrc[lane + 64 * k2];
+    };
+    constexpr bool EARLY_M = EPI_M && sizeof(T) == 8;
+    if constexpr (EARLY_M) fetch_m();
     if constexpr (LEAF) {
         // Forward, the input pairs are (coarse partner A, leaf boxes 8S .. 8S + 7): pair
         // A 2^L' + box holds V[box][A] applied to rows 8 box .. 8 box + 7 of the input.  Adjoint,
@@ -668,14 +681,8 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_stru
     for (int st = 0; st < KL; ++st) {
         const int j = ADJ ? KL - 1 - st : st;
         if (TWL && st + 1 < KL && tid < NTW) twn = tw_src(ADJ ? j - 1 : j + 1, tid);
-        if (EPI_M && st == KL - 1) {
-            // the middle block of this wave's output pair, for the store phase
-            const long gpo = ADJ ? A * 2 * a.G0 + S * P + wave : (A * P + wave) * Glast + S;
-            const C *msrc = a.M + (size_t)gpo * Q * Q;
-#pragma unroll
-            for (int k2 = 0; k2 < NMP; ++k2)
-                if (lane + 64 * k2 < Q * Q) mpf[k2] = msrc[lane + 64 * k2];
-        }
+        if constexpr (EPI_M && !EARLY_M)
+            if (st == KL - 1) fetch_m();
         C acc[Q];
         const int dst = struct_step<T, Q, KL, ADJ, CS>(a, lds, stw + grp * 8 * Q, grp, h, j, lane, acc);
         __syncthreads();
