@@ -596,7 +596,10 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_stru
     C twn = czero<C>();
     constexpr int NMP = (Q * Q + 63) / 64;
     C mpf[NMP];
-    if (TWL && tid < NTW) stw[tid] = tw_src(ADJ ? KL - 1 : 0, tid);
+    // Loads carry no branch (out-of-range lanes read a valid element and discard it): a load
+    // under a lane condition sits in a block of its own, and the wait for it comes before the
+    // next load is issued, which serializes the round trips of the load phase.
+    const C tw0 = tw_src(ADJ ? KL - 1 : 0, tid < NTW ? tid : 0);
     // When the pass applies M, the middle block of this wave's output pair is fetched into
     // registers for the store phase: in double precision before the load phase, so that its
     // latency overlaps the coefficients' (measured faster); in single precision during the last
@@ -605,8 +608,7 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_stru
         const long gpo = ADJ ? A * 2 * a.G0 + S * P + wave : (A * P + wave) * Glast + S;
         const C *msrc = a.M + (size_t)gpo * Q * Q;
 #pragma unroll
-        for (int k2 = 0; k2 < NMP; ++k2)
-            if (lane + 64 * k2 < Q * Q) mpf[k2] = msrc[lane + 64 * k2];
+        for (int k2 = 0; k2 < NMP; ++k2) mpf[k2] = msrc[lane + 64 * k2 < Q * Q ? lane + 64 * k2 : Q * Q - 1];
     };
     constexpr bool EARLY_M = EPI_M && sizeof(T) == 8;
     if constexpr (EARLY_M) fetch_m();
@@ -631,13 +633,20 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_stru
         const C *blk = a.V + ((size_t)box * kLeafPts + partner) * VB;
         C vpf[NVB];
 #pragma unroll
-        for (int k2 = 0; k2 < NVB; ++k2)
-            if (lane + 64 * k2 < VB) vpf[k2] = blk[lane + 64 * k2];
+        for (int k2 = 0; k2 < NVB; ++k2) vpf[k2] = blk[lane + 64 * k2 < VB ? lane + 64 * k2 : VB - 1];
         const double2 *xs = a.X + (size_t)box0 * kLeafPts;
-        for (int e = tid; e < 64 * 64; e += P * 64) {
-            const int r = e & 63, cc = e >> 6;
-            const double2 v = cc < ncol ? xs[r + (size_t)(cb + cc) * a.ldx] : zc(0.0, 0.0);
-            lds[cc * XP + r] = cmake<C>((T)v.x, (T)v.y);
+        constexpr int NXS = 64 * 64 / (P * 64);                  // staged elements per thread
+        double2 xv[NXS];
+#pragma unroll
+        for (int q = 0; q < NXS; ++q) {
+            const int e = tid + q * P * 64, r = e & 63, cc = e >> 6;
+            xv[q] = xs[r + (size_t)(cb + (cc < ncol ? cc : 0)) * a.ldx];
+        }
+        if (TWL && tid < NTW) stw[tid] = tw0;
+#pragma unroll
+        for (int q = 0; q < NXS; ++q) {
+            const int e = tid + q * P * 64, r = e & 63, cc = e >> 6;
+            lds[cc * XP + r] = cc < ncol ? cmake<C>((T)xv[q].x, (T)xv[q].y) : czero<C>();
         }
         __syncthreads();
         C x[kLeafPts];
@@ -671,16 +680,20 @@ __global__ void __launch_bounds__((1 << KL) * 64, sizeof(T) == 4 ? 6 : 4) k_stru
     } else {
         const int lp = wave;
         const long gp = ADJ ? (A * P + lp) * Glast + S : A * 2 * a.G0 + S * P + lp;
-        const C *src = a.in + (size_t)gp * Q * ld + col;
+        const C *src = a.in + (size_t)gp * Q * ld + (act ? col : (int)blockIdx.y * 64);
+        C v[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) lds[(lp * Q + i) * 64 + lane] = act ? src[i * ld] : czero<C>();
+        for (int i = 0; i < Q; ++i) v[i] = src[i * ld];
+        if (TWL && tid < NTW) stw[tid] = tw0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) lds[(lp * Q + i) * 64 + lane] = act ? v[i] : czero<C>();
     }
     __syncthreads();
     const int grp = wave >> 1, h = wave & 1;
 #pragma unroll
     for (int st = 0; st < KL; ++st) {
         const int j = ADJ ? KL - 1 - st : st;
-        if (TWL && st + 1 < KL && tid < NTW) twn = tw_src(ADJ ? j - 1 : j + 1, tid);
+        if (TWL && st + 1 < KL) twn = tw_src(ADJ ? j - 1 : j + 1, tid < NTW ? tid : 0);
         if constexpr (EPI_M && !EARLY_M)
             if (st == KL - 1) fetch_m();
         C acc[Q];

@@ -186,13 +186,16 @@ __global__ void __launch_bounds__((1 << KL) * 64, 4) k_split_fused(SplitArgsK a)
         const long g = (A * (1L << j) + b / Gl) * (a.G0 >> j) + S * Gl + b % Gl;
         return a.A[j] + (size_t)g * BLK4 + o;
     };
+    // Loads carry no branch (out-of-range threads read a valid element and discard it): a load
+    // under a thread condition sits in a block of its own, and the wait for it comes before the
+    // next load is issued.
     u4 pf[NSTG];
     {
         const int j0 = ADJ ? KL - 1 : 0;
 #pragma unroll
         for (int r = 0; r < NSTG; ++r) {
             const int e = tid + r * NT;
-            if (e < NG * BLK4) pf[r] = *blk_src(j0, e);
+            pf[r] = *blk_src(j0, e < NG * BLK4 ? e : 0);
         }
     }
     // load pair `wave`, scale per column, split into the planes at the first factor's slots
@@ -200,12 +203,14 @@ __global__ void __launch_bounds__((1 << KL) * 64, 4) k_split_fused(SplitArgsK a)
     {
         const int lp = wave;
         const long gp = ADJ ? (A * P + lp) * Glast + S : A * 2 * a.G0 + S * P + lp;
-        const C *src = a.in + (size_t)gp * Q * ld + col;
+        const C *src = a.in + (size_t)gp * Q * ld + (act ? col : (int)blockIdx.y * 64);
         C v[Q];
         float m = 0.f;
 #pragma unroll
+        for (int i = 0; i < Q; ++i) v[i] = src[i * ld];
+#pragma unroll
         for (int i = 0; i < Q; ++i) {
-            v[i] = act ? src[i * ld] : make_float2(0.f, 0.f);
+            if (!act) v[i] = make_float2(0.f, 0.f);
             m = fmaxf(m, fmaxf(fabsf(v[i].x), fabsf(v[i].y)));
         }
         cmax[lp][lane] = m;
@@ -273,7 +278,7 @@ __global__ void __launch_bounds__((1 << KL) * 64, 4) k_split_fused(SplitArgsK a)
 #pragma unroll
             for (int r = 0; r < NSTG; ++r) {
                 const int e = tid + r * NT;
-                if (e < NG * BLK4) pf[r] = *blk_src(jn, e);
+                pf[r] = *blk_src(jn, e < NG * BLK4 ? e : 0);
             }
         }
         u4 Bop[2][4];
