@@ -316,14 +316,17 @@ __global__ void __launch_bounds__(128) k2_step(K2Args<T> a) {
 #pragma unroll
     for (int c = 0; c < KC; ++c) acc[c] = czero<C>();
     const int nbs = a.nb / a.nsplit;
+    // lanes beyond the block's rows read its last row (no lane condition on the loads, which would
+    // put each one in a block of its own and wait for it there) and store nothing
+    const int rc = act ? r : R - 1;
     for (int bb = split * nbs; bb < (split + 1) * nbs; ++bb) {
-        const C *Ab = a.A + ((size_t)o * a.nb + bb) * R * CC + r;
+        const C *Ab = a.A + ((size_t)o * a.nb + bb) * R * CC + rc;
         if (STEP == VF || STEP == UA) {
             // input from a user vector: the b^2 points of one leaf box
             const long base = (STEP == VF) ? (o % g.S) * g.b2 : (o / g.T) * g.b2;
             const bool internal = STEP == VF && a.fint;
             for (int j = 0; j < CC; ++j) {
-                const C av = act ? Ab[(size_t)j * R] : czero<C>();
+                const C av = Ab[(size_t)j * R];
                 const long m = base + j;
                 const long row = internal ? m : lex_of(m, g.L, g.n);
                 const double2 *xp = a.X + row + (size_t)c0 * a.ldx;
@@ -349,7 +352,7 @@ __global__ void __launch_bounds__(128) k2_step(K2Args<T> a) {
             const C *xp = a.cin + (size_t)srow * g.q2 * a.ldc + c0;
 #pragma unroll 3
             for (int j = 0; j < CC; ++j) {
-                const C av = act ? Ab[(size_t)j * R] : czero<C>();
+                const C av = Ab[(size_t)j * R];
 #pragma unroll
                 for (int c = 0; c < KC; ++c) cfma(acc[c], av, xp[(size_t)j * a.ldc + c]);
             }
