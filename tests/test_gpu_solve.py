@@ -164,3 +164,25 @@ def test_dense_rhs_error_is_the_butterfly_error():
     assert 1e-7 < e_refined < 1e-4
     assert 1e-7 < e_direct < 1e-4
     assert e_tilde < 1e-11
+
+
+def test_empty_batch_is_a_no_op():
+    """Zero right-hand sides: every entry point of the path accepts an (N, 0) block, returns
+    FIO_OK and launches nothing; a following call on the same handles is unaffected."""
+    F = fiohss()
+    step("empty batch n=1024")
+    B, U, ob, fac = setup_imported(F)
+    z = F.empty(1024, 0)
+    for prec in (F.FIO_PREC_FP64, F.FIO_PREC_FP32, F.FIO_PREC_SPLIT_FP16):
+        assert tuple(B.apply(z, prec).shape) == (1024, 0)
+        assert tuple(B.apply_adj(z, prec).shape) == (1024, 0)
+    assert tuple(U.solve(z).shape) == (1024, 0)
+    for mode, prec, steps in ((F.FIO_SOLVE_DIRECT, 0, 0), (F.FIO_SOLVE_IR, 2, 1), (F.FIO_SOLVE_PCG, 0, 3)):
+        fh, info = F.approx_solve(B, U, z, mode=mode, prec=prec, max_ir=steps)
+        assert tuple(fh.shape) == (1024, 0)
+    fh, info = F.approx_solve_static(B, U, z, mode=F.FIO_SOLVE_IR, prec=2, max_ir=1)
+    assert tuple(fh.shape) == (1024, 0)
+    f = fi.rhs(0, 1024, 3)
+    u = ob.apply(f)
+    fh, info = F.approx_solve(B, U, dev(u))
+    assert perr(host(fh), osolve.direct_solve(ob, fac, u)) < 1e-12
