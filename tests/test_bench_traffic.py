@@ -50,3 +50,23 @@ def test_traffic_summary_scales_by_the_copy_and_averages_per_kernel(tmp_path, ca
     assert ks["bf_split16"]["algorithmic_bytes_per_launch"] == bench.kernel_model("bf_split16", n, 9, k)[0]
     assert d["source_hash"] == bench.kernel_source_hash()
     assert "| bf_split16 | 2 |" in capsys.readouterr().out
+
+
+def test_roofline_prices_the_explicit_form_per_launch():
+    """The roofline of the headline's passes at N = 2^18, q = 9, 64 columns, from the explicit
+    factor form written out here: 12 transfer levels of (N/2) groups of 2q x 2q entries in four
+    3-level passes, the middle factor's N q^2 entries on one of them, 8 bytes per entry as split
+    halves (16 in FP64); 8 flops per entry and column, three split products on the matrix cores;
+    the coefficient round trip 2 N q k e apart.  A measured launch time then fixes frac."""
+    n, q, k = 1 << 18, 9, 64
+    assert bench.pass_plan(n) == [(3, False), (3, True), (3, False), (3, False)]
+    per_pass = (3 * (n // 2) * (2 * q) ** 2 * 4 + n * q * q) / 4      # entries, M averaged over 4 passes
+    byts, flops, spill, peak = bench.kernel_model("bf_split16", n, q, k)
+    assert byts == per_pass * 8 == 1061683200
+    assert flops == 3 * 8 * per_pass * k and spill == 2 * n * q * k * 8 and peak == 2500.0
+    r = bench.roofline_of("bf_split16", n, q, k, 0.7422, None)
+    assert r["bound"] == "hbm" and abs(r["frac"] - 1061683200 / 0.7422e-3 / 8e12) < 1e-4
+    byts, flops, spill, peak = bench.kernel_model("bf_struct_f64", n, q, k)
+    assert byts == per_pass * 16 and flops == 8 * per_pass * k and spill == 2 * n * q * k * 16 and peak == 78.6
+    r = bench.roofline_of("bf_struct_f64", n, q, k, 1.3278, None)
+    assert r["bound"] == "alu" and abs(r["achieved"] - 8 * per_pass * k / 1.3278e-3 / 1e12) < 0.01
