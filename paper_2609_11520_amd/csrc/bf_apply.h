@@ -437,6 +437,7 @@ template <typename T, int Q> struct StructArgs {
     long ldx;
     T P[2][Q][Q];            // P_c(i, t)
     T PT[2][Q][Q];           // P_c(t, i): the transposes, so that every variant reads one pattern
+    T SD[Q][Q];              // column t: S(r, t), r < (q+1)/2, then D(r, t), r < q/2 (see struct_step)
 };
 
 // One transfer factor of a structured pass for the calling wave: group grp of forward step j,
@@ -482,7 +483,7 @@ __device__ __forceinline__ int struct_step(const StructArgs<T, Q> &a, const cpx<
             // loads are issued with the column (the whole matrix at once would not fit the
             // scalar registers and would be spilled into vector lanes)
             int ot = t * Q;
-            if constexpr (D) asm volatile("" : "+s"(ot));
+            asm volatile("" : "+s"(ot));
             const C x0 = lds[(s0 * Q + t) * 64 + lane], x1 = lds[(s1 * Q + t) * 64 + lane];
             const C w0 = ADJ ? cmul(cconj(t0[t]), x0) : cmul(t0[2 * Q + t], x0);
             const C w1 = ADJ ? cmul(cconj(t1[t]), x1) : cmul(t1[2 * Q + t], x1);
@@ -506,31 +507,53 @@ __device__ __forceinline__ int struct_step(const StructArgs<T, Q> &a, const cpx<
             }
         }
     } else {
+        // Both quadrants sum into one output through G_o = P_o^T, o = the child summed over
+        // (forward: c_in, adjoint: c_out).  The Chebyshev points are symmetric about the box
+        // centre, so P_1(i, t) = P_0(q-1-i, q-1-t), i.e. G_1 = J G_0 J with J the index reversal.
+        // With z_t = w_1[q-1-t], s = w_0 + z and d = w_0 - z, rows r and r' = q-1-r of the sum
+        // are S_r.s + D_r.d and S_r.s - D_r.d with S = (G_0(r, .) + G_0(r', .)) / 2 and
+        // D = (G_0(r, .) - G_0(r', .)) / 2, and the middle row of odd q is G_0(m, .).s: half the
+        // multiply-adds of the two separate quadrant products (StructArgs::SD holds S and D).
+        constexpr int NS = (Q + 1) / 2, ND = Q / 2;
+        const int c0out = ADJ ? 0 : h, c0in = ADJ ? h : 0, c1out = ADJ ? 1 : h, c1in = ADJ ? h : 1;
+        const int src0 = ADJ ? lout0 : lin0, src1 = ADJ ? lout0 + Gl : lin0 + 1;
+        // input-side twiddles: forward b(c_out, c_in, .), adjoint conj(a(c_out, c_in, .))
+        const C *tw0 = tw + c0out * 4 * Q + (ADJ ? c0in : 2 + c0in) * Q;
+        const C *tw1 = tw + c1out * 4 * Q + (ADJ ? c1in : 2 + c1in) * Q;
+        C e[NS], f[ND];
 #pragma unroll
-        for (int o = 0; o < 2; ++o) {
-            // FWD: o = c_in, output child c_out = h.  ADJ: o = c_out, input child c_in = h.
-            const int cout = ADJ ? o : h, cin = ADJ ? h : o;
-            const int srcp = ADJ ? (o ? lout0 + Gl : lout0) : lin0 + o;
-            const C *ta = tw + cout * 4 * Q + cin * Q;          // a(c_out, c_in, .)
-            const C *tb = tw + cout * 4 * Q + (2 + cin) * Q;    // b(c_out, c_in, .)
-            // In double precision an opaque zero offset makes each child load its matrix for
-            // itself (otherwise the compiler keeps all 2 q^2 scalar registers of both matrices
-            // live and spills them into vector lanes).
-            int opaque0 = 0;
-            if constexpr (D) asm volatile("s_mov_b32 %0, 0" : "=s"(opaque0));
-            const T *Pm = (!TRANS ? &a.PT[0][0][0] : &a.P[0][0][0]) + (CS ? cin : cout) * Q * Q + opaque0;
+        for (int r = 0; r < NS; ++r) e[r] = czero<C>();
 #pragma unroll
-            for (int t = 0; t < Q; ++t) {
-                const C x = lds[(srcp * Q + t) * 64 + lane];
-                const C wt = ADJ ? cmul(cconj(ta[t]), x) : cmul(tb[t], x);
+        for (int r = 0; r < ND; ++r) f[r] = czero<C>();
 #pragma unroll
-                for (int r = 0; r < Q; ++r) {
-                    const T m = Pm[t * Q + r];
-                    acc[r].x = fma(m, wt.x, acc[r].x);
-                    acc[r].y = fma(m, wt.y, acc[r].y);
-                }
+        for (int t = 0; t < Q; ++t) {
+            // one column of S and D per input index, loaded with the column (an opaque offset,
+            // so that the whole matrix is not held in scalar registers)
+            int ot = t * Q;
+            asm volatile("" : "+s"(ot));
+            const C x0 = lds[(src0 * Q + t) * 64 + lane], x1 = lds[(src1 * Q + (Q - 1 - t)) * 64 + lane];
+            const C w0 = ADJ ? cmul(cconj(tw0[t]), x0) : cmul(tw0[t], x0);
+            const C z = ADJ ? cmul(cconj(tw1[Q - 1 - t]), x1) : cmul(tw1[Q - 1 - t], x1);
+            const C sv = cadd(w0, z), dv = csub(w0, z);
+#pragma unroll
+            for (int r = 0; r < NS; ++r) {
+                const T m = (&a.SD[0][0])[ot + r];
+                e[r].x = fma(m, sv.x, e[r].x);
+                e[r].y = fma(m, sv.y, e[r].y);
+            }
+#pragma unroll
+            for (int r = 0; r < ND; ++r) {
+                const T m = (&a.SD[0][0])[ot + NS + r];
+                f[r].x = fma(m, dv.x, f[r].x);
+                f[r].y = fma(m, dv.y, f[r].y);
             }
         }
+#pragma unroll
+        for (int r = 0; r < ND; ++r) {
+            acc[r] = cadd(e[r], f[r]);
+            acc[Q - 1 - r] = csub(e[r], f[r]);
+        }
+        if constexpr (Q % 2 == 1) acc[ND] = e[ND];
     }
     if (FACT) {
         // forward C side: a(c_out, .) of either input child; adjoint B side: b(., c_in) of
@@ -1061,6 +1084,19 @@ static void apply_q(fio_bf_s *bf, bool adj, const double2 *X, long ldx, double2 
                             sa.P[c][i][t] = (T)bf->Pchild[(c * Q + i) * Q + t];
                             sa.PT[c][t][i] = sa.P[c][i][t];
                         }
+                // symmetric and antisymmetric row combinations of G_0 = P_0^T, in double
+                // precision before rounding to T: G_0(r, t) = P_0(t, r)
+                for (int t = 0; t < Q; ++t) {
+                    const double *p0 = bf->Pchild;
+                    for (int r = 0; r < (Q + 1) / 2; ++r) {
+                        const double g = p0[t * Q + r], gm = p0[t * Q + (Q - 1 - r)];
+                        sa.SD[t][r] = (T)(2 * r + 1 == Q ? g : 0.5 * (g + gm));
+                    }
+                    for (int r = 0; r < Q / 2; ++r) {
+                        const double g = p0[t * Q + r], gm = p0[t * Q + (Q - 1 - r)];
+                        sa.SD[t][(Q + 1) / 2 + r] = (T)(0.5 * (g - gm));
+                    }
+                }
                 if (leaf) {
                     FIO_TIMED(f64 ? "bf_struct_leaf_f64" : "bf_struct_leaf_f32", s);
                     run_struct_leaf<T, Q>(sa, a, epi, bf->N, s);

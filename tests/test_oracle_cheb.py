@@ -31,3 +31,29 @@ def test_batched_matches_single():
     a = cheb.lagrange_values(np.stack([z, z + 1.0]), np.stack([x, x + 1.0]))
     assert np.allclose(a[0], cheb.lagrange_matrix(z, x), atol=1e-13)
     assert np.allclose(a[1], cheb.lagrange_matrix(z + 1.0, x + 1.0), atol=1e-11)
+
+
+@pytest.mark.parametrize("q", [5, 9, 13])
+def test_child_interpolation_mirror_symmetry(q):
+    """The Chebyshev points are symmetric about the box centre, so interpolating from the parent
+    basis at child 1's points is child 0's matrix with both indices reversed:
+    P_1(i, t) = P_0(q-1-i, q-1-t).  The structured passes use this to sum the two quadrants of a
+    factor through symmetric and antisymmetric row combinations of one matrix; here the identity
+    and that sum are checked on the oracle's matrices (random complex inputs)."""
+    P = cheb.child_lagrange(q)
+    assert np.max(np.abs(P[1] - P[0][::-1, ::-1])) < 1e-14
+    G0, G1 = P[0].T, P[1].T
+    rng = np.random.default_rng(q)
+    w0, w1 = (rng.standard_normal(q) + 1j * rng.standard_normal(q) for _ in range(2))
+    z = w1[::-1]
+    s, d = w0 + z, w0 - z
+    m = q // 2
+    S = 0.5 * (G0 + G0[::-1])
+    S[m] = G0[m]
+    D = 0.5 * (G0 - G0[::-1])
+    v = np.empty(q, dtype=complex)
+    v[:m] = S[:m] @ s + D[:m] @ d
+    v[q - m:] = (S[:m] @ s - D[:m] @ d)[::-1]
+    v[m] = S[m] @ s
+    ref = G0 @ w0 + G1 @ w1
+    assert np.max(np.abs(v - ref)) < 1e-13 * np.max(np.abs(ref))
