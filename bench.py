@@ -816,6 +816,40 @@ def main():
             with open(a.tune_file, "w") as fh:
                 fh.write(B.tune_export())
     log("autotuned tiles (%s)" % tune_source, json.dumps(tuned))
+    # the split-precision K~^* apply with each engine pinned (matrix cores: split-FP16 passes;
+    # vector units: FP32 structured passes), whatever the tuner chose, so that both engines are
+    # measured on every run; the tuned configuration is restored afterwards
+    split_engines = {}
+    tuned_adj = B.get_tile(k, prec=F.FIO_PREC_SPLIT_FP16, adj=True)
+    wsa = torch.empty(B.workspace_size(k, F.FIO_PREC_SPLIT_FP16), dtype=torch.uint8, device=dev)
+    ya = F.empty(n, k)
+    for eng, valu in (("mfma", 0), ("valu", 1)):
+        cfg = dict(tuned_adj)
+        cfg.update(kmax=3, valu=valu)
+        B.set_tile(k, F.FIO_PREC_SPLIT_FP16, True, **cfg)
+        for _ in range(2):
+            B.apply_adj(u, prec=F.FIO_PREC_SPLIT_FP16, out=ya, ws=wsa)
+        sync()
+        F.timing_reset()
+        F.timing_enable(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            B.apply_adj(u, prec=F.FIO_PREC_SPLIT_FP16, out=ya, ws=wsa)
+        e1.record()
+        sync()
+        F.timing_enable(False)
+        rec = {"apply_ms": round(e0.elapsed_time(e1) / 10, 4)}
+        pk = "bf_split16" if valu == 0 else "bf_struct_f32"
+        cnt, ms = F.timing_query(pk)
+        if cnt:
+            rec["pass_kernel"] = pk
+            rec["roofline"] = roofline_of(pk, n, q, k, ms / cnt, stored_traffic(pk))
+        split_engines[eng] = rec
+    B.set_tile(k, F.FIO_PREC_SPLIT_FP16, True, **tuned_adj)
+    split_engines["tuned_adjoint_engine"] = "valu" if tuned_adj["valu"] else "mfma"
+    del ya, wsa
+    log("split-precision K~^* engines", json.dumps(split_engines))
 
     results = {}
     kernel_stats = {}
@@ -1016,7 +1050,8 @@ def main():
     line = {
         "metric": METRIC, "value": round(mixed["value"], 2), "unit": "RHS/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(mixed["ms_per_step"], 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "fp16x2+fp32+fp64" if head == "split16" else "fp32+fp64",
+        "scaling": "weak", "vs_baseline": None, "dtype": ("fp16x2+fp32+fp64" if head == "split16" and split_engines["tuned_adjoint_engine"] == "mfma"
+                  else "fp32+fp64"),
         "data": "synthetic",
         "config": {"workload": "1D FIO N=2^%d, c(x)=(2+sin 2pi x)/16, q=%d, HSS tol %g, p=10, %d RHS, "
                                "refinement steps calibrated to rel residual %g" % (int(np.log2(n)), q, a.hss_tol, k,
@@ -1037,7 +1072,7 @@ def main():
                       "hss_adaptive_rhat16": round(t_hss_ad, 3), "hss_adaptive_max_rank_per_level": ranks_ad},
         "kernels_ms": {p: {kn: [c, round(m, 3)] for kn, (c, m) in d.items()} for p, d in kernel_stats.items()},
         "serving": serve, "workload_2d": w2d, "workload_var_amp": wamp, "workload_2d_var_amp": w2a,
-        "workload_2e16": w16, "accuracy_ok": accuracy_ok,
+        "workload_2e16": w16, "split_precision_engines": split_engines, "accuracy_ok": accuracy_ok,
         "roofline": roof, "roofline_by_kernel": others, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
