@@ -552,36 +552,40 @@ __global__ void __launch_bounds__(256) k_ulv_level(LevelArgs a, const double2 *_
 #pragma unroll
         for (int y = 0; y < 2; ++y) acc[x][y] = zc(0.0, 0.0);
     for (int k0 = 0; k0 < m; k0 += 16) {
-        for (int e = tid; e < 512; e += 256) {
-            int mm, kk;
-            double2 v = zc(0.0, 0.0);
+        // all four loads of a thread are issued before any is used (no load inside a thread
+        // condition: a thread outside the node or the column block reads W[0] and keeps zero)
+        double2 ta[2], tb[2];
+        int am[2], ak[2], bk[2], bn[2];
+        bool aok[2], bok[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int e = tid + 256 * q;
             if (DOWN) {      // op(A) = W^*: element (row, kk) = conj(W(kk, row))
-                kk = e % 16;
-                mm = e / 16;
-                int gm = m0 + mm, gk = k0 + kk;
-                if (gm < m && gk < m) {
-                    double2 t = W[gk + (size_t)gm * m];
-                    v = zc(t.x, -t.y);
-                }
+                ak[q] = e % 16;
+                am[q] = e / 16;
             } else {
-                mm = e % 32;
-                kk = e / 32;
-                int gm = m0 + mm, gk = k0 + kk;
-                if (gm < m && gk < m) v = W[gm + (size_t)gk * m];
+                am[q] = e % 32;
+                ak[q] = e / 32;
             }
-            As[kk][mm] = v;
+            const int gm = m0 + am[q], gk = k0 + ak[q];
+            aok[q] = gm < m && gk < m;
+            ta[q] = W[aok[q] ? (DOWN ? gk + (size_t)gm * m : gm + (size_t)gk * m) : 0];
+            bk[q] = e % 16;
+            bn[q] = e / 16;
+            const int hk = k0 + bk[q], hn = n0 + bn[q];
+            bok[q] = hk < m && hn < nrhs;
+            const double2 *src;
+            if (DOWN)
+                src = !bok[q] ? W : (hk < k ? Bh + (yo + hk) + (size_t)hn * ldb : Ylo + (ro + hk - k) + (size_t)hn * ldlo);
+            else
+                src = !bok[q] ? W : Yin + (yo + hk) + (size_t)hn * ldin;
+            tb[q] = *src;
         }
-        for (int e = tid; e < 512; e += 256) {
-            int kk = e % 16, nn = e / 16;
-            int gk = k0 + kk, gn = n0 + nn;
-            double2 v = zc(0.0, 0.0);
-            if (gk < m && gn < nrhs) {
-                if (DOWN)
-                    v = gk < k ? Bh[(yo + gk) + (size_t)gn * ldb] : Ylo[(ro + gk - k) + (size_t)gn * ldlo];
-                else
-                    v = Yin[(yo + gk) + (size_t)gn * ldin];
-            }
-            Bs[kk][nn] = v;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const double2 t = DOWN ? zc(ta[q].x, -ta[q].y) : ta[q];
+            As[ak[q]][am[q]] = aok[q] ? t : zc(0.0, 0.0);
+            Bs[bk[q]][bn[q]] = bok[q] ? tb[q] : zc(0.0, 0.0);
         }
         __syncthreads();
 #pragma unroll
@@ -653,40 +657,37 @@ __global__ void __launch_bounds__(256) k_ulv_level64(LevelArgs a, const double2 
         bnn[r] = e / 16;
     }
     double2 pa[4], pb[4];
+    // The loads carry no branch: a thread outside the node or the column block reads W[0] (the
+    // node has m >= 1 rows), and the zeroing and the conjugation of the W^* operand happen when
+    // the tile is written to LDS.  With the load inside a thread condition and the conjugation
+    // next to it, the compiler waited for each load before issuing the next.
+    auto a_ok = [&](int k0, int r) { return amm[r] < m && k0 + akk[r] < m; };
+    auto b_ok = [&](int k0, int r) { return k0 + bkk[r] < m && n0 + bnn[r] < nrhs; };
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int gm = amm[r], gk = k0 + akk[r];
-            double2 v = zc(0.0, 0.0);
-            if (gm < m && gk < m) {
-                if (DOWN) {
-                    const double2 t = W[gk + (size_t)gm * m];
-                    v = zc(t.x, -t.y);
-                } else {
-                    v = W[gm + (size_t)gk * m];
-                }
-            }
-            pa[r] = v;
+            pa[r] = W[a_ok(k0, r) ? (DOWN ? gk + (size_t)gm * m : gm + (size_t)gk * m) : 0];
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int gk = k0 + bkk[r], gn = n0 + bnn[r];
-            double2 v = zc(0.0, 0.0);
-            if (gk < m && gn < nrhs) {
-                if (DOWN)
-                    v = gk < k ? Bh[(yo + gk) + (size_t)gn * ldb] : Ylo[(ro + gk - k) + (size_t)gn * ldlo];
-                else
-                    v = Yin[(yo + gk) + (size_t)gn * ldin];
-            }
-            pb[r] = v;
+            const double2 *src;
+            if (DOWN)
+                src = !b_ok(k0, r) ? W
+                                   : (gk < k ? Bh + (yo + gk) + (size_t)gn * ldb : Ylo + (ro + gk - k) + (size_t)gn * ldlo);
+            else
+                src = !b_ok(k0, r) ? W : Yin + (yo + gk) + (size_t)gn * ldin;
+            pb[r] = *src;
         }
     };
     fetch(0);
     for (int k0 = 0; k0 < m; k0 += 16) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            As[akk[r]][amm[r]] = pa[r];
-            Bs[bkk[r]][bnn[r]] = pb[r];
+            const double2 t = DOWN ? zc(pa[r].x, -pa[r].y) : pa[r];
+            As[akk[r]][amm[r]] = a_ok(k0, r) ? t : zc(0.0, 0.0);
+            Bs[bkk[r]][bnn[r]] = b_ok(k0, r) ? pb[r] : zc(0.0, 0.0);
         }
         __syncthreads();
         // the next tile is fetched while this one is used
